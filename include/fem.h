@@ -1,0 +1,197 @@
+/*
+ * fem.h -- C ABI of libfem: global stiffness and mass matrices of lowest-order
+ * edge elements (Nedelec curl-curl + mass, Raviart-Thomas div-div + mass) on
+ * 2D triangle and 3D tetrahedron meshes, assembled on an MI355X (gfx950) GPU.
+ *
+ * Method: Anjam & Valdman, "Fast MATLAB assembly of FEM matrices in 2D and 3D:
+ * Edge elements" (arXiv:1409.4618).
+ *   - mesh structures and global dof numbering: Section 3 (first two tables);
+ *   - orientation (sign) data: Section 2.3 and Section 3;
+ *   - Piola maps and reference bases: Sections 2.1 (RT) and 2.2 (Nedelec);
+ *   - local and global matrices: Section 2.4;
+ *   - assembly call sequence (affine maps, get_faces, signs, stiffness/mass):
+ *     Section 3.2.
+ *
+ * Conventions shared by every entry point
+ *   - All ids are 0-based (the paper is 1-based).
+ *   - "dev" pointers are device (HBM) pointers on the current HIP device; "host"
+ *     pointers are ordinary host memory. The caller owns every buffer it passes
+ *     in; the library never frees them. The library owns everything inside a
+ *     handle (topology, pattern, maps, scratch) and frees it in *_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
+ *     enqueued on it asynchronously unless the entry point says it synchronises.
+ *   - Every entry point returns a fem_status. On an error nothing is enqueued,
+ *     output buffers are left untouched, and fem_last_error() returns a message
+ *     (thread-local, valid until the next call on that thread). Faults detected
+ *     inside an asynchronous kernel (a zero Jacobian determinant, a non-finite
+ *     coordinate) set a per-handle device error word read by fem_status_query.
+ *   - Global dof numbering (the paper leaves the row order open): edge rows are
+ *     the sorted node pairs (lo, hi), face rows the sorted node triples
+ *     (a, b, c), both in lexicographic order.
+ *   - Sign data: Nedelec (2D and 3D) and 2D Raviart-Thomas use +1 for a local
+ *     edge whose start node has the larger global index (Section 3 states this
+ *     for 2D; the 3D local edges are 1->2, 1->3, 1->4, 2->3, 3->4, 4->2 of
+ *     Figure 1). 3D Raviart-Thomas uses minus the parity of the permutation
+ *     taking the local node order to (sorted face nodes, opposite node), which
+ *     equals the det-based rule of Section 2.3.
+ *   - The 3D Raviart-Thomas basis is the printed one, whose flux through its
+ *     face is 1/2 (Section 2.1).
+ *   - Coefficients: K(a) = sum_K a_K K^K and M(b) = sum_K b_K M^K with one value
+ *     per element; a NULL coefficient pointer means 1 (the paper's matrices).
+ *   - CSR: rowptr int64 [n_rows+1], colind int32 [nnz] ascending within a row,
+ *     full (not triangular) storage, every (dof_k, dof_l) pair of every element
+ *     present even when its value is zero. K and M share the pattern. Values are
+ *     bitwise symmetric and deterministic (no floating-point atomics).
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fem_mesh_s* fem_mesh;
+typedef struct fem_batch_s* fem_batch;
+
+typedef enum {
+    FEM_NEDELEC = 0,         /* H(curl): curl-curl stiffness + mass, dofs on edges        */
+    FEM_RAVIART_THOMAS = 1   /* H(div): div-div stiffness + mass, dofs on edges (2D) /
+                                faces (3D)                                                 */
+} fem_kind;
+
+typedef enum {
+    FEM_OK = 0,
+    FEM_EINVAL = 1,       /* bad argument: NULL pointer, dim not 2/3, kind/dim mismatch, ... */
+    FEM_ERANGE = 2,       /* an element references a node id outside [0, n_nodes)          */
+    FEM_EDEGENERATE = 3,  /* an element has det B_K == 0 (e.g. a repeated node)            */
+    FEM_ENONFINITE = 4,   /* a node coordinate or a Jacobian determinant is not finite     */
+    FEM_EOVERFLOW = 5,    /* a size exceeds an index limit (int32 ids, row length > 255)   */
+    FEM_ENOMEM = 6,       /* device allocation failed                                      */
+    FEM_EHIP = 7,         /* a HIP runtime call failed                                     */
+    FEM_ENOTREADY = 8     /* the pattern for this kind has not been built (fem_pattern)   */
+} fem_status;
+
+/* Topology: Section 3 (get_edges / get_faces / signs_edges / signs_faces).
+ *   nodes  dev f64 [n_nodes][dim]   node coordinates (nodes2coord), row-major
+ *   elems  dev i32 [n_elems][dim+1] element -> node ids (elems2nodes), row-major
+ *   dim    2 (triangles) or 3 (tetrahedra)
+ * Builds the global edge (and in 3D face) numbering, elems2edges / elems2faces
+ * and the sign data by a device radix sort + unique over node-index keys, and
+ * validates the mesh (node ids in range, finite coordinates, det B_K != 0).
+ * Synchronises `stream` (to learn the number of edges / faces).
+ * On success *out owns the topology; release it with fem_mesh_destroy.
+ * Limits: n_elems * (edges per element) < 2^31, n_nodes < 2^31.             */
+fem_status fem_topology(const double* nodes, int64_t n_nodes, int dim,
+                        const int32_t* elems, int64_t n_elems,
+                        void* stream, fem_mesh* out);
+
+/* Counts of a mesh (host outputs; any pointer may be NULL). n_faces is 0 in 2D. */
+fem_status fem_mesh_counts(fem_mesh mesh, int64_t* n_nodes, int64_t* n_elems,
+                           int64_t* n_edges, int64_t* n_faces, int* dim);
+
+/* Borrowed device pointers to the topology (valid until fem_mesh_destroy):
+ *   edges2nodes i32 [n_edges][2] (lo < hi), elems2edges i32 [n_elems][3|6],
+ *   signs_e i8 [n_elems][3|6], faces2nodes i32 [n_faces][3] (a < b < c),
+ *   elems2faces i32 [n_elems][4], signs_f i8 [n_elems][4] (3D only; NULL in 2D).
+ * Any output pointer may be NULL.                                            */
+fem_status fem_mesh_topology(fem_mesh mesh, const int32_t** edges2nodes,
+                             const int32_t** elems2edges, const int8_t** signs_e,
+                             const int32_t** faces2nodes, const int32_t** elems2faces,
+                             const int8_t** signs_f);
+
+/* One-time CSR sparsity pattern of `kind` and the per-element scatter map
+ * (the global step that the paper leaves out at the end of Section 3.2).
+ * Builds it on first use (synchronises `stream`), then returns borrowed device
+ * pointers: rowptr i64 [n_rows+1], colind i32 [nnz]. n_rows is the number of
+ * edges (Nedelec, 2D RT) or faces (3D RT). Outputs may be NULL.
+ * FEM_EOVERFLOW if a row has more than 255 entries or n_elems * n_local^2 >= 2^31. */
+fem_status fem_pattern(fem_mesh mesh, fem_kind kind, void* stream,
+                       int64_t* n_rows, int64_t* nnz,
+                       const int64_t** rowptr, const int32_t** colind);
+
+/* Numeric assembly (the hot path): values of K(a) and M(b) on the pattern of
+ * fem_pattern(kind), Section 2.4. Asynchronous on `stream`.
+ *   nodes  dev f64 [n_nodes][dim]  coordinates (may differ from fem_topology's;
+ *                                  the topology is reused)
+ *   a, b   dev f64 [n_elems] or NULL (= 1)
+ *   K_vals dev f64 [nnz] output (may be NULL to skip K); M_vals likewise
+ * Each value is written exactly once (no accumulation into the outputs).
+ * FEM_ENOTREADY if fem_pattern(kind) has not been called.                  */
+fem_status fem_assemble(fem_mesh mesh, fem_kind kind, const double* nodes,
+                        const double* a, const double* b,
+                        double* K_vals, double* M_vals, void* stream);
+
+/* Adjoint of fem_assemble for L = sum_p gK[p] K(a)[p] + gM[p] M(b)[p]
+ * (for L = u^T (K(a) + M(b)) u pass gK[p] = gM[p] = u_row(p) u_col(p)).
+ * Not part of the paper: the derivative of its local matrices (Section 2.4) with
+ * respect to the coefficients and the vertex coordinates. Asynchronous.
+ *   gK, gM  dev f64 [nnz] upstream weights (NULL = 0)
+ *   ga, gb  dev f64 [n_elems] outputs dL/da, dL/db (NULL to skip)
+ *   gnodes  dev f64 [n_nodes][dim] output dL/dnodes (NULL to skip); overwritten,
+ *           nodes in no element get 0.
+ * Uses library-owned scratch inside the handle (allocated on first use).    */
+fem_status fem_assemble_backward(fem_mesh mesh, fem_kind kind, const double* nodes,
+                                 const double* a, const double* b,
+                                 const double* gK, const double* gM,
+                                 double* ga, double* gb, double* gnodes, void* stream);
+
+/* Synchronises the last stream used with `mesh`, returns and clears the
+ * asynchronous device error word (FEM_OK, FEM_EDEGENERATE or FEM_ENONFINITE). */
+fem_status fem_status_query(fem_mesh mesh);
+
+void fem_mesh_destroy(fem_mesh mesh);
+
+/* ---------------------------------------------------------------------------
+ * Batched assembly: many meshes of uneven sizes (mixed dims and kinds) in ONE
+ * persistent kernel launch. Not in the paper (a launch-amortisation layer over
+ * the same per-element computation).
+ *   meshes  host array [n] of handles, each with fem_pattern(kinds[i]) built
+ *   kinds   host array [n]
+ * The batch borrows the meshes (they must outlive it).                     */
+fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n,
+                            fem_batch* out);
+
+/* Bind the per-mesh buffers (host arrays [n] of device pointers; a/b entries
+ * may be NULL = 1, K/M entries may be NULL to skip). Copies a small table to the
+ * device and synchronises. Rebinding is allowed between launches.           */
+fem_status fem_batch_bind(fem_batch batch, const double* const* nodes,
+                          const double* const* a, const double* const* b,
+                          double* const* K_vals, double* const* M_vals);
+
+/* Autotuner: times every candidate (rows per tile, schedule) with the bound
+ * buffers on `stream`, keeps the fastest, and records it in the JSON cache file
+ * `cache_path` (NULL = no file). If the file already holds an entry for this
+ * device and batch signature, that entry is used without timing. Synchronises. */
+fem_status fem_batch_tune(fem_batch batch, const char* cache_path, void* stream);
+
+/* Which configuration the batch uses (host outputs, may be NULL):
+ * rows per tile (64/128/256), schedule (0 static, 1 dynamic queue, 2 LPT-sorted
+ * dynamic queue), number of work items, persistent grid size.               */
+fem_status fem_batch_config(fem_batch batch, int* rows_per_tile, int* schedule,
+                            int64_t* n_work, int* grid);
+
+/* Select a configuration by hand (skips tuning).                            */
+fem_status fem_batch_set_config(fem_batch batch, int rows_per_tile, int schedule);
+
+/* One persistent launch over all bound meshes. Asynchronous; contains no
+ * memset or allocation, so it may be captured into a HIP graph.            */
+fem_status fem_batch_assemble(fem_batch batch, void* stream);
+
+/* Capture one fem_batch_assemble into a HIP graph held by the batch
+ * (re-captured after bind / set_config / tune), then replay it on `stream`.  */
+fem_status fem_batch_graph_launch(fem_batch batch, void* stream);
+
+void fem_batch_destroy(fem_batch batch);
+
+/* Message of the last error on this thread ("" if none). */
+const char* fem_last_error(void);
+
+/* Library version string. */
+const char* fem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_H */

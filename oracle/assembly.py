@@ -18,8 +18,9 @@ The 3D Nedelec stiffness formula is printed with s_k twice; s_k s_l is the
 reading (as in every other formula of that section).
 
 The integrals over the reference element are done with the conical-product
-Gauss-Legendre rule of ``reference.quadrature`` (degree 5 in 3D, 6 in 2D, for
-integrands of degree <= 2), so the local matrices are exact up to rounding.
+Gauss-Legendre rule of ``reference.quadrature`` with 3 points per direction
+(exact to degree 3 in 3D, 4 in 2D, for integrands of degree <= 2), so the local
+matrices are exact up to rounding.
 Global accumulation sums every local entry (k, l) of every element, in
 ascending element order, into the (dof_k, dof_l) position; entries that sum to
 zero stay in the pattern.
@@ -33,7 +34,7 @@ import numpy as np
 from . import reference as ref
 from .topology import Topology, build_topology
 
-CHUNK = 1 << 19
+CHUNK = 1 << 16
 
 
 def geometry(nodes: np.ndarray, elems: np.ndarray, dtype=np.float64):
@@ -65,7 +66,10 @@ def n_dofs(topo: Topology, kind: str) -> int:
     return topo.n_faces if (kind == "rt" and topo.dim == 3) else topo.n_edges
 
 
-def local_matrices_from_B(B: np.ndarray, kind: str, signs: np.ndarray, m: int = 4):
+QUAD_M = 3  # Gauss-Legendre points per direction: exact to degree 4 (2D) / 3 (3D)
+
+
+def local_matrices_from_B(B: np.ndarray, kind: str, signs: np.ndarray, m: int = QUAD_M):
     """Sign-adjusted local K, M (without coefficients) from B [T,d,d] -> ([T,n,n], [T,n,n])."""
     dim = B.shape[1]
     x, w = ref.quadrature(dim, m)
@@ -77,36 +81,37 @@ def local_matrices_from_B(B: np.ndarray, kind: str, signs: np.ndarray, m: int = 
     T = B.shape[0]
     Mloc = np.zeros((T, n, n), dtype=B.dtype)
     Kloc = np.zeros((T, n, n), dtype=B.dtype)
+    # Piola-mapped values at each quadrature point: columns of [T, d, n]
     if kind == "rt":
-        for q in range(len(w)):
-            v = np.einsum("tij,kj->tki", B, vals[q])     # B eta_k(x_q)
-            Mloc += w[q] * np.einsum("tki,tli->tkl", v, v)
+        P = B                                            # x -> B x
+    else:
+        P = np.swapaxes(np.linalg.inv(B), 1, 2)          # x -> B^-T x
+    for q in range(len(w)):
+        v = P @ vals[q].T                                # [T, d, n]
+        Mloc += w[q] * (np.swapaxes(v, 1, 2) @ v)        # (mapped eta_k) . (mapped eta_l)
+    if kind == "rt":
         Mloc /= aJ[:, None, None]
-        dv = ref.div_basis(kind, dim)                    # constants
+        dv = ref.div_basis(kind, dim)                    # constant divergences
         for q in range(len(w)):
-            Kloc += w[q] * np.broadcast_to(np.outer(dv, dv), (T, n, n))
+            Kloc += w[q] * np.outer(dv, dv)[None]
         Kloc = Kloc / aJ[:, None, None]
     else:
-        Binv = np.linalg.inv(B)
-        for q in range(len(w)):
-            v = np.einsum("tji,kj->tki", Binv, vals[q])  # B^-T eta_k(x_q)
-            Mloc += w[q] * np.einsum("tki,tli->tkl", v, v)
         Mloc *= aJ[:, None, None]
         c = ref.curl_basis(kind, dim)
         if dim == 2:
             for q in range(len(w)):
-                Kloc += w[q] * np.broadcast_to(np.outer(c, c), (T, n, n))
+                Kloc += w[q] * np.outer(c, c)[None]
         else:
-            bc = np.einsum("tij,kj->tki", B, c)          # B curl eta_k
+            bc = B @ c.T                                 # [T, 3, n]: B curl eta_k
             for q in range(len(w)):
-                Kloc += w[q] * np.einsum("tki,tli->tkl", bc, bc)
+                Kloc += w[q] * (np.swapaxes(bc, 1, 2) @ bc)
         Kloc = Kloc / aJ[:, None, None]
     ss = S[:, :, None] * S[:, None, :]
     return Kloc * ss, Mloc * ss
 
 
 def local_matrices(nodes: np.ndarray, elems: np.ndarray, kind: str, signs: np.ndarray,
-                   m: int = 4):
+                   m: int = QUAD_M):
     """Local K, M for all elements (chunked over elements; each element independent)."""
     T = elems.shape[0]
     dim = elems.shape[1] - 1

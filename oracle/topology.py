@@ -53,24 +53,42 @@ class Topology:
         return 0 if self.faces2nodes is None else self.faces2nodes.shape[0]
 
 
+def _unique_rows_lex(cols):
+    """Unique rows of the integer columns ``cols`` (each [n], values < 2^31) in
+    lexicographic order, and for every input row the index of its unique row.
+    A lexicographic sort followed by "keep the first of each run"."""
+    order = np.lexsort(tuple(reversed(cols)))           # primary key = cols[0]
+    srt = [c[order] for c in cols]
+    head = np.ones(order.size, dtype=bool)
+    if order.size > 1:
+        diff = np.zeros(order.size - 1, dtype=bool)
+        for c in srt:
+            diff |= c[1:] != c[:-1]
+        head[1:] = diff
+    rank = np.cumsum(head) - 1
+    inv = np.empty(order.size, dtype=np.int64)
+    inv[order] = rank
+    uniq = np.stack([c[head] for c in srt], axis=1)
+    return uniq, inv
+
+
 def get_edges(elems: np.ndarray):
     """Unique edges (lexicographic rows of sorted node pairs) and the element->edge map."""
     dim = elems.shape[1] - 1
     e = np.asarray(elems, dtype=np.int64)
-    pairs = np.stack([np.stack([e[:, s], e[:, t]], axis=1) for s, t in LOCAL_EDGES[dim]], axis=1)
-    pairs = np.sort(pairs, axis=2)                       # (lo, hi) per local edge
-    flat = pairs.reshape(-1, 2)
-    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
-    return uniq, inv.reshape(e.shape[0], len(LOCAL_EDGES[dim]))
+    ne = len(LOCAL_EDGES[dim])
+    s = np.stack([e[:, a] for a, _ in LOCAL_EDGES[dim]], axis=1).reshape(-1)
+    t = np.stack([e[:, b] for _, b in LOCAL_EDGES[dim]], axis=1).reshape(-1)
+    lo, hi = np.minimum(s, t), np.maximum(s, t)           # (lo, hi) per local edge
+    uniq, inv = _unique_rows_lex([lo, hi])
+    return uniq, inv.reshape(e.shape[0], ne)
 
 
 def get_faces(elems: np.ndarray):
     """Unique faces (lexicographic rows of sorted node triples) and the element->face map."""
     e = np.asarray(elems, dtype=np.int64)
-    tri = np.stack([e[:, list(f)] for f in LOCAL_FACES], axis=1)
-    tri = np.sort(tri, axis=2)
-    flat = tri.reshape(-1, 3)
-    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
+    tri = np.sort(np.stack([e[:, list(f)] for f in LOCAL_FACES], axis=1), axis=2).reshape(-1, 3)
+    uniq, inv = _unique_rows_lex([tri[:, 0], tri[:, 1], tri[:, 2]])
     return uniq, inv.reshape(e.shape[0], 4)
 
 

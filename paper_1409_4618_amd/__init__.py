@@ -1,0 +1,292 @@
+"""Python binding of libfem: lowest-order edge-element assembly on MI355X.
+
+Every step runs in the HIP kernels of ``libfem.so`` (C ABI in include/fem.h);
+this module only marshals arguments. PyTorch provides device memory, the
+current HIP stream and the autograd hook.
+
+    import paper_1409_4618_amd as fem
+    mesh = fem.Mesh(nodes, elems)              # topology on the GPU
+    K, M = fem.assemble(mesh, "ned", nodes, a, b)
+    rowptr, colind = mesh.pattern("ned")
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+from ._lib import (FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
+
+__all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "FemAssemble", "FemError",
+           "kind_code", "NED", "RT"]
+
+NED = "ned"
+RT = "rt"
+
+
+def kind_code(kind) -> int:
+    if kind in (NED, "nedelec", FEM_NEDELEC):
+        return FEM_NEDELEC
+    if kind in (RT, "raviart-thomas", FEM_RAVIART_THOMAS):
+        return FEM_RAVIART_THOMAS
+    raise ValueError(f"unknown kind {kind!r}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _check_dev(t, dtype, name, shape=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _copy_from_device(ptr: int, n: int, dtype):
+    """Copy a borrowed library buffer into a new torch tensor (same device)."""
+    torch = _torch()
+    out = torch.empty(n, dtype=dtype, device="cuda")
+    if n:
+        nbytes = n * out.element_size()
+        check(0 if hip().hipMemcpyAsync(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr),
+                                        nbytes, 3, _stream_ptr()) == 0 else 7, "hipMemcpyAsync")
+    return out
+
+
+class Mesh:
+    """Topology handle (fem_topology): global edge / face numbering and sign data."""
+
+    def __init__(self, nodes, elems):
+        torch = _torch()
+        if elems.dim() != 2 or elems.shape[1] not in (3, 4):
+            raise ValueError("elems must be [T, 3] or [T, 4]")
+        self.dim = int(elems.shape[1]) - 1
+        _check_dev(nodes, torch.float64, "nodes")
+        _check_dev(elems, torch.int32, "elems")
+        if nodes.dim() != 2 or nodes.shape[1] != self.dim:
+            raise ValueError(f"nodes must be [V, {self.dim}]")
+        self._h = ctypes.c_void_p(0)
+        L = lib()
+        check(L.fem_topology(_ptr(nodes), nodes.shape[0], self.dim, _ptr(elems), elems.shape[0],
+                             _stream_ptr(), ctypes.byref(self._h)), "fem_topology")
+        V = ctypes.c_int64()
+        T = ctypes.c_int64()
+        E = ctypes.c_int64()
+        F = ctypes.c_int64()
+        d = ctypes.c_int()
+        check(L.fem_mesh_counts(self._h, ctypes.byref(V), ctypes.byref(T), ctypes.byref(E),
+                                ctypes.byref(F), ctypes.byref(d)), "fem_mesh_counts")
+        self.n_nodes, self.n_elems, self.n_edges, self.n_faces = V.value, T.value, E.value, F.value
+        self._patterns = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().fem_mesh_destroy(h)
+                h.value = None
+            except Exception:
+                pass
+
+    def topology(self):
+        """Copies of the topology arrays as device tensors (dict)."""
+        torch = _torch()
+        ptrs = [ctypes.c_void_p() for _ in range(6)]
+        check(lib().fem_mesh_topology(self._h, *[ctypes.byref(p) for p in ptrs]), "fem_mesh_topology")
+        ne = 6 if self.dim == 3 else 3
+        out = {
+            "edges2nodes": _copy_from_device(ptrs[0].value, 2 * self.n_edges, torch.int32).view(-1, 2),
+            "elems2edges": _copy_from_device(ptrs[1].value, ne * self.n_elems, torch.int32).view(-1, ne),
+            "signs_e": _copy_from_device(ptrs[2].value, ne * self.n_elems, torch.int8).view(-1, ne),
+        }
+        if self.dim == 3:
+            out["faces2nodes"] = _copy_from_device(ptrs[3].value, 3 * self.n_faces, torch.int32).view(-1, 3)
+            out["elems2faces"] = _copy_from_device(ptrs[4].value, 4 * self.n_elems, torch.int32).view(-1, 4)
+            out["signs_f"] = _copy_from_device(ptrs[5].value, 4 * self.n_elems, torch.int8).view(-1, 4)
+        return out
+
+    def pattern_info(self, kind):
+        """(n_rows, nnz) of the CSR pattern of ``kind`` (built on first use)."""
+        kc = kind_code(kind)
+        if kc not in self._patterns:
+            n = ctypes.c_int64()
+            nnz = ctypes.c_int64()
+            rp = ctypes.c_void_p()
+            ci = ctypes.c_void_p()
+            check(lib().fem_pattern(self._h, kc, _stream_ptr(), ctypes.byref(n), ctypes.byref(nnz),
+                                    ctypes.byref(rp), ctypes.byref(ci)), "fem_pattern")
+            self._patterns[kc] = (n.value, nnz.value, rp.value, ci.value)
+        return self._patterns[kc][:2]
+
+    def pattern(self, kind):
+        """Copies of (rowptr int64 [n_rows+1], colind int32 [nnz]) as device tensors."""
+        torch = _torch()
+        self.pattern_info(kind)
+        n, nnz, rp, ci = self._patterns[kind_code(kind)]
+        return (_copy_from_device(rp, n + 1, torch.int64), _copy_from_device(ci, nnz, torch.int32))
+
+    def status(self):
+        """Synchronise and raise if an asynchronous kernel flagged an error."""
+        check(lib().fem_status_query(self._h), "fem_status_query")
+
+
+def assemble_into(mesh: Mesh, kind, nodes, a, b, K, M):
+    """fem_assemble into caller-provided outputs (no allocation)."""
+    check(lib().fem_assemble(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b), _ptr(K),
+                             _ptr(M), _stream_ptr()), "fem_assemble")
+
+
+def assemble(mesh: Mesh, kind, nodes, a=None, b=None):
+    """Values (K, M) of K(a), M(b) on ``mesh.pattern(kind)``: f64 device tensors [nnz]."""
+    torch = _torch()
+    _, nnz = mesh.pattern_info(kind)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(a, torch.float64, "a", (mesh.n_elems,))
+    _check_dev(b, torch.float64, "b", (mesh.n_elems,))
+    K = torch.empty(nnz, dtype=torch.float64, device=nodes.device)
+    M = torch.empty(nnz, dtype=torch.float64, device=nodes.device)
+    assemble_into(mesh, kind, nodes, a, b, K, M)
+    return K, M
+
+
+def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b=True,
+                      need_nodes=True):
+    """Adjoint: (dL/dnodes, dL/da, dL/db) for L = gK . K(a) + gM . M(b)."""
+    torch = _torch()
+    _, nnz = mesh.pattern_info(kind)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(gK, torch.float64, "gK", (nnz,))
+    _check_dev(gM, torch.float64, "gM", (nnz,))
+    dev = nodes.device
+    ga = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_a else None
+    gb = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_b else None
+    gn = torch.empty_like(nodes) if need_nodes else None
+    check(lib().fem_assemble_backward(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b),
+                                      _ptr(gK), _ptr(gM), _ptr(ga), _ptr(gb), _ptr(gn),
+                                      _stream_ptr()), "fem_assemble_backward")
+    return gn, ga, gb
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class FemAssemble(torch.autograd.Function):
+        """(nodes, a, b) -> (K values, M values) with the hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, nodes, a, b, mesh, kind):
+            K, M = assemble(mesh, kind, nodes, a, b)
+            ctx.mesh = mesh
+            ctx.kind = kind
+            ctx.save_for_backward(nodes, a, b)
+            return K, M
+
+        @staticmethod
+        def backward(ctx, gK, gM):
+            nodes, a, b = ctx.saved_tensors
+            _, nnz = ctx.mesh.pattern_info(ctx.kind)
+            z = None
+            if gK is None or gM is None:
+                z = torch.zeros(nnz, dtype=torch.float64, device=nodes.device)
+            gK = z if gK is None else gK.contiguous()
+            gM = z if gM is None else gM.contiguous()
+            gn, ga, gb = assemble_backward(ctx.mesh, ctx.kind, nodes, a, b, gK, gM,
+                                           need_a=ctx.needs_input_grad[1],
+                                           need_b=ctx.needs_input_grad[2],
+                                           need_nodes=ctx.needs_input_grad[0])
+            return gn, ga, gb, None, None
+
+    return FemAssemble
+
+
+_FA = None
+
+
+def FemAssemble():
+    global _FA
+    if _FA is None:
+        _FA = _autograd_function()
+    return _FA
+
+
+def assemble_autograd(mesh: Mesh, kind, nodes, a, b):
+    """Differentiable (K, M) values with respect to nodes, a and b."""
+    return FemAssemble().apply(nodes, a, b, mesh, kind)
+
+
+class Batch:
+    """Many meshes in one persistent launch (fem_batch_*)."""
+
+    def __init__(self, meshes: Sequence[Mesh], kinds: Sequence):
+        self.meshes = list(meshes)
+        self.kinds = [kind_code(k) for k in kinds]
+        for m, k in zip(self.meshes, self.kinds):
+            m.pattern_info(k)
+        n = len(self.meshes)
+        handles = (ctypes.c_void_p * n)(*[m.handle.value for m in self.meshes])
+        kinds_arr = (ctypes.c_int * n)(*self.kinds)
+        self._h = ctypes.c_void_p(0)
+        check(lib().fem_batch_create(handles, kinds_arr, n, ctypes.byref(self._h)), "fem_batch_create")
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().fem_batch_destroy(h)
+                h.value = None
+            except Exception:
+                pass
+
+    def bind(self, nodes, a, b, K, M):
+        n = len(self.meshes)
+
+        def arr(ts):
+            return (ctypes.c_void_p * n)(*[(0 if t is None else t.data_ptr()) for t in ts])
+
+        self._keep = (list(nodes), list(a), list(b), list(K), list(M))
+        check(lib().fem_batch_bind(self._h, arr(nodes), arr(a), arr(b), arr(K), arr(M)), "fem_batch_bind")
+
+    def tune(self, cache_path: Optional[str] = None):
+        p = None if cache_path is None else cache_path.encode()
+        check(lib().fem_batch_tune(self._h, p, _stream_ptr()), "fem_batch_tune")
+
+    def set_config(self, rows_per_tile: int, schedule: int):
+        check(lib().fem_batch_set_config(self._h, rows_per_tile, schedule), "fem_batch_set_config")
+
+    def config(self):
+        R = ctypes.c_int()
+        s = ctypes.c_int()
+        nw = ctypes.c_int64()
+        g = ctypes.c_int()
+        check(lib().fem_batch_config(self._h, ctypes.byref(R), ctypes.byref(s), ctypes.byref(nw),
+                                     ctypes.byref(g)), "fem_batch_config")
+        return {"rows_per_tile": R.value, "schedule": s.value, "n_work": nw.value, "grid": g.value}
+
+    def assemble(self):
+        check(lib().fem_batch_assemble(self._h, _stream_ptr()), "fem_batch_assemble")
+
+    def graph_launch(self):
+        check(lib().fem_batch_graph_launch(self._h, _stream_ptr()), "fem_batch_graph_launch")

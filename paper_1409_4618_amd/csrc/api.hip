@@ -1,0 +1,537 @@
+// C ABI of libfem (declared in include/fem.h): argument checking, handle
+// lifetime, the batched launch with its autotuner and HIP-graph replay.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fem_internal.h"
+
+namespace fem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+fem_status fail(fem_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+fem_status hip_fail(hipError_t e, const char* what) {
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    set_error(msg);
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FEM_ENOMEM : FEM_EHIP;
+}
+
+hipError_t dmalloc(fem_mesh m, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) m->allocs.push_back(*p);
+    return e;
+}
+
+static DofSet& dofset(fem_mesh m, fem_kind kind) {
+    return (m->dim == 3 && kind == FEM_RAVIART_THOMAS) ? m->faces : m->edges;
+}
+
+static int env_rows_per_tile(int kc) {
+    const char* v = std::getenv("FEM_ROWS_PER_TILE");
+    if (v) {
+        const int r = std::atoi(v);
+        if (r == 64 || r == 128 || r == 256) return r;
+    }
+    return default_rows_per_tile(kc);
+}
+
+}  // namespace fem
+
+using namespace fem;
+
+extern "C" {
+
+const char* fem_last_error(void) { return g_last_error.c_str(); }
+
+const char* fem_version(void) { return "libfem 1.0 (gfx950, fp64)"; }
+
+void fem_mesh_destroy(fem_mesh m) {
+    if (!m) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : m->allocs) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+    delete m;
+}
+
+fem_status fem_topology(const double* nodes, int64_t n_nodes, int dim, const int32_t* elems,
+                        int64_t n_elems, void* stream, fem_mesh* out) {
+    g_last_error.clear();
+    if (!out) return fail(FEM_EINVAL, "fem_topology: out is NULL");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(FEM_EINVAL, "fem_topology: dim must be 2 or 3");
+    if (n_nodes <= 0 || n_elems <= 0) return fail(FEM_EINVAL, "fem_topology: empty mesh");
+    if (!nodes || !elems) return fail(FEM_EINVAL, "fem_topology: nodes or elems is NULL");
+    const int ne = dim == 3 ? 6 : 3;
+    if (n_nodes >= (int64_t(1) << 31) || n_elems * ne >= (int64_t(1) << 31) ||
+        n_elems * (dim + 1) >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_topology: mesh exceeds the int32 index limits");
+    fem_mesh m = new fem_mesh_s();
+    (void)hipGetDevice(&m->device);
+    m->dim = dim;
+    m->V = n_nodes;
+    m->T = n_elems;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    fem_status st = build_topology(m, nodes, elems, s);
+    if (st != FEM_OK) {
+        std::string msg = g_last_error;
+        fem_mesh_destroy(m);
+        g_last_error = msg;
+        return st;
+    }
+    *out = m;
+    return FEM_OK;
+}
+
+fem_status fem_mesh_counts(fem_mesh m, int64_t* n_nodes, int64_t* n_elems, int64_t* n_edges,
+                           int64_t* n_faces, int* dim) {
+    if (!m) return fail(FEM_EINVAL, "fem_mesh_counts: mesh is NULL");
+    if (n_nodes) *n_nodes = m->V;
+    if (n_elems) *n_elems = m->T;
+    if (n_edges) *n_edges = m->edges.n;
+    if (n_faces) *n_faces = m->dim == 3 ? m->faces.n : 0;
+    if (dim) *dim = m->dim;
+    return FEM_OK;
+}
+
+fem_status fem_mesh_topology(fem_mesh m, const int32_t** edges2nodes, const int32_t** elems2edges,
+                             const int8_t** signs_e, const int32_t** faces2nodes,
+                             const int32_t** elems2faces, const int8_t** signs_f) {
+    if (!m) return fail(FEM_EINVAL, "fem_mesh_topology: mesh is NULL");
+    if (edges2nodes) *edges2nodes = m->edges2nodes;
+    if (elems2edges) *elems2edges = m->edges.elems2dofs;
+    if (signs_e) *signs_e = m->signs_e;
+    if (faces2nodes) *faces2nodes = m->dim == 3 ? m->faces2nodes : nullptr;
+    if (elems2faces) *elems2faces = m->dim == 3 ? m->faces.elems2dofs : nullptr;
+    if (signs_f) *signs_f = m->dim == 3 ? m->signs_f : nullptr;
+    return FEM_OK;
+}
+
+fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows, int64_t* nnz,
+                       const int64_t** rowptr, const int32_t** colind) {
+    g_last_error.clear();
+    if (!m) return fail(FEM_EINVAL, "fem_pattern: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS) return fail(FEM_EINVAL, "fem_pattern: bad kind");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    DofSet& ds = dofset(m, kind);
+    if (fem_status st = build_pattern(m, ds, s)) return st;
+    if (n_rows) *n_rows = ds.pat.n_rows;
+    if (nnz) *nnz = ds.pat.nnz;
+    if (rowptr) *rowptr = ds.pat.rowptr;
+    if (colind) *colind = ds.pat.colind;
+    return FEM_OK;
+}
+
+static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
+                               const double* b, double* K, double* M, int R, MeshDev* md) {
+    DofSet& ds = dofset(m, kind);
+    if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+    md->elems = m->elems;
+    md->nodes = nodes;
+    md->a = a;
+    md->b = b;
+    md->K = K;
+    md->M = M;
+    md->rowptr = ds.pat.rowptr;
+    md->rs_ptr = ds.rs_ptr;
+    md->rs_slot = ds.rs_slot;
+    md->colpos = ds.pat.colpos;
+    md->n_rows = ds.pat.n_rows;
+    md->n_tiles = (ds.pat.n_rows + R - 1) / R;
+    md->kind_code = kind_code(m->dim, kind);
+    md->pad = 0;
+    md->err_word = m->err_word;
+    return FEM_OK;
+}
+
+fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
+                        const double* b, double* K_vals, double* M_vals, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_assemble: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS) return fail(FEM_EINVAL, "fem_assemble: bad kind");
+    if (!nodes) return fail(FEM_EINVAL, "fem_assemble: nodes is NULL");
+    if (!K_vals && !M_vals) return FEM_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    const int kc = kind_code(m->dim, kind);
+    const int R = env_rows_per_tile(kc);
+    MeshDev md;
+    if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md)) return st;
+    const int pmax = dofset(m, kind).pat.tile_pmax[rows_index(R)];
+    return launch_forward(md, R, pmax, s);
+}
+
+fem_status fem_assemble_backward(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
+                                 const double* b, const double* gK, const double* gM, double* ga,
+                                 double* gb, double* gnodes, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_assemble_backward: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS)
+        return fail(FEM_EINVAL, "fem_assemble_backward: bad kind");
+    if (!nodes) return fail(FEM_EINVAL, "fem_assemble_backward: nodes is NULL");
+    DofSet& ds = dofset(m, kind);
+    if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+    if (!ga && !gb && !gnodes) return FEM_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    return launch_backward(m, ds, kind, nodes, a, b, gK, gM, ga, gb, gnodes, s);
+}
+
+fem_status fem_status_query(fem_mesh m) {
+    if (!m) return fail(FEM_EINVAL, "fem_status_query: mesh is NULL");
+    int err = 0;
+    FEM_HIP(hipStreamSynchronize(m->last_stream));
+    FEM_HIP(hipMemcpy(&err, m->err_word, sizeof(int), hipMemcpyDeviceToHost));
+    FEM_HIP(hipMemset(m->err_word, 0, sizeof(int)));
+    if (err & ERR_NONFINITE) return fail(FEM_ENONFINITE, "a Jacobian determinant was not finite");
+    if (err & ERR_DEGENERATE) return fail(FEM_EDEGENERATE, "an element had a zero or non-finite Jacobian determinant");
+    return FEM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batched assembly
+// ===========================================================================
+struct fem_batch_s {
+    int device = 0;
+    std::vector<fem_mesh> meshes;
+    std::vector<fem_kind> kinds;
+    std::vector<MeshDev> host_table;
+    bool bound = false;
+    MeshDev* table_dev = nullptr;
+    int2* work_dev = nullptr;
+    int64_t work_cap = 0;
+    int64_t n_work = 0;
+    unsigned* counters = nullptr;
+    int R = 128;
+    int schedule = 1;
+    int grid = 0;
+    int pmax = 0;
+    bool work_valid = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_valid = false;
+};
+
+namespace fem {
+
+static void drop_graph(fem_batch B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_valid = false;
+}
+
+static fem_status build_work(fem_batch B) {
+    const int R = B->R;
+    std::vector<int2> work;
+    std::vector<double> cost;
+    B->pmax = 0;
+    for (size_t i = 0; i < B->meshes.size(); ++i) {
+        fem_mesh m = B->meshes[i];
+        DofSet& ds = dofset(m, B->kinds[i]);
+        const int64_t nt = (ds.pat.n_rows + R - 1) / R;
+        B->pmax = std::max(B->pmax, ds.pat.tile_pmax[rows_index(R)]);
+        const double per_row = ds.pat.n_rows ? (double)ds.pat.nnz / (double)ds.pat.n_rows : 0.0;
+        for (int64_t t = 0; t < nt; ++t) {
+            work.push_back(make_int2((int)i, (int)t));
+            const int64_t rows = std::min<int64_t>(R, ds.pat.n_rows - t * R);
+            cost.push_back(per_row * (double)rows * ds.nloc);
+        }
+    }
+    if (B->schedule == 2) {
+        std::vector<size_t> idx(work.size());
+        for (size_t q = 0; q < idx.size(); ++q) idx[q] = q;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+        std::vector<int2> w2(work.size());
+        for (size_t q = 0; q < idx.size(); ++q) w2[q] = work[idx[q]];
+        work.swap(w2);
+    }
+    B->n_work = (int64_t)work.size();
+    if (B->n_work > B->work_cap) {
+        if (B->work_dev) FEM_HIP(hipFree(B->work_dev));
+        B->work_dev = nullptr;
+        FEM_HIP(hipMalloc((void**)&B->work_dev, std::max<int64_t>(1, B->n_work) * sizeof(int2)));
+        B->work_cap = B->n_work;
+    }
+    if (B->n_work)
+        FEM_HIP(hipMemcpy(B->work_dev, work.data(), B->n_work * sizeof(int2), hipMemcpyHostToDevice));
+    // persistent grid: as many workgroups as can be resident
+    int per_cu = 1;
+    const int bytes = B->pmax * 16;
+    if (bytes > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_batch: a row tile needs more LDS than the device has");
+    per_cu = batch_blocks_per_cu(R, bytes);
+    B->grid = (int)std::min<int64_t>((int64_t)cu_count() * per_cu, std::max<int64_t>(1, B->n_work));
+    // rebuild the device table with the tile count for this R
+    for (size_t i = 0; i < B->host_table.size(); ++i) {
+        MeshDev& md = B->host_table[i];
+        md.n_tiles = (md.n_rows + R - 1) / R;
+    }
+    if (B->bound)
+        FEM_HIP(hipMemcpy(B->table_dev, B->host_table.data(), B->host_table.size() * sizeof(MeshDev),
+                          hipMemcpyHostToDevice));
+    B->work_valid = true;
+    drop_graph(B);
+    return FEM_OK;
+}
+
+static std::string batch_signature(fem_batch B) {
+    std::ostringstream os;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < B->meshes.size(); ++i) {
+        const uint64_t v[3] = {(uint64_t)B->meshes[i]->T, (uint64_t)B->meshes[i]->dim, (uint64_t)B->kinds[i]};
+        for (uint64_t x : v) {
+            h ^= x;
+            h *= 1099511628211ull;
+        }
+    }
+    os << B->meshes.size() << "-" << std::hex << h;
+    return os.str();
+}
+
+static std::string device_name() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string n = p.gcnArchName;
+    for (char& c : n)
+        if (c == '"' || c == '\n') c = '_';
+    return n + "-cu" + std::to_string(p.multiProcessorCount);
+}
+
+// Cache file: one JSON object per line,
+// {"device": "...", "signature": "...", "rows_per_tile": R, "schedule": S, "ms": t}
+static bool cache_lookup(const char* path, const std::string& dev, const std::string& sig, int* R,
+                         int* sched) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        if (line.find("\"device\": \"" + dev + "\"") == std::string::npos) continue;
+        if (line.find("\"signature\": \"" + sig + "\"") == std::string::npos) continue;
+        const size_t pr = line.find("\"rows_per_tile\": ");
+        const size_t ps = line.find("\"schedule\": ");
+        if (pr == std::string::npos || ps == std::string::npos) continue;
+        const int r = std::atoi(line.c_str() + pr + 17);
+        const int sc = std::atoi(line.c_str() + ps + 12);
+        if ((r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2) {
+            *R = r;
+            *sched = sc;
+            found = true;  // last matching line wins
+        }
+    }
+    return found;
+}
+
+static void cache_store(const char* path, const std::string& dev, const std::string& sig, int R,
+                        int sched, double ms) {
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "{\"device\": \"%s\", \"signature\": \"%s\", \"rows_per_tile\": %d, \"schedule\": %d, \"ms\": %.6f}\n",
+                  dev.c_str(), sig.c_str(), R, sched, ms);
+    f << buf;
+}
+
+}  // namespace fem
+
+extern "C" {
+
+fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n, fem_batch* out) {
+    g_last_error.clear();
+    if (!out) return fail(FEM_EINVAL, "fem_batch_create: out is NULL");
+    *out = nullptr;
+    if (n <= 0 || !meshes || !kinds) return fail(FEM_EINVAL, "fem_batch_create: empty batch");
+    fem_batch B = new fem_batch_s();
+    (void)hipGetDevice(&B->device);
+    for (int i = 0; i < n; ++i) {
+        if (!meshes[i] || (kinds[i] != FEM_NEDELEC && kinds[i] != FEM_RAVIART_THOMAS)) {
+            delete B;
+            return fail(FEM_EINVAL, "fem_batch_create: NULL mesh or bad kind");
+        }
+        if (!dofset(meshes[i], kinds[i]).pat.built) {
+            delete B;
+            return fail(FEM_ENOTREADY, "fem_batch_create: pattern not built for a mesh");
+        }
+        B->meshes.push_back(meshes[i]);
+        B->kinds.push_back(kinds[i]);
+    }
+    B->host_table.resize(n);
+    hipError_t e = hipMalloc((void**)&B->table_dev, n * sizeof(MeshDev));
+    if (e == hipSuccess) e = hipMalloc((void**)&B->counters, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(B->counters, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fem_status st = hip_fail(e, "fem_batch_create");
+        fem_batch_destroy(B);
+        return st;
+    }
+    B->R = 128;
+    B->schedule = 1;
+    *out = B;
+    return FEM_OK;
+}
+
+fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double* const* a,
+                          const double* const* b, double* const* K_vals, double* const* M_vals) {
+    if (!B || !nodes) return fail(FEM_EINVAL, "fem_batch_bind: NULL argument");
+    for (size_t i = 0; i < B->meshes.size(); ++i) {
+        if (!nodes[i]) return fail(FEM_EINVAL, "fem_batch_bind: nodes[i] is NULL");
+        MeshDev md;
+        fem_status st = fill_meshdev(B->meshes[i], B->kinds[i], nodes[i], a ? a[i] : nullptr,
+                                     b ? b[i] : nullptr, K_vals ? K_vals[i] : nullptr,
+                                     M_vals ? M_vals[i] : nullptr, B->R, &md);
+        if (st) return st;
+        B->host_table[i] = md;
+    }
+    FEM_HIP(hipMemcpy(B->table_dev, B->host_table.data(), B->host_table.size() * sizeof(MeshDev),
+                      hipMemcpyHostToDevice));
+    B->bound = true;
+    drop_graph(B);
+    if (!B->work_valid) return build_work(B);
+    return FEM_OK;
+}
+
+fem_status fem_batch_set_config(fem_batch B, int R, int schedule) {
+    if (!B) return fail(FEM_EINVAL, "fem_batch_set_config: batch is NULL");
+    if ((R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > 2)
+        return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 64/128/256, schedule 0..2");
+    B->R = R;
+    B->schedule = schedule;
+    return build_work(B);
+}
+
+fem_status fem_batch_config(fem_batch B, int* R, int* schedule, int64_t* n_work, int* grid) {
+    if (!B) return fail(FEM_EINVAL, "fem_batch_config: batch is NULL");
+    if (R) *R = B->R;
+    if (schedule) *schedule = B->schedule;
+    if (n_work) *n_work = B->n_work;
+    if (grid) *grid = B->grid;
+    return FEM_OK;
+}
+
+fem_status fem_batch_assemble(fem_batch B, void* stream) {
+    if (!B) return fail(FEM_EINVAL, "fem_batch_assemble: batch is NULL");
+    if (!B->bound) return fail(FEM_ENOTREADY, "fem_batch_assemble: call fem_batch_bind first");
+    if (!B->work_valid)
+        if (fem_status st = build_work(B)) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return launch_batch(B->table_dev, B->work_dev, B->n_work, B->R, B->schedule, B->grid, B->pmax,
+                        B->counters, s);
+}
+
+fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
+    if (!B) return fail(FEM_EINVAL, "fem_batch_tune: batch is NULL");
+    if (!B->bound) return fail(FEM_ENOTREADY, "fem_batch_tune: call fem_batch_bind first");
+    const std::string dev = device_name();
+    const std::string sig = batch_signature(B);
+    int R = 0, sc = 0;
+    if (cache_lookup(cache_path, dev, sig, &R, &sc)) return fem_batch_set_config(B, R, sc);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    FEM_HIP(hipEventCreate(&e0));
+    FEM_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    int bestR = 128, bestS = 1;
+    const int Rs[3] = {64, 128, 256};
+    for (int ri = 0; ri < 3; ++ri) {
+        for (int sched = 0; sched < 3; ++sched) {
+            B->R = Rs[ri];
+            B->schedule = sched;
+            if (build_work(B) != FEM_OK) continue;  // e.g. tile too large for LDS
+            bool ok = true;
+            for (int w = 0; w < 2 && ok; ++w) ok = fem_batch_assemble(B, stream) == FEM_OK;
+            if (!ok) continue;
+            FEM_HIP(hipEventRecord(e0, s));
+            const int reps = 5;
+            for (int w = 0; w < reps && ok; ++w) ok = fem_batch_assemble(B, stream) == FEM_OK;
+            FEM_HIP(hipEventRecord(e1, s));
+            FEM_HIP(hipEventSynchronize(e1));
+            if (!ok) continue;
+            float ms = 0.f;
+            FEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double t = ms / reps;
+            if (t < best) {
+                best = t;
+                bestR = Rs[ri];
+                bestS = sched;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fem_status st = fem_batch_set_config(B, bestR, bestS);
+    if (st == FEM_OK) cache_store(cache_path, dev, sig, bestR, bestS, best);
+    return st;
+}
+
+fem_status fem_batch_graph_launch(fem_batch B, void* stream) {
+    if (!B) return fail(FEM_EINVAL, "fem_batch_graph_launch: batch is NULL");
+    if (!B->bound) return fail(FEM_ENOTREADY, "fem_batch_graph_launch: call fem_batch_bind first");
+    if (!B->work_valid)
+        if (fem_status st = build_work(B)) return st;
+    if (!B->graph_valid) {
+        drop_graph(B);
+        // make sure the kernel attributes are set outside the capture
+        FEM_HIP(hipStreamSynchronize(B->cap_stream));
+        if (fem_status st = fem_batch_assemble(B, B->cap_stream)) return st;
+        FEM_HIP(hipStreamSynchronize(B->cap_stream));
+        FEM_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeRelaxed));
+        fem_status st = fem_batch_assemble(B, B->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+        if (st != FEM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        B->graph = g;
+        e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(B);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        B->graph_valid = true;
+    }
+    FEM_HIP(hipGraphLaunch(B->exec, reinterpret_cast<hipStream_t>(stream)));
+    return FEM_OK;
+}
+
+void fem_batch_destroy(fem_batch B) {
+    if (!B) return;
+    (void)hipDeviceSynchronize();
+    drop_graph(B);
+    if (B->table_dev) (void)hipFree(B->table_dev);
+    if (B->work_dev) (void)hipFree(B->work_dev);
+    if (B->counters) (void)hipFree(B->counters);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    delete B;
+}
+
+}  // extern "C"

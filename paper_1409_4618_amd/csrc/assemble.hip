@@ -1,0 +1,692 @@
+// Numeric assembly of K(a), M(b) (forward), its adjoint (backward) and the
+// batched persistent launch.
+//
+// Forward ("row tiles"): the CSR rows are cut into tiles of R consecutive rows;
+// a tile owns the contiguous value range rowptr[r0] .. rowptr[r0+R]. One
+// workgroup of R threads takes a tile, one thread per row. The thread walks the
+// row's slots (element, local dof) in ascending element order, recomputes that
+// element's geometry in registers, forms row k of the element's K and M
+// (Section 2.4; closed forms in element.h) and adds it into the row's segment of
+// an LDS copy of the tile's values, at the byte offsets of the scatter map. The
+// sum over the elements sharing a matrix entry is therefore a segmented
+// reduction in a fixed order (deterministic, no atomics), and the tile is
+// written to HBM once with coalesced stores.
+//
+// Workgroups are mapped to tiles XCD by XCD (workgroup b runs on XCD b mod 8),
+// so each XCD walks a contiguous range of rows and its L2 sees the reuse of
+// element data between neighbouring rows.
+#include <algorithm>
+
+#include "element.h"
+#include "fem_internal.h"
+
+namespace fem {
+
+template <int KC>
+struct KT;
+template <>
+struct KT<0> {  // 2D (Nedelec / Raviart-Thomas)
+    static constexpr int DIM = 2, NLOC = 3, NV = 3;
+};
+template <>
+struct KT<1> {  // 3D Raviart-Thomas
+    static constexpr int DIM = 3, NLOC = 4, NV = 4;
+};
+template <>
+struct KT<2> {  // 3D Nedelec
+    static constexpr int DIM = 3, NLOC = 6, NV = 4;
+};
+
+int kind_code(int dim, fem_kind kind) {
+    if (dim == 2) return 0;
+    return kind == FEM_RAVIART_THOMAS ? 1 : 2;
+}
+
+int rows_index(int rows_per_tile) { return rows_per_tile == 64 ? 0 : (rows_per_tile == 128 ? 1 : 2); }
+
+// Element data of one slot: global node ids and coordinates.
+template <int KC>
+struct SlotData {
+    int gid[KT<KC>::NV];
+    double x[KT<KC>::NV][KT<KC>::DIM];
+};
+
+// Row k of the local K, M of an element (no coefficients), sign-adjusted.
+// Returns the Jacobian determinant (for the error check).
+template <int KC>
+__device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double* Kr, double* Mr) {
+    if constexpr (KC == 2) {
+        V3 x[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = {d.x[v][0], d.x[v][1], d.x[v][2]};
+        const Geo3 g = geo3(x);
+        double s[6];
+        ned3_signs(d.gid, s);
+        ned3_row(g, s, k, Kr, Mr);
+        return g.J;
+    } else if constexpr (KC == 1) {
+        V3 x[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = {d.x[v][0], d.x[v][1], d.x[v][2]};
+        const GeoRT3 g = geo_rt3(x);
+        double s[4];
+        rt3_signs(d.gid, s);
+        rt3_row(g, s, k, Kr, Mr);
+        return g.J;
+    } else {
+        V2 x[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) x[v] = {d.x[v][0], d.x[v][1]};
+        const Geo2 g = geo2(x);
+        double s[3];
+        tri_signs(d.gid, s);
+        tri_row(g, s, k, Kr, Mr);
+        return g.J;
+    }
+}
+
+template <int NLOC>
+__device__ __forceinline__ uint64_t load_colpos(const uint8_t* colpos, int64_t j) {
+    if constexpr (NLOC > 4) {
+        return reinterpret_cast<const uint64_t*>(colpos)[j];
+    } else {
+        return reinterpret_cast<const uint32_t*>(colpos)[j];
+    }
+}
+
+// One tile of R rows: the body shared by the single-mesh and the batched kernels.
+template <int KC, int R, int U>
+__device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double* sK, double* sM) {
+    using Tr = KT<KC>;
+    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
+    const int tid = threadIdx.x;
+    const int64_t r0 = tile * R;
+    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
+    const int64_t p0 = md.rowptr[r0];
+    const int nt = (int)(md.rowptr[r1] - p0);
+    for (int i = tid; i < nt; i += R) {
+        sK[i] = 0.0;
+        sM[i] = 0.0;
+    }
+    __syncthreads();
+    const int64_t r = r0 + tid;
+    bool bad = false;
+    if (r < r1) {
+        const int rb = (int)(md.rowptr[r] - p0);
+        const int j0 = md.rs_ptr[r];
+        const int j1 = md.rs_ptr[r + 1];
+        for (int j = j0; j < j1; j += U) {
+            int slot[U];
+            uint64_t cp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = (j + u < j1) ? j + u : j1 - 1;
+                slot[u] = md.rs_slot[jj];
+                cp[u] = load_colpos<NLOC>(md.colpos, jj);
+            }
+            SlotData<KC> sd[U];
+            double ca[U], cb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = slot[u] / NLOC;
+                if constexpr (NV == 4) {
+                    const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
+                    sd[u].gid[0] = q.x;
+                    sd[u].gid[1] = q.y;
+                    sd[u].gid[2] = q.z;
+                    sd[u].gid[3] = q.w;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sd[u].gid[v] = md.elems[e * NV + v];
+                }
+                ca[u] = md.a ? md.a[e] : 1.0;
+                cb[u] = md.b ? md.b[e] : 1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+                        sd[u].x[v][c] = md.nodes[(int64_t)sd[u].gid[v] * DIM + c];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (j + u < j1) {
+                    const int k = slot[u] - (slot[u] / NLOC) * NLOC;
+                    double Kr[NLOC], Mr[NLOC];
+                    const double J = slot_row<KC>(sd[u], k, Kr, Mr);
+                    bad |= !(fabs(J) > 0.0) || !isfinite(J);
+#pragma unroll
+                    for (int l = 0; l < NLOC; ++l) {
+                        const int pos = rb + (int)((cp[u] >> (8 * l)) & 0xFFu);
+                        sK[pos] += ca[u] * Kr[l];
+                        sM[pos] += cb[u] * Mr[l];
+                    }
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
+    __syncthreads();
+    double* K = md.K;
+    double* M = md.M;
+    if (K)
+        for (int i = tid; i < nt; i += R) K[p0 + i] = sK[i];
+    if (M)
+        for (int i = tid; i < nt; i += R) M[p0 + i] = sM[i];
+}
+
+constexpr int FWD_U = 4;
+
+template <int KC, int R>
+__global__ __launch_bounds__(R) void k_forward(const MeshDev md) {
+    extern __shared__ double smem[];
+    // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
+    // contiguous range of tiles.
+    const int64_t per = gridDim.x / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= md.n_tiles) return;
+    const int pmax = (int)((md.rowptr[(tile + 1) * R < md.n_rows ? (tile + 1) * R : md.n_rows] -
+                            md.rowptr[tile * R]));
+    fwd_tile<KC, R, FWD_U>(md, tile, smem, smem + pmax);
+}
+
+// Batched persistent kernel: every workgroup pulls (mesh, tile) work items.
+// schedule 0: static stride over the work list; 1 and 2: a device counter
+// (2 = the host sorted the work list by decreasing cost first). The last
+// workgroup to finish resets the counters, so no memset is needed between
+// launches (graph replays included).
+template <int R>
+__global__ __launch_bounds__(R) void k_batch(const MeshDev* __restrict__ table,
+                                             const int2* __restrict__ work, int64_t n_work,
+                                             int schedule, unsigned* counters) {
+    extern __shared__ double smem[];
+    __shared__ int64_t s_w;
+    int64_t w = blockIdx.x;
+    for (;;) {
+        if (schedule != 0) {
+            if (threadIdx.x == 0) s_w = (int64_t)atomicAdd(&counters[0], 1u);
+            __syncthreads();
+            w = s_w;
+            __syncthreads();
+        }
+        if (w >= n_work) break;
+        const int2 item = work[w];
+        const MeshDev md = table[item.x];
+        const int64_t tile = item.y;
+        const int64_t r1 = (tile + 1) * R < md.n_rows ? (tile + 1) * R : md.n_rows;
+        const int nt = (int)(md.rowptr[r1] - md.rowptr[tile * R]);
+        switch (md.kind_code) {
+            case 0: fwd_tile<0, R, FWD_U>(md, tile, smem, smem + nt); break;
+            case 1: fwd_tile<1, R, FWD_U>(md, tile, smem, smem + nt); break;
+            default: fwd_tile<2, R, FWD_U>(md, tile, smem, smem + nt); break;
+        }
+        __syncthreads();
+        if (schedule == 0) w += gridDim.x;
+    }
+    if (schedule != 0 && threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+int lds_limit_bytes() {
+    static int lim = 0;
+    if (!lim) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        lim = v;
+    }
+    return lim;
+}
+
+int cu_count() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        n = v;
+    }
+    return n;
+}
+
+int default_rows_per_tile(int kc) { return kc == 2 ? 128 : 256; }
+
+template <class K>
+static hipError_t set_lds(K kernel, int bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int KC, int R>
+static fem_status launch_fwd_t(const MeshDev& md, int pmax, hipStream_t s) {
+    const int bytes = pmax * 16;
+    FEM_HIP(set_lds(k_forward<KC, R>, bytes));
+    const int64_t grid = ((md.n_tiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_forward<KC, R>), dim3((unsigned)grid), dim3(R), bytes, s, md);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
+fem_status launch_forward(const MeshDev& md, int R, int pmax, hipStream_t s) {
+    if (md.n_tiles == 0) return FEM_OK;
+    if (pmax * 16 > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_assemble: a row tile needs more LDS than the device has");
+#define FEM_FWD_CASE(KC)                                                     \
+    switch (R) {                                                             \
+        case 64: return launch_fwd_t<KC, 64>(md, pmax, s);                   \
+        case 128: return launch_fwd_t<KC, 128>(md, pmax, s);                 \
+        default: return launch_fwd_t<KC, 256>(md, pmax, s);                  \
+    }
+    switch (md.kind_code) {
+        case 0: FEM_FWD_CASE(0);
+        case 1: FEM_FWD_CASE(1);
+        default: FEM_FWD_CASE(2);
+    }
+#undef FEM_FWD_CASE
+}
+
+template <int R>
+static fem_status launch_batch_t(const MeshDev* table, const int2* work, int64_t n_work,
+                                 int schedule, int grid, int pmax, unsigned* counters,
+                                 hipStream_t s) {
+    const int bytes = pmax * 16;
+    FEM_HIP(set_lds(k_batch<R>, bytes));
+    hipLaunchKernelGGL(k_batch<R>, dim3((unsigned)grid), dim3(R), bytes, s, table, work, n_work,
+                       schedule, counters);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
+fem_status launch_batch(const MeshDev* table, const int2* work, int64_t n_work, int R,
+                        int schedule, int grid, int pmax, unsigned* counters, hipStream_t s) {
+    if (n_work == 0) return FEM_OK;
+    if (pmax * 16 > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_batch: a row tile needs more LDS than the device has");
+    switch (R) {
+        case 64: return launch_batch_t<64>(table, work, n_work, schedule, grid, pmax, counters, s);
+        case 128: return launch_batch_t<128>(table, work, n_work, schedule, grid, pmax, counters, s);
+        default: return launch_batch_t<256>(table, work, n_work, schedule, grid, pmax, counters, s);
+    }
+}
+
+// ===========================================================================
+// Backward: element-major adjoint.
+// For each element: gather the upstream weights of its n_local^2 entries through
+// the scatter map, contract them with the local matrices (dL/da, dL/db) and with
+// their derivatives with respect to the element's vertices (hand-derived from
+// the closed forms of element.h; d|J| = |J| tr(B^-1 dB)). The per-element
+// vertex derivatives are then summed per node in ascending element order.
+// ===========================================================================
+struct BwdArgs {
+    const int32_t* elems;
+    const double* nodes;
+    const double* a;
+    const double* b;
+    const double* gK;
+    const double* gM;
+    const int32_t* elems2dofs;
+    const int64_t* rowptr;
+    const int32_t* slot_rank;
+    const uint8_t* colpos;
+    double* ga;
+    double* gb;
+    double* partials;
+    int64_t T;
+    int* err_word;
+};
+
+template <int NLOC>
+__device__ __forceinline__ void gather_weights(const BwdArgs& A, int64_t e, double GK[NLOC][NLOC],
+                                               double GM[NLOC][NLOC]) {
+#pragma unroll
+    for (int k = 0; k < NLOC; ++k) {
+        const int64_t s = e * NLOC + k;
+        const int64_t base = A.rowptr[A.elems2dofs[s]];
+        const uint64_t cp = load_colpos<NLOC>(A.colpos, A.slot_rank[s]);
+#pragma unroll
+        for (int l = 0; l < NLOC; ++l) {
+            const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
+            GK[k][l] = A.gK ? A.gK[pos] : 0.0;
+            GM[k][l] = A.gM ? A.gM[pos] : 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ V3 vsel(const V3* v, int i) { return v[i]; }
+
+// 3D Nedelec
+__device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
+    int gid[4];
+    V3 x[4];
+    const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
+    gid[0] = q4.x; gid[1] = q4.y; gid[2] = q4.z; gid[3] = q4.w;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
+    double GK[6][6], GM[6][6];
+    gather_weights<6>(A, e, GK, GM);
+    const Geo3 g = geo3(x);
+    V3 o[6];
+    ned3_o(g, o);
+    double s[6];
+    ned3_signs(gid, s);
+    const double aJ = fabs(g.J);
+    double Phi = 0.0;
+    V3 q[6];
+    double Q[4][4];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q[k] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Q[i][j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = nib(NED3_START, k), j = nib(NED3_END, k);
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            const int m = nib(NED3_START, l), n = nib(NED3_END, l);
+            const double ss = s[k] * s[l];
+            const double gk = GK[k][l] * ss;
+            const double gm = GM[k][l] * ss;
+            Phi += gk * dot(o[k], o[l]);
+            q[k] = add(q[k], scale(o[l], gk));
+            q[l] = add(q[l], scale(o[k], gk));
+            Q[j][n] += gm * (1.0 + (i == m));
+            Q[j][m] -= gm * (1.0 + (i == n));
+            Q[i][n] -= gm * (1.0 + (j == m));
+            Q[i][m] += gm * (1.0 + (j == n));
+        }
+    }
+    double Psi = 0.0;
+    V3 w[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        w[a] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            Psi += Q[a][bb] * dot(g.c[a], g.c[bb]);
+            w[a] = add(w[a], scale(g.c[bb], Q[a][bb] + Q[bb][a]));
+        }
+    }
+    const double ca = A.a ? A.a[e] : 1.0;
+    const double cb = A.b ? A.b[e] : 1.0;
+    if (A.ga) A.ga[e] = (2.0 / 3.0) * Phi / aJ;
+    if (A.gb) A.gb[e] = Psi / (120.0 * aJ);
+    if (A.partials) {
+        const V3 dPhi[3] = {add(sub(q[1], q[2]), q[4]), add(sub(q[2], q[0]), q[5]),
+                            add(sub(q[0], q[1]), q[3])};
+        const V3 w1 = sub(w[1], w[0]), w2 = sub(w[2], w[0]), w3 = sub(w[3], w[0]);
+        const V3 dPsi[3] = {add(cross(w2, g.b3), cross(g.b2, w3)), add(cross(g.b3, w1), cross(w3, g.b1)),
+                            add(cross(w1, g.b2), cross(g.b1, w2))};
+        const double fk = ca * (2.0 / 3.0) / aJ;
+        const double fm = cb * (1.0 / 120.0) / aJ;
+        V3 d0 = {0.0, 0.0, 0.0};
+        double* out = A.partials + e * 12;
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            const V3 cj = g.c[jj + 1];
+            const V3 dj = add(scale(sub(dPhi[jj], scale(cj, Phi / g.J)), fk),
+                              scale(sub(dPsi[jj], scale(cj, Psi / g.J)), fm));
+            out[3 * (jj + 1)] = dj.x;
+            out[3 * (jj + 1) + 1] = dj.y;
+            out[3 * (jj + 1) + 2] = dj.z;
+            d0 = sub(d0, dj);
+        }
+        out[0] = d0.x;
+        out[1] = d0.y;
+        out[2] = d0.z;
+    }
+    if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+}
+
+// 3D Raviart-Thomas
+__device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
+    int gid[4];
+    V3 x[4];
+    const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
+    gid[0] = q4.x; gid[1] = q4.y; gid[2] = q4.z; gid[3] = q4.w;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
+    double GK[4][4], GM[4][4];
+    gather_weights<4>(A, e, GK, GM);
+    const GeoRT3 g = geo_rt3(x);
+    double s[4];
+    rt3_signs(gid, s);
+    const double aJ = fabs(g.J);
+    double hK = 0.0, hM = 0.0, cross_term = 0.0;
+    double rho[4] = {0.0, 0.0, 0.0, 0.0};
+    V3 z[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) z[p] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pk = 3 - k;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int pl = 3 - l;
+            const double ss = s[k] * s[l];
+            const double hk = GK[k][l] * ss;
+            const double hm = GM[k][l] * ss;
+            hK += hk;
+            hM += hm;
+            rho[pk] += hm;
+            rho[pl] += hm;
+            cross_term += hm * dot(g.y[pk], g.y[pl]);
+            z[pk] = add(z[pk], scale(g.y[pl], hm));
+            z[pl] = add(z[pl], scale(g.y[pk], hm));
+        }
+    }
+    double ru = 0.0;
+#pragma unroll
+    for (int p = 1; p < 4; ++p) ru += rho[p] * g.u[p];
+    const double Omega = hM * g.base - 5.0 * ru + 20.0 * cross_term;
+    const double ca = A.a ? A.a[e] : 1.0;
+    const double cb = A.b ? A.b[e] : 1.0;
+    if (A.ga) A.ga[e] = 1.5 * hK / aJ;
+    if (A.gb) A.gb[e] = Omega / (120.0 * aJ);
+    if (A.partials) {
+        const V3 S = add(add(g.y[1], g.y[2]), g.y[3]);
+        V3 rp = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int p = 1; p < 4; ++p) rp = add(rp, scale(g.y[p], rho[p]));
+        const V3 c[3] = {cross(g.y[2], g.y[3]), cross(g.y[3], g.y[1]), cross(g.y[1], g.y[2])};
+        V3 d0 = {0.0, 0.0, 0.0};
+        double* out = A.partials + e * 12;
+#pragma unroll
+        for (int a = 1; a < 4; ++a) {
+            const V3 dOm = add(sub(scale(add(S, g.y[a]), 2.0 * hM), scale(add(scale(S, rho[a]), rp), 5.0)),
+                               scale(z[a], 20.0));
+            const V3 ck = c[a - 1];
+            const V3 dK = scale(ck, -ca * 1.5 * hK / (aJ * g.J));
+            const V3 dM = scale(sub(dOm, scale(ck, Omega / g.J)), cb / (120.0 * aJ));
+            const V3 da = add(dK, dM);
+            out[3 * a] = da.x;
+            out[3 * a + 1] = da.y;
+            out[3 * a + 2] = da.z;
+            d0 = sub(d0, da);
+        }
+        out[0] = d0.x;
+        out[1] = d0.y;
+        out[2] = d0.z;
+    }
+    if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+}
+
+// 2D (both kinds)
+__device__ void bwd_tri(const BwdArgs& A, int64_t e) {
+    int gid[3];
+    V2 x[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        gid[v] = A.elems[e * 3 + v];
+        x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
+    }
+    double GK[3][3], GM[3][3];
+    gather_weights<3>(A, e, GK, GM);
+    const Geo2 g = geo2(x);
+    double s[3];
+    tri_signs(gid, s);
+    const double aJ = fabs(g.J);
+    double hK = 0.0;
+    double Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q[i][j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = nib(TRI_START, k), j = nib(TRI_END, k);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int m = nib(TRI_START, l), n = nib(TRI_END, l);
+            const double ss = s[k] * s[l];
+            hK += GK[k][l] * ss;
+            const double gm = GM[k][l] * ss;
+            Q[j][n] += gm * (1.0 + (i == m));
+            Q[j][m] -= gm * (1.0 + (i == n));
+            Q[i][n] -= gm * (1.0 + (j == m));
+            Q[i][m] += gm * (1.0 + (j == n));
+        }
+    }
+    double Psi = 0.0;
+    V2 w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w[a] = {0.0, 0.0};
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            Psi += Q[a][bb] * dot2(g.c[a], g.c[bb]);
+            const double f = Q[a][bb] + Q[bb][a];
+            w[a] = {w[a].x + f * g.c[bb].x, w[a].y + f * g.c[bb].y};
+        }
+    }
+    const double ca = A.a ? A.a[e] : 1.0;
+    const double cb = A.b ? A.b[e] : 1.0;
+    if (A.ga) A.ga[e] = 2.0 * hK / aJ;
+    if (A.gb) A.gb[e] = Psi / (24.0 * aJ);
+    if (A.partials) {
+        const V2 w1 = {w[1].x - w[0].x, w[1].y - w[0].y};
+        const V2 w2 = {w[2].x - w[0].x, w[2].y - w[0].y};
+        const V2 dPsi[2] = {{w2.y, -w2.x}, {-w1.y, w1.x}};
+        const double fk = -ca * 2.0 * hK / (aJ * g.J);
+        const double fm = cb / (24.0 * aJ);
+        double* out = A.partials + e * 6;
+        double d0x = 0.0, d0y = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const V2 cj = g.c[jj + 1];
+            const double dx = fk * cj.x + fm * (dPsi[jj].x - cj.x * Psi / g.J);
+            const double dy = fk * cj.y + fm * (dPsi[jj].y - cj.y * Psi / g.J);
+            out[2 * (jj + 1)] = dx;
+            out[2 * (jj + 1) + 1] = dy;
+            d0x -= dx;
+            d0y -= dy;
+        }
+        out[0] = d0x;
+        out[1] = d0y;
+    }
+    if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.T) return;
+    if constexpr (KC == 2) bwd_ned3(A, e);
+    else if constexpr (KC == 1) bwd_rt3(A, e);
+    else bwd_tri(A, e);
+}
+
+// gnodes[v] = sum of the per-element vertex derivatives, ascending element order.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const int32_t* node_slot,
+                                                      const double* partials, int64_t V, double* gnodes) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    double acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+    const int j1 = node_ptr[v + 1];
+    for (int j = node_ptr[v]; j < j1; ++j) {
+        const int64_t q = node_slot[j];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += partials[q * DIM + c];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) gnodes[v * DIM + c] = acc[c];
+}
+
+fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
+                           const double* a, const double* b, const double* gK, const double* gM,
+                           double* ga, double* gb, double* gnodes, hipStream_t s) {
+    const int kc = kind_code(m->dim, kind);
+    const int nv = m->dim + 1;
+    if (gnodes) {
+        if (fem_status st = build_node_map(m, s)) return st;
+        if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, m->T * nv * m->dim));
+    }
+    BwdArgs A;
+    A.elems = m->elems;
+    A.nodes = nodes;
+    A.a = a;
+    A.b = b;
+    A.gK = gK;
+    A.gM = gM;
+    A.elems2dofs = ds.elems2dofs;
+    A.rowptr = ds.pat.rowptr;
+    A.slot_rank = ds.pat.slot_rank;
+    A.colpos = ds.pat.colpos;
+    A.ga = ga;
+    A.gb = gb;
+    A.partials = gnodes ? m->elem_partials : nullptr;
+    A.T = m->T;
+    A.err_word = m->err_word;
+    const unsigned grid = (unsigned)((m->T + 255) / 256);
+    if (m->T > 0) {
+        if (kc == 2) hipLaunchKernelGGL(k_backward<2>, dim3(grid), dim3(256), 0, s, A);
+        else if (kc == 1) hipLaunchKernelGGL(k_backward<1>, dim3(grid), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL(k_backward<0>, dim3(grid), dim3(256), 0, s, A);
+        FEM_HIP(hipGetLastError());
+    }
+    if (gnodes && m->V > 0) {
+        const unsigned gv = (unsigned)((m->V + 255) / 256);
+        if (m->dim == 3)
+            hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->node_slot,
+                               m->elem_partials, m->V, gnodes);
+        else
+            hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->node_slot,
+                               m->elem_partials, m->V, gnodes);
+        FEM_HIP(hipGetLastError());
+    }
+    return FEM_OK;
+}
+
+}  // namespace fem
+
+namespace fem {
+int batch_blocks_per_cu(int R, int bytes) {
+    int n = 0;
+    hipError_t e;
+    switch (R) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<64>, 64, bytes); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<128>, 128, bytes); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<256>, 256, bytes); break;
+    }
+    if (e != hipSuccess || n <= 0) n = 1;
+    return n;
+}
+}  // namespace fem

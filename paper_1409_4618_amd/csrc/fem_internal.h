@@ -1,0 +1,148 @@
+// Internal declarations of libfem (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fem.h"
+
+namespace fem {
+
+// ---------------------------------------------------------------------------
+// error reporting
+void set_error(const std::string& msg);
+fem_status fail(fem_status st, const std::string& msg);
+fem_status hip_fail(hipError_t e, const char* what);
+
+#define FEM_HIP(call)                                              \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return ::fem::hip_fail(_e, #call);   \
+    } while (0)
+
+// device error word bits
+enum : int { ERR_DEGENERATE = 1, ERR_NONFINITE = 2, ERR_RANGE = 4, ERR_OVERFLOW = 8 };
+
+// ---------------------------------------------------------------------------
+// device buffers owned by a handle
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Pattern + maps for one dof type (edges or faces) of a mesh.
+struct Pattern {
+    bool built = false;
+    int nloc = 0;             // local dofs per element (3, 4 or 6)
+    int cp_stride = 0;        // bytes per colpos record (4 or 8)
+    int64_t n_rows = 0;
+    int64_t nnz = 0;
+    int64_t* rowptr = nullptr;    // [n_rows+1]
+    int32_t* colind = nullptr;    // [nnz]
+    uint8_t* colpos = nullptr;    // [n_slots][cp_stride], in row-sorted slot order
+    int32_t* slot_rank = nullptr; // [n_slots] position of slot s in the row-sorted order
+    int max_row_len = 0;
+    // max nnz of a tile of R consecutive rows, for R = 64, 128, 256
+    int tile_pmax[3] = {0, 0, 0};
+};
+
+// Dof structure of a mesh shared by the kinds that use the same dofs.
+struct DofSet {
+    int nloc = 0;
+    int64_t n = 0;                 // number of dofs (edges or faces)
+    int32_t* elems2dofs = nullptr; // [T][nloc]
+    int32_t* rs_ptr = nullptr;     // [n+1] start of each dof's run of slots
+    int32_t* rs_slot = nullptr;    // [T*nloc] slots (e*nloc + k) sorted by (dof, slot)
+    Pattern pat;
+};
+
+}  // namespace fem
+
+struct fem_mesh_s {
+    int device = 0;
+    int dim = 0;
+    int64_t V = 0, T = 0;
+    int32_t* elems = nullptr;        // library copy [T][dim+1]
+    int32_t* edges2nodes = nullptr;  // [E][2]
+    int8_t* signs_e = nullptr;       // [T][ne]
+    int32_t* faces2nodes = nullptr;  // [F][3]
+    int8_t* signs_f = nullptr;       // [T][4]
+    fem::DofSet edges;
+    fem::DofSet faces;
+    // backward scratch
+    double* elem_partials = nullptr; // [T][(dim+1)*dim]
+    int32_t* node_ptr = nullptr;     // [V+1]
+    int32_t* node_slot = nullptr;    // [T*(dim+1)] (e*(dim+1)+v) sorted by node
+    int* err_word = nullptr;         // device error word
+    hipStream_t last_stream = nullptr;
+    std::vector<void*> allocs;       // everything to free
+};
+
+namespace fem {
+
+// memory helpers (record the allocation in the mesh)
+hipError_t dmalloc(fem_mesh m, void** p, size_t bytes);
+template <class T>
+hipError_t dmalloc(fem_mesh m, T** p, size_t count) {
+    return dmalloc(m, reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// primitives (radix_sort.hip)
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+// keys/vals hold the input; tmp buffers of the same size are needed. The sorted
+// result ends up in keys/vals. `scratch` is managed internally (hipMalloc).
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
+                            uint32_t* vals_tmp, int64_t n, int bits, hipStream_t s);
+// Exclusive prefix sum of a u32 array in place (total < 2^32).
+hipError_t scan_exclusive_u32(uint32_t* data, int64_t n, hipStream_t s);
+int bit_length(uint64_t v);
+
+// ---------------------------------------------------------------------------
+// topology / pattern (topology.hip)
+fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems,
+                          hipStream_t s);
+fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s);
+fem_status build_node_map(fem_mesh m, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// per-tile kernels (assemble.hip)
+struct MeshDev {
+    // geometry / topology
+    const int32_t* elems;
+    const double* nodes;
+    const double* a;
+    const double* b;
+    double* K;
+    double* M;
+    // pattern
+    const int64_t* rowptr;
+    const int32_t* rs_ptr;
+    const int32_t* rs_slot;
+    const uint8_t* colpos;
+    int64_t n_rows;
+    int64_t n_tiles;        // for the chosen rows-per-tile
+    int32_t kind_code;      // 0: 2D (both kinds), 1: 3D Raviart-Thomas, 2: 3D Nedelec
+    int32_t pad;
+    int* err_word;
+};
+
+int kind_code(int dim, fem_kind kind);
+int rows_index(int rows_per_tile);  // 64 -> 0, 128 -> 1, 256 -> 2
+fem_status launch_forward(const MeshDev& md, int rows_per_tile, int pmax, hipStream_t s);
+fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
+                           const double* a, const double* b, const double* gK,
+                           const double* gM, double* ga, double* gb, double* gnodes,
+                           hipStream_t s);
+fem_status launch_batch(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
+                        int rows_per_tile, int schedule, int grid, int pmax,
+                        unsigned* counters, hipStream_t s);
+int lds_limit_bytes();
+int batch_blocks_per_cu(int rows_per_tile, int lds_bytes);
+int cu_count();
+int default_rows_per_tile(int kind_code);
+
+}  // namespace fem

@@ -1,0 +1,511 @@
+// Mesh topology (global edge / face numbering, element -> dof maps, sign data)
+// and the one-time CSR pattern with its scatter map.
+//
+// Section 3 (Anjam & Valdman): the rows of edges2nodes / faces2nodes are the
+// global degrees of freedom, elems2edges / elems2faces the local -> global
+// maps. Here an edge is the sorted node pair (lo, hi) with key lo*V + hi, a face
+// the sorted triple (a, b, c) with key eid(a,b)*V + c (eid = global id of the
+// edge (a, b), which preserves lexicographic order and keeps keys below 2^64
+// for any mesh with int32 ids). A stable radix sort of (key, slot) pairs, slot =
+// element*n_local + local index, followed by unique gives the lexicographic
+// numbering, the element -> dof map, and for each dof the run of slots that
+// reference it in ascending element order (used by the assembly kernels).
+//
+// Pattern: every local pair (k, l) of every element gives the key
+// dof_k * N + dof_l; sort + unique gives colind and rowptr, and each element's
+// pairs get their CSR position (the scatter map). The map is stored compactly
+// as, for each slot in row-sorted order, the byte offsets of its n_local
+// columns inside the row.
+#include "element.h"
+#include "fem_internal.h"
+
+namespace fem {
+
+constexpr int TB = 256;
+
+static inline unsigned nblk(int64_t n, int t = TB) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- validation
+__global__ void k_validate_range(const int32_t* elems, int64_t n, int64_t V, int* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = elems[i];
+    if (v < 0 || v >= V) atomicOr(err, ERR_RANGE);
+}
+
+__global__ void k_validate_nodes(const double* nodes, int64_t n, int* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!isfinite(nodes[i])) atomicOr(err, ERR_NONFINITE);
+}
+
+template <int DIM>
+__global__ void k_validate_det(const double* nodes, const int32_t* elems, int64_t T, int* err) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    double J;
+    if (DIM == 3) {
+        V3 x[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t n = elems[e * 4 + v];
+            x[v] = {nodes[n * 3], nodes[n * 3 + 1], nodes[n * 3 + 2]};
+        }
+        J = geo3(x).J;
+    } else {
+        V2 x[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int64_t n = elems[e * 3 + v];
+            x[v] = {nodes[n * 2], nodes[n * 2 + 1]};
+        }
+        J = geo2(x).J;
+    }
+    if (J == 0.0) atomicOr(err, ERR_DEGENERATE);
+    if (!isfinite(J)) atomicOr(err, ERR_NONFINITE);
+}
+
+// ---------------------------------------------------------------- edges / faces
+template <int DIM>
+__global__ void k_edge_keys(const int32_t* elems, int64_t T, int64_t V, uint64_t* keys,
+                            uint32_t* vals) {
+    constexpr int NE = DIM == 3 ? 6 : 3;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T * NE) return;
+    const int64_t e = q / NE;
+    const int k = (int)(q - e * NE);
+    const int s = DIM == 3 ? nib(NED3_START, k) : nib(TRI_START, k);
+    const int t = DIM == 3 ? nib(NED3_END, k) : nib(TRI_END, k);
+    const uint64_t gs = (uint32_t)elems[e * (DIM + 1) + s];
+    const uint64_t gt = (uint32_t)elems[e * (DIM + 1) + t];
+    const uint64_t lo = gs < gt ? gs : gt;
+    const uint64_t hi = gs < gt ? gt : gs;
+    keys[q] = lo * (uint64_t)V + hi;
+    vals[q] = (uint32_t)q;
+}
+
+__global__ void k_flags(const uint64_t* keys, int64_t n, uint32_t* flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// After the exclusive scan of the flags: id = scan + flag - 1.
+__global__ void k_edge_unique(const uint64_t* keys, const uint32_t* sorted_slots,
+                              const uint32_t* scan, int64_t n, int64_t V, int32_t* elems2dofs,
+                              int32_t* edges2nodes, int32_t* rs_ptr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool head = (i == 0 || keys[i] != keys[i - 1]);
+    const int32_t id = (int32_t)(scan[i] + (head ? 1u : 0u) - 1u);
+    elems2dofs[sorted_slots[i]] = id;
+    if (head) {
+        const uint64_t k = keys[i];
+        edges2nodes[2 * (int64_t)id] = (int32_t)(k / (uint64_t)V);
+        edges2nodes[2 * (int64_t)id + 1] = (int32_t)(k % (uint64_t)V);
+        rs_ptr[id] = (int32_t)i;
+    }
+}
+
+// 3D local edge index of the local node pair {p, q}.
+__device__ __forceinline__ int tet_edge_index(int p, int q) {
+    const int a = p < q ? p : q;
+    const int b = p < q ? q : p;
+    // (0,1)->0 (0,2)->1 (0,3)->2 (1,2)->3 (2,3)->4 (1,3)->5
+    if (a == 0) return b - 1;
+    if (a == 1) return b == 2 ? 3 : 5;
+    return 4;
+}
+
+// Sorted (by global id) local node numbers of 3D face k (face k is opposite node 3-k).
+__device__ __forceinline__ void face_sorted_local(const int gid[4], int k, int out[3]) {
+    const int p = 3 - k;
+    int u = (p == 0) ? 1 : 0;
+    int v = (p <= 1) ? 2 : 1;
+    int w = (p <= 2) ? 3 : 2;
+    // sort three local numbers by their global ids
+    if (gid[u] > gid[v]) { const int t = u; u = v; v = t; }
+    if (gid[v] > gid[w]) { const int t = v; v = w; w = t; }
+    if (gid[u] > gid[v]) { const int t = u; u = v; v = t; }
+    out[0] = u;
+    out[1] = v;
+    out[2] = w;
+}
+
+__global__ void k_face_keys(const int32_t* elems, const int32_t* elems2edges, int64_t T, int64_t V,
+                            uint64_t* keys, uint32_t* vals) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T * 4) return;
+    const int64_t e = q / 4;
+    const int k = (int)(q - e * 4);
+    int gid[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gid[v] = elems[e * 4 + v];
+    int loc[3];
+    face_sorted_local(gid, k, loc);
+    const uint64_t eid = (uint32_t)elems2edges[e * 6 + tet_edge_index(loc[0], loc[1])];
+    keys[q] = eid * (uint64_t)V + (uint64_t)(uint32_t)gid[loc[2]];
+    vals[q] = (uint32_t)q;
+}
+
+__global__ void k_face_unique(const int32_t* elems, const uint64_t* keys,
+                              const uint32_t* sorted_slots, const uint32_t* scan, int64_t n,
+                              int32_t* elems2dofs, int32_t* faces2nodes, int32_t* rs_ptr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool head = (i == 0 || keys[i] != keys[i - 1]);
+    const int32_t id = (int32_t)(scan[i] + (head ? 1u : 0u) - 1u);
+    const uint32_t slot = sorted_slots[i];
+    elems2dofs[slot] = id;
+    if (head) {
+        const int64_t e = slot / 4;
+        const int k = (int)(slot - e * 4);
+        int gid[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gid[v] = elems[e * 4 + v];
+        int loc[3];
+        face_sorted_local(gid, k, loc);
+        faces2nodes[3 * (int64_t)id] = gid[loc[0]];
+        faces2nodes[3 * (int64_t)id + 1] = gid[loc[1]];
+        faces2nodes[3 * (int64_t)id + 2] = gid[loc[2]];
+        rs_ptr[id] = (int32_t)i;
+    }
+}
+
+template <int DIM>
+__global__ void k_edge_signs(const int32_t* elems, int64_t T, int8_t* signs) {
+    constexpr int NE = DIM == 3 ? 6 : 3;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T * NE) return;
+    const int64_t e = q / NE;
+    const int k = (int)(q - e * NE);
+    const int s = DIM == 3 ? nib(NED3_START, k) : nib(TRI_START, k);
+    const int t = DIM == 3 ? nib(NED3_END, k) : nib(TRI_END, k);
+    signs[q] = elems[e * (DIM + 1) + s] > elems[e * (DIM + 1) + t] ? 1 : -1;
+}
+
+__global__ void k_face_signs(const int32_t* elems, int64_t T, int8_t* signs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    int gid[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gid[v] = elems[e * 4 + v];
+    double s[4];
+    rt3_signs(gid, s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) signs[e * 4 + k] = s[k] > 0 ? 1 : -1;
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+
+// ---------------------------------------------------------------- helpers
+static fem_status read_count(const uint32_t* scan, const uint64_t* keys, int64_t n, hipStream_t s,
+                             int64_t* count) {
+    uint32_t last_scan = 0;
+    uint64_t k[2] = {0, 0};
+    FEM_HIP(hipMemcpyAsync(&last_scan, scan + n - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (n >= 2) {
+        FEM_HIP(hipMemcpyAsync(k, keys + n - 2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    }
+    FEM_HIP(hipStreamSynchronize(s));
+    const bool head = (n == 1) || (k[1] != k[0]);
+    *count = (int64_t)last_scan + (head ? 1 : 0);
+    return FEM_OK;
+}
+
+static fem_status read_err(fem_mesh m, hipStream_t s, int* out) {
+    FEM_HIP(hipMemcpyAsync(out, m->err_word, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+struct TmpBufs {
+    uint64_t* keys = nullptr;
+    uint64_t* keys_tmp = nullptr;
+    uint32_t* vals = nullptr;
+    uint32_t* vals_tmp = nullptr;
+    uint32_t* scan = nullptr;
+    hipError_t alloc(int64_t n) {
+        hipError_t e;
+        if ((e = hipMalloc((void**)&keys, n * sizeof(uint64_t))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&keys_tmp, n * sizeof(uint64_t))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&vals, n * sizeof(uint32_t))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&vals_tmp, n * sizeof(uint32_t))) != hipSuccess) return e;
+        if ((e = hipMalloc((void**)&scan, n * sizeof(uint32_t))) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    ~TmpBufs() {
+        if (keys) (void)hipFree(keys);
+        if (keys_tmp) (void)hipFree(keys_tmp);
+        if (vals) (void)hipFree(vals);
+        if (vals_tmp) (void)hipFree(vals_tmp);
+        if (scan) (void)hipFree(scan);
+    }
+};
+
+// ---------------------------------------------------------------- topology
+fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems_in,
+                          hipStream_t s) {
+    const int dim = m->dim;
+    const int64_t T = m->T, V = m->V;
+    const int nv = dim + 1;
+    const int ne = dim == 3 ? 6 : 3;
+    FEM_HIP(dmalloc(m, &m->err_word, 1));
+    FEM_HIP(hipMemsetAsync(m->err_word, 0, sizeof(int), s));
+    FEM_HIP(dmalloc(m, &m->elems, T * nv));
+    FEM_HIP(hipMemcpyAsync(m->elems, elems_in, T * nv * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    // 1. node ids in range, coordinates finite
+    hipLaunchKernelGGL(k_validate_range, dim3(nblk(T * nv)), dim3(TB), 0, s, m->elems, T * nv, V,
+                       m->err_word);
+    hipLaunchKernelGGL(k_validate_nodes, dim3(nblk(V * dim)), dim3(TB), 0, s, nodes, V * dim,
+                       m->err_word);
+    FEM_HIP(hipGetLastError());
+    int err = 0;
+    if (fem_status st = read_err(m, s, &err)) return st;
+    if (err & ERR_RANGE) return fail(FEM_ERANGE, "fem_topology: an element references a node id outside [0, n_nodes)");
+    if (err & ERR_NONFINITE) return fail(FEM_ENONFINITE, "fem_topology: a node coordinate is not finite");
+    // 2. non-degenerate elements
+    if (dim == 3)
+        hipLaunchKernelGGL(k_validate_det<3>, dim3(nblk(T)), dim3(TB), 0, s, nodes, m->elems, T, m->err_word);
+    else
+        hipLaunchKernelGGL(k_validate_det<2>, dim3(nblk(T)), dim3(TB), 0, s, nodes, m->elems, T, m->err_word);
+    FEM_HIP(hipGetLastError());
+    if (fem_status st = read_err(m, s, &err)) return st;
+    if (err & ERR_DEGENERATE) return fail(FEM_EDEGENERATE, "fem_topology: an element has a zero Jacobian determinant");
+    if (err & ERR_NONFINITE) return fail(FEM_ENONFINITE, "fem_topology: an element has a non-finite Jacobian determinant");
+
+    // 3. edges
+    const int64_t ns = T * ne;
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(ns > T * 4 ? ns : T * 4));
+    if (dim == 3)
+        hipLaunchKernelGGL(k_edge_keys<3>, dim3(nblk(ns)), dim3(TB), 0, s, m->elems, T, V, tb.keys, tb.vals);
+    else
+        hipLaunchKernelGGL(k_edge_keys<2>, dim3(nblk(ns)), dim3(TB), 0, s, m->elems, T, V, tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    const int edge_bits = bit_length((uint64_t)V * (uint64_t)V - 1);
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, ns, edge_bits, s));
+    hipLaunchKernelGGL(k_flags, dim3(nblk(ns)), dim3(TB), 0, s, tb.keys, ns, tb.scan);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(tb.scan, ns, s));
+    int64_t E = 0;
+    if (fem_status st = read_count(tb.scan, tb.keys, ns, s, &E)) return st;
+    DofSet& ed = m->edges;
+    ed.nloc = ne;
+    ed.n = E;
+    FEM_HIP(dmalloc(m, &ed.elems2dofs, ns));
+    FEM_HIP(dmalloc(m, &m->edges2nodes, 2 * E));
+    FEM_HIP(dmalloc(m, &ed.rs_ptr, E + 1));
+    FEM_HIP(dmalloc(m, &ed.rs_slot, ns));
+    hipLaunchKernelGGL(k_edge_unique, dim3(nblk(ns)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan, ns,
+                       V, ed.elems2dofs, m->edges2nodes, ed.rs_ptr);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, ed.rs_ptr + E, (int32_t)ns);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(hipMemcpyAsync(ed.rs_slot, tb.vals, ns * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    FEM_HIP(dmalloc(m, &m->signs_e, ns));
+    if (dim == 3)
+        hipLaunchKernelGGL(k_edge_signs<3>, dim3(nblk(ns)), dim3(TB), 0, s, m->elems, T, m->signs_e);
+    else
+        hipLaunchKernelGGL(k_edge_signs<2>, dim3(nblk(ns)), dim3(TB), 0, s, m->elems, T, m->signs_e);
+    FEM_HIP(hipGetLastError());
+
+    // 4. faces (3D)
+    if (dim == 3) {
+        const int64_t nf = T * 4;
+        hipLaunchKernelGGL(k_face_keys, dim3(nblk(nf)), dim3(TB), 0, s, m->elems, ed.elems2dofs, T, V,
+                           tb.keys, tb.vals);
+        FEM_HIP(hipGetLastError());
+        const int face_bits = bit_length((uint64_t)E * (uint64_t)V - 1);
+        FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, nf, face_bits, s));
+        hipLaunchKernelGGL(k_flags, dim3(nblk(nf)), dim3(TB), 0, s, tb.keys, nf, tb.scan);
+        FEM_HIP(hipGetLastError());
+        FEM_HIP(scan_exclusive_u32(tb.scan, nf, s));
+        int64_t F = 0;
+        if (fem_status st = read_count(tb.scan, tb.keys, nf, s, &F)) return st;
+        DofSet& fd = m->faces;
+        fd.nloc = 4;
+        fd.n = F;
+        FEM_HIP(dmalloc(m, &fd.elems2dofs, nf));
+        FEM_HIP(dmalloc(m, &m->faces2nodes, 3 * F));
+        FEM_HIP(dmalloc(m, &fd.rs_ptr, F + 1));
+        FEM_HIP(dmalloc(m, &fd.rs_slot, nf));
+        hipLaunchKernelGGL(k_face_unique, dim3(nblk(nf)), dim3(TB), 0, s, m->elems, tb.keys, tb.vals,
+                           tb.scan, nf, fd.elems2dofs, m->faces2nodes, fd.rs_ptr);
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, fd.rs_ptr + F, (int32_t)nf);
+        FEM_HIP(hipGetLastError());
+        FEM_HIP(hipMemcpyAsync(fd.rs_slot, tb.vals, nf * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        FEM_HIP(dmalloc(m, &m->signs_f, nf));
+        hipLaunchKernelGGL(k_face_signs, dim3(nblk(T)), dim3(TB), 0, s, m->elems, T, m->signs_f);
+        FEM_HIP(hipGetLastError());
+    }
+    FEM_HIP(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+// ---------------------------------------------------------------- pattern
+__global__ void k_pair_keys(const int32_t* elems2dofs, int64_t T, int nloc, int64_t N,
+                            uint64_t* keys, uint32_t* vals) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n2 = (int64_t)nloc * nloc;
+    if (q >= T * n2) return;
+    const int64_t e = q / n2;
+    const int kl = (int)(q - e * n2);
+    const int k = kl / nloc;
+    const int l = kl - k * nloc;
+    const uint64_t I = (uint32_t)elems2dofs[e * nloc + k];
+    const uint64_t J = (uint32_t)elems2dofs[e * nloc + l];
+    keys[q] = I * (uint64_t)N + J;
+    vals[q] = (uint32_t)q;
+}
+
+__global__ void k_pair_unique(const uint64_t* keys, const uint32_t* sorted_pairs,
+                              const uint32_t* scan, int64_t n, int64_t N, int32_t* colind,
+                              int64_t* rowptr, int32_t* map) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    const bool head = (i == 0 || k != keys[i - 1]);
+    const int32_t id = (int32_t)(scan[i] + (head ? 1u : 0u) - 1u);
+    map[sorted_pairs[i]] = id;
+    if (head) {
+        const uint64_t row = k / (uint64_t)N;
+        colind[id] = (int32_t)(k - row * (uint64_t)N);
+        if (i == 0 || keys[i - 1] / (uint64_t)N != row) rowptr[row] = id;
+    }
+}
+
+__global__ void k_slot_rank(const int32_t* rs_slot, int64_t n, int32_t* rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rank[rs_slot[i]] = (int32_t)i;
+}
+
+__global__ void k_colpos(const int32_t* rs_slot, const int32_t* elems2dofs, const int32_t* map,
+                         const int64_t* rowptr, int64_t n_slots, int nloc, int cp, uint8_t* colpos,
+                         int* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    const int64_t s = rs_slot[i];
+    const int64_t base = rowptr[elems2dofs[s]];
+    const int64_t e = s / nloc;
+    const int k = (int)(s - e * nloc);
+    uint8_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < nloc; ++l) {
+        const int64_t off = (int64_t)map[(e * nloc + k) * nloc + l] - base;
+        if (off < 0 || off > 255) atomicOr(err, ERR_OVERFLOW);
+        out[l] = (uint8_t)off;
+    }
+    for (int l = 0; l < cp; ++l) colpos[i * cp + l] = out[l];
+}
+
+__global__ void k_row_stats(const int64_t* rowptr, int64_t N, int* max_len, int* tile_pmax) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int64_t len = rowptr[r + 1] - rowptr[r];
+    atomicMax(max_len, (int)(len > 0x7fffffff ? 0x7fffffff : len));
+    const int R[3] = {64, 128, 256};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (r % R[q] == 0) {
+            const int64_t r1 = (r + R[q] < N) ? r + R[q] : N;
+            const int64_t nn = rowptr[r1] - rowptr[r];
+            atomicMax(&tile_pmax[q], (int)(nn > 0x7fffffff ? 0x7fffffff : nn));
+        }
+    }
+}
+
+fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
+    Pattern& p = ds.pat;
+    if (p.built) return FEM_OK;
+    const int64_t T = m->T;
+    const int nloc = ds.nloc;
+    const int64_t N = ds.n;
+    const int64_t n_slots = T * nloc;
+    const int64_t n_pairs = n_slots * nloc;
+    if (n_pairs >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_pattern: n_elems * n_local^2 must be below 2^31");
+    p.nloc = nloc;
+    p.cp_stride = nloc <= 4 ? 4 : 8;
+    p.n_rows = N;
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(n_pairs));
+    hipLaunchKernelGGL(k_pair_keys, dim3(nblk(n_pairs)), dim3(TB), 0, s, ds.elems2dofs, T, nloc, N,
+                       tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    const int bits = bit_length((uint64_t)N * (uint64_t)N - 1);
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_pairs, bits, s));
+    hipLaunchKernelGGL(k_flags, dim3(nblk(n_pairs)), dim3(TB), 0, s, tb.keys, n_pairs, tb.scan);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(tb.scan, n_pairs, s));
+    int64_t nnz = 0;
+    if (fem_status st = read_count(tb.scan, tb.keys, n_pairs, s, &nnz)) return st;
+    p.nnz = nnz;
+    FEM_HIP(dmalloc(m, &p.rowptr, N + 1));
+    FEM_HIP(dmalloc(m, &p.colind, nnz));
+    int32_t* map = nullptr;  // CSR position of every (element, k, l), temporary
+    FEM_HIP(hipMalloc((void**)&map, n_pairs * sizeof(int32_t)));
+    struct MapFree {
+        int32_t* p;
+        ~MapFree() { (void)hipFree(p); }
+    } map_free{map};
+    hipLaunchKernelGGL(k_pair_unique, dim3(nblk(n_pairs)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan,
+                       n_pairs, N, p.colind, p.rowptr, map);
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p.rowptr + N, nnz);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(dmalloc(m, &p.slot_rank, n_slots));
+    hipLaunchKernelGGL(k_slot_rank, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, n_slots, p.slot_rank);
+    FEM_HIP(dmalloc(m, &p.colpos, n_slots * p.cp_stride));
+    FEM_HIP(hipMemsetAsync(m->err_word, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_colpos, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, ds.elems2dofs, map,
+                       p.rowptr, n_slots, nloc, p.cp_stride, p.colpos, m->err_word);
+    FEM_HIP(hipGetLastError());
+    // row statistics (reuse the scan buffer as 4 ints)
+    int* stats = reinterpret_cast<int*>(tb.scan);
+    FEM_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(int), s));
+    hipLaunchKernelGGL(k_row_stats, dim3(nblk(N)), dim3(TB), 0, s, p.rowptr, N, stats, stats + 1);
+    FEM_HIP(hipGetLastError());
+    int host_stats[4];
+    int err = 0;
+    FEM_HIP(hipMemcpyAsync(host_stats, stats, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipMemcpyAsync(&err, m->err_word, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    p.max_row_len = host_stats[0];
+    for (int q = 0; q < 3; ++q) p.tile_pmax[q] = host_stats[1 + q];
+    if ((err & ERR_OVERFLOW) || p.max_row_len > 255)
+        return fail(FEM_EOVERFLOW, "fem_pattern: a row has more than 255 entries");
+    p.built = true;
+    return FEM_OK;
+}
+
+// ---------------------------------------------------------------- node map (backward)
+__global__ void k_node_keys(const int32_t* elems, int64_t n, uint64_t* keys, uint32_t* vals,
+                            int32_t* counts) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t v = elems[q];
+    keys[q] = (uint32_t)v;
+    vals[q] = (uint32_t)q;
+    atomicAdd(&counts[v], 1);
+}
+
+fem_status build_node_map(fem_mesh m, hipStream_t s) {
+    if (m->node_ptr) return FEM_OK;
+    const int64_t n = m->T * (m->dim + 1);
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(n));
+    FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
+    FEM_HIP(dmalloc(m, &m->node_slot, n));
+    FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_node_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, tb.keys, tb.vals,
+                       m->node_ptr);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->node_ptr), m->V + 1, s));
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n,
+                             bit_length((uint64_t)m->V - 1), s));
+    FEM_HIP(hipMemcpyAsync(m->node_slot, tb.vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+}  // namespace fem

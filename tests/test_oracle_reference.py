@@ -22,9 +22,12 @@ from oracle.assembly import local_matrices_from_B
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_quadrature_exact_on_monomials(dim):
-    x, w = R.quadrature(dim, 4)
-    deg = 6 if dim == 2 else 5
+@pytest.mark.parametrize("m", [3, 4])
+def test_quadrature_exact_on_monomials(dim, m):
+    """The m-point conical rule is exact to total degree 2m - dim (3 points per
+    direction, the oracle's rule: degree 4 in 2D, 3 in 3D)."""
+    x, w = R.quadrature(dim, m)
+    deg = 2 * m - dim
     assert abs(w.sum() - R.REF_VOLUME[dim]) < 1e-15
     for exps in product(range(deg + 1), repeat=dim):
         if sum(exps) > deg:
@@ -32,6 +35,10 @@ def test_quadrature_exact_on_monomials(dim):
         exact = math.prod(math.factorial(e) for e in exps) / math.factorial(sum(exps) + dim)
         val = np.sum(w * np.prod(x ** np.array(exps), axis=1))
         assert abs(val - exact) < 1e-15, (exps, val, exact)
+    # and not exact one degree higher (the rule is the one described)
+    exps = (deg + 1,) + (0,) * (dim - 1)
+    exact = math.factorial(deg + 1) / math.factorial(deg + 1 + dim)
+    assert abs(np.sum(w * x[:, 0] ** (deg + 1)) - exact) > 1e-12
 
 
 def _line_integral(f, xs, xt, m=5):
