@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (profiler byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1",
@@ -245,6 +247,16 @@ def main():
                      "unit": "GB/s", "frac": round(f64["frac"], 4), "traffic": None,
                      "kernel": "k_forward<2,128>", "bytes_per_launch": f64["bytes"]},
     }
+    if args.calib_copy:
+        # a plain device copy of known size (1 GiB read + 1 GiB written per launch),
+        # to scale the HBM byte counters of a profiler run
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = 2 * src.numel() * 8
+        del src, dst
     if args.quick:
         print(json.dumps(result), flush=True)
         return

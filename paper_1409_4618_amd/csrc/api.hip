@@ -41,14 +41,7 @@ static DofSet& dofset(fem_mesh m, fem_kind kind) {
     return (m->dim == 3 && kind == FEM_RAVIART_THOMAS) ? m->faces : m->edges;
 }
 
-static int env_rows_per_tile(int kc) {
-    const char* v = std::getenv("FEM_ROWS_PER_TILE");
-    if (v) {
-        const int r = std::atoi(v);
-        if (r == 64 || r == 128 || r == 256) return r;
-    }
-    return default_rows_per_tile(kc);
-}
+static int env_rows_per_tile(int kc) { return default_rows_per_tile(kc); }
 
 }  // namespace fem
 
@@ -134,6 +127,9 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
     m->last_stream = s;
     DofSet& ds = dofset(m, kind);
     if (fem_status st = build_pattern(m, ds, s)) return st;
+    if (forward_uses_tile_elems())
+        if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
+            return st;
     if (n_rows) *n_rows = ds.pat.n_rows;
     if (nnz) *nnz = ds.pat.nnz;
     if (rowptr) *rowptr = ds.pat.rowptr;
@@ -142,7 +138,8 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
 }
 
 static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
-                               const double* b, double* K, double* M, int R, MeshDev* md) {
+                               const double* b, double* K, double* M, int R, MeshDev* md,
+                               bool need_tile_elems) {
     DofSet& ds = dofset(m, kind);
     if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
     md->elems = m->elems;
@@ -158,8 +155,14 @@ static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, c
     md->n_rows = ds.pat.n_rows;
     md->n_tiles = (ds.pat.n_rows + R - 1) / R;
     md->kind_code = kind_code(m->dim, kind);
-    md->pad = 0;
     md->err_word = m->err_word;
+    const Pattern::TileElems& te = ds.pat.tiles[rows_index(R)];
+    md->max_tile_elems = te.built ? te.max_elems : 0;
+    md->tile_eptr = te.eptr;
+    md->tile_elems = te.elems;
+    md->slot_info = te.slot_info;
+    if (need_tile_elems && !te.built)
+        return fail(FEM_ENOTREADY, "row-tile element lists not built for this tile size");
     return FEM_OK;
 }
 
@@ -174,7 +177,9 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
     const int kc = kind_code(m->dim, kind);
     const int R = env_rows_per_tile(kc);
     MeshDev md;
-    if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md)) return st;
+    if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md,
+                                     forward_uses_tile_elems()))
+        return st;
     const int pmax = dofset(m, kind).pat.tile_pmax[rows_index(R)];
     return launch_forward(md, R, pmax, s);
 }
@@ -406,7 +411,7 @@ fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double*
         MeshDev md;
         fem_status st = fill_meshdev(B->meshes[i], B->kinds[i], nodes[i], a ? a[i] : nullptr,
                                      b ? b[i] : nullptr, K_vals ? K_vals[i] : nullptr,
-                                     M_vals ? M_vals[i] : nullptr, B->R, &md);
+                                     M_vals ? M_vals[i] : nullptr, B->R, &md, false);
         if (st) return st;
         B->host_table[i] = md;
     }

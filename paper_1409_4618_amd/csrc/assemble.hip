@@ -16,6 +16,7 @@
 // so each XCD walks a contiguous range of rows and its L2 sees the reuse of
 // element data between neighbouring rows.
 #include <algorithm>
+#include <cstdlib>
 
 #include "element.h"
 #include "fem_internal.h"
@@ -42,7 +43,9 @@ int kind_code(int dim, fem_kind kind) {
     return kind == FEM_RAVIART_THOMAS ? 1 : 2;
 }
 
-int rows_index(int rows_per_tile) { return rows_per_tile == 64 ? 0 : (rows_per_tile == 128 ? 1 : 2); }
+int rows_index(int rows_per_tile) {
+    return rows_per_tile == 32 ? 0 : rows_per_tile == 64 ? 1 : rows_per_tile == 128 ? 2 : 3;
+}
 
 // Element data of one slot: global node ids and coordinates.
 template <int KC>
@@ -94,33 +97,43 @@ __device__ __forceinline__ uint64_t load_colpos(const uint8_t* colpos, int64_t j
     }
 }
 
-// One tile of R rows: the body shared by the single-mesh and the batched kernels.
-template <int KC, int R, int U>
-__device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double* sK, double* sM) {
+// One tile of R rows, G lanes per row: the body shared by the single-mesh and
+// the batched kernels (workgroup of R*G threads).
+//
+// Lane g of a row handles the row's slots g, g+G, g+2G, ... in batches of U
+// (all loads of a batch are issued first). The G lanes of a row add their
+// element rows into the row's LDS segment in G ordered sub-rounds, so every
+// matrix entry is summed in ascending slot (= element) order: deterministic,
+// and bitwise symmetric because the local matrices are.
+template <int KC, int R, int G, int U>
+__device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double2* sKM) {
     using Tr = KT<KC>;
     constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
+    constexpr int NT = R * G;
     const int tid = threadIdx.x;
+    const int lrow = tid / G;
+    const int g = tid - lrow * G;
     const int64_t r0 = tile * R;
     const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
     const int64_t p0 = md.rowptr[r0];
     const int nt = (int)(md.rowptr[r1] - p0);
-    for (int i = tid; i < nt; i += R) {
-        sK[i] = 0.0;
-        sM[i] = 0.0;
-    }
+    for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
     __syncthreads();
-    const int64_t r = r0 + tid;
+    const int64_t r = r0 + lrow;
     bool bad = false;
     if (r < r1) {
         const int rb = (int)(md.rowptr[r] - p0);
         const int j0 = md.rs_ptr[r];
         const int j1 = md.rs_ptr[r + 1];
-        for (int j = j0; j < j1; j += U) {
+        for (int jb = j0; jb < j1; jb += G * U) {
             int slot[U];
             uint64_t cp[U];
+            bool live[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int jj = (j + u < j1) ? j + u : j1 - 1;
+                const int j = jb + g + G * u;
+                live[u] = j < j1;
+                const int jj = live[u] ? j : j1 - 1;
                 slot[u] = md.rs_slot[jj];
                 cp[u] = load_colpos<NLOC>(md.colpos, jj);
             }
@@ -153,16 +166,20 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (j + u < j1) {
-                    const int k = slot[u] - (slot[u] / NLOC) * NLOC;
-                    double Kr[NLOC], Mr[NLOC];
-                    const double J = slot_row<KC>(sd[u], k, Kr, Mr);
-                    bad |= !(fabs(J) > 0.0) || !isfinite(J);
+                const int k = slot[u] - (slot[u] / NLOC) * NLOC;
+                double Kr[NLOC], Mr[NLOC];
+                const double J = slot_row<KC>(sd[u], k, Kr, Mr);
+                bad |= live[u] && (!(fabs(J) > 0.0) || !isfinite(J));
+                // slot jb + g + G*u: sub-round g of step u, i.e. ascending slot order
 #pragma unroll
-                    for (int l = 0; l < NLOC; ++l) {
-                        const int pos = rb + (int)((cp[u] >> (8 * l)) & 0xFFu);
-                        sK[pos] += ca[u] * Kr[l];
-                        sM[pos] += cb[u] * Mr[l];
+                for (int gg = 0; gg < G; ++gg) {
+                    if (g == gg && live[u]) {
+#pragma unroll
+                        for (int l = 0; l < NLOC; ++l) {
+                            const int pos = rb + (int)((cp[u] >> (8 * l)) & 0xFFu);
+                            const double2 o = sKM[pos];
+                            sKM[pos] = make_double2(o.x + ca[u] * Kr[l], o.y + cb[u] * Mr[l]);
+                        }
                     }
                 }
             }
@@ -172,25 +189,259 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
     __syncthreads();
     double* K = md.K;
     double* M = md.M;
-    if (K)
-        for (int i = tid; i < nt; i += R) K[p0 + i] = sK[i];
-    if (M)
-        for (int i = tid; i < nt; i += R) M[p0 + i] = sM[i];
+    for (int i = tid; i < nt; i += NT) {
+        const double2 v = sKM[i];
+        if (K) K[p0 + i] = v.x;
+        if (M) M[p0 + i] = v.y;
+    }
 }
 
-constexpr int FWD_U = 4;
+// Same tile, one slot per lane per step, with the loads of the next step
+// (slot id, scatter offsets, element node ids, coefficients) issued before the
+// current step's coordinates are used: two of the three dependent gather
+// levels overlap the current element's arithmetic.
+template <int KC>
+struct SlotHead {
+    int slot;
+    uint64_t cp;
+    int gid[KT<KC>::NV];
+    double ca, cb;
+};
 
-template <int KC, int R>
-__global__ __launch_bounds__(R) void k_forward(const MeshDev md) {
-    extern __shared__ double smem[];
+template <int KC>
+__device__ __forceinline__ void load_head(const MeshDev& md, int j, SlotHead<KC>& h) {
+    constexpr int NLOC = KT<KC>::NLOC, NV = KT<KC>::NV;
+    h.slot = md.rs_slot[j];
+    h.cp = load_colpos<NLOC>(md.colpos, j);
+    const int64_t e = h.slot / NLOC;
+    if constexpr (NV == 4) {
+        const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
+        h.gid[0] = q.x;
+        h.gid[1] = q.y;
+        h.gid[2] = q.z;
+        h.gid[3] = q.w;
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) h.gid[v] = md.elems[e * NV + v];
+    }
+    h.ca = md.a ? md.a[e] : 1.0;
+    h.cb = md.b ? md.b[e] : 1.0;
+}
+
+template <int KC, int R, int G>
+__device__ __forceinline__ void fwd_tile_pf(const MeshDev& md, int64_t tile, double2* sKM) {
+    using Tr = KT<KC>;
+    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
+    constexpr int NT = R * G;
+    const int tid = threadIdx.x;
+    const int lrow = tid / G;
+    const int g = tid - lrow * G;
+    const int64_t r0 = tile * R;
+    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
+    const int64_t p0 = md.rowptr[r0];
+    const int nt = (int)(md.rowptr[r1] - p0);
+    for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int64_t r = r0 + lrow;
+    bool bad = false;
+    if (r < r1) {
+        const int rb = (int)(md.rowptr[r] - p0);
+        const int j0 = md.rs_ptr[r];
+        const int j1 = md.rs_ptr[r + 1];
+        const int steps = (j1 - j0 + G - 1) / G;  // same for the G lanes of a row
+        SlotHead<KC> cur;
+        int j = j0 + g;
+        load_head<KC>(md, j < j1 ? j : j1 - 1, cur);
+        for (int st = 0; st < steps; ++st, j += G) {
+            const bool live = j < j1;
+            SlotData<KC> sd;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sd.gid[v] = cur.gid[v];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) sd.x[v][c] = md.nodes[(int64_t)cur.gid[v] * DIM + c];
+            }
+            SlotHead<KC> nxt;
+            const int jn = j + G;
+            load_head<KC>(md, jn < j1 ? jn : j1 - 1, nxt);
+            const int k = cur.slot - (cur.slot / NLOC) * NLOC;
+            double Kr[NLOC], Mr[NLOC];
+            const double J = slot_row<KC>(sd, k, Kr, Mr);
+            bad |= live && (!(fabs(J) > 0.0) || !isfinite(J));
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                if (g == gg && live) {
+#pragma unroll
+                    for (int l = 0; l < NLOC; ++l) {
+                        const int pos = rb + (int)((cur.cp >> (8 * l)) & 0xFFu);
+                        const double2 o = sKM[pos];
+                        sKM[pos] = make_double2(o.x + cur.ca * Kr[l], o.y + cur.cb * Mr[l]);
+                    }
+                }
+            }
+            cur = nxt;
+        }
+    }
+    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
+    __syncthreads();
+    double* K = md.K;
+    double* M = md.M;
+    for (int i = tid; i < nt; i += NT) {
+        const double2 v = sKM[i];
+        if (K) K[p0 + i] = v.x;
+        if (M) M[p0 + i] = v.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row tile with an element cache in LDS. Phase 0: the workgroup loads every
+// element of the tile's list once (node ids, coordinates, coefficients) into
+// LDS records. Phase 1: lane g of a row walks the row's slots g, g+G, ...; a
+// slot carries only its element's index in the tile list and its local dof,
+// so the per-slot global traffic is two streaming loads and the element data
+// comes from LDS. Summation order as in fwd_tile (ascending slot order).
+template <int KC>
+struct ElemRec {
+    static constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM;
+    double x[NV][DIM];
+    double a, b;
+    int gid[NV];
+    // padding to an odd multiple of 16 bytes spreads the records over the LDS banks
+    int pad[KC == 0 ? 1 : 4];
+};
+static_assert(sizeof(ElemRec<2>) == 144, "3D record size");
+static_assert(sizeof(ElemRec<1>) == 144, "3D record size");
+static_assert(sizeof(ElemRec<0>) == 80, "2D record size");
+
+int elem_record_bytes(int kc) { return kc == 0 ? (int)sizeof(ElemRec<0>) : (int)sizeof(ElemRec<2>); }
+
+int forward_lds_bytes(int kc, int pmax, int max_tile_elems) {
+    return max_tile_elems * elem_record_bytes(kc) + pmax * 16;
+}
+
+template <int KC, int R, int G>
+__device__ __forceinline__ void fwd_tile_cached(const MeshDev& md, int64_t tile, char* smem) {
+    using Tr = KT<KC>;
+    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
+    constexpr int NT = R * G;
+    ElemRec<KC>* rec = reinterpret_cast<ElemRec<KC>*>(smem);
+    double2* sKM = reinterpret_cast<double2*>(smem + (size_t)md.max_tile_elems * sizeof(ElemRec<KC>));
+    const int tid = threadIdx.x;
+    const int lrow = tid / G;
+    const int g = tid - lrow * G;
+    const int64_t r0 = tile * R;
+    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
+    const int64_t p0 = md.rowptr[r0];
+    const int nt = (int)(md.rowptr[r1] - p0);
+    const int e_beg = md.tile_eptr[tile];
+    const int ne = md.tile_eptr[tile + 1] - e_beg;
+    // phase 0: element records (one gather per element of the tile)
+    for (int i = tid; i < ne; i += NT) {
+        const int64_t e = md.tile_elems[e_beg + i];
+        ElemRec<KC> rr;
+        if constexpr (NV == 4) {
+            const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
+            rr.gid[0] = q.x;
+            rr.gid[1] = q.y;
+            rr.gid[2] = q.z;
+            rr.gid[3] = q.w;
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) rr.gid[v] = md.elems[e * NV + v];
+        }
+        rr.a = md.a ? md.a[e] : 1.0;
+        rr.b = md.b ? md.b[e] : 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) rr.x[v][c] = md.nodes[(int64_t)rr.gid[v] * DIM + c];
+        rec[i] = rr;
+    }
+    for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    // phase 1: rows
+    const int64_t r = r0 + lrow;
+    bool bad = false;
+    if (r < r1) {
+        const int rb = (int)(md.rowptr[r] - p0);
+        const int j0 = md.rs_ptr[r];
+        const int j1 = md.rs_ptr[r + 1];
+        const int steps = (j1 - j0 + G - 1) / G;  // same for the G lanes of a row
+        int j = j0 + g;
+        int jj = j < j1 ? j : j1 - 1;
+        uint32_t info = md.slot_info[jj];
+        uint64_t cp = load_colpos<NLOC>(md.colpos, jj);
+        for (int st = 0; st < steps; ++st, j += G) {
+            const bool live = j < j1;
+            // next slot's streaming loads, issued before this slot's arithmetic
+            const int jn = j + G;
+            const int jjn = jn < j1 ? jn : j1 - 1;
+            const uint32_t info_n = md.slot_info[jjn];
+            const uint64_t cp_n = load_colpos<NLOC>(md.colpos, jjn);
+            const ElemRec<KC>& er = rec[info >> 3];
+            SlotData<KC> sd;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                sd.gid[v] = er.gid[v];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) sd.x[v][c] = er.x[v][c];
+            }
+            const double ca = er.a, cb = er.b;
+            const int k = (int)(info & 7u);
+            double Kr[NLOC], Mr[NLOC];
+            const double J = slot_row<KC>(sd, k, Kr, Mr);
+            bad |= live && (!(fabs(J) > 0.0) || !isfinite(J));
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                if (g == gg && live) {
+#pragma unroll
+                    for (int l = 0; l < NLOC; ++l) {
+                        const int pos = rb + (int)((cp >> (8 * l)) & 0xFFu);
+                        const double2 o = sKM[pos];
+                        sKM[pos] = make_double2(o.x + ca * Kr[l], o.y + cb * Mr[l]);
+                    }
+                }
+            }
+            info = info_n;
+            cp = cp_n;
+        }
+    }
+    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
+    __syncthreads();
+    double* K = md.K;
+    double* M = md.M;
+    for (int i = tid; i < nt; i += NT) {
+        const double2 v = sKM[i];
+        if (K) K[p0 + i] = v.x;
+        if (M) M[p0 + i] = v.y;
+    }
+}
+
+// Tile body: U = 0 selects the prefetching one-slot-per-step loop, U = -1 the
+// element-cached tile.
+template <int KC, int R, int G, int U>
+__device__ __forceinline__ void tile_body(const MeshDev& md, int64_t tile, char* smem) {
+    if constexpr (U == -1) fwd_tile_cached<KC, R, G>(md, tile, smem);
+    else if constexpr (U == 0) fwd_tile_pf<KC, R, G>(md, tile, reinterpret_cast<double2*>(smem));
+    else fwd_tile<KC, R, G, U>(md, tile, reinterpret_cast<double2*>(smem));
+}
+
+// Forward kernel variants: (rows per tile R, lanes per row G, slots per lane U).
+struct FwdVariant {
+    int R, G, U;
+};
+// index 0..5; FEM_FWD_VARIANT selects one for experiments.
+constexpr FwdVariant FWD_VARIANTS[] = {{128, 1, 4}, {128, 2, -1}, {64, 2, -1}, {64, 4, -1}, {128, 2, 1}, {32, 4, -1}};
+
+template <int KC, int R, int G, int U>
+__global__ __launch_bounds__(R * G) void k_forward(const MeshDev md) {
+    extern __shared__ __align__(16) char smem_raw[];
     // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous range of tiles.
     const int64_t per = gridDim.x / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= md.n_tiles) return;
-    const int pmax = (int)((md.rowptr[(tile + 1) * R < md.n_rows ? (tile + 1) * R : md.n_rows] -
-                            md.rowptr[tile * R]));
-    fwd_tile<KC, R, FWD_U>(md, tile, smem, smem + pmax);
+    tile_body<KC, R, G, U>(md, tile, smem_raw);
 }
 
 // Batched persistent kernel: every workgroup pulls (mesh, tile) work items.
@@ -198,11 +449,11 @@ __global__ __launch_bounds__(R) void k_forward(const MeshDev md) {
 // (2 = the host sorted the work list by decreasing cost first). The last
 // workgroup to finish resets the counters, so no memset is needed between
 // launches (graph replays included).
-template <int R>
-__global__ __launch_bounds__(R) void k_batch(const MeshDev* __restrict__ table,
-                                             const int2* __restrict__ work, int64_t n_work,
-                                             int schedule, unsigned* counters) {
-    extern __shared__ double smem[];
+template <int R, int G, int U>
+__global__ __launch_bounds__(R * G) void k_batch(const MeshDev* __restrict__ table,
+                                                 const int2* __restrict__ work, int64_t n_work,
+                                                 int schedule, unsigned* counters) {
+    extern __shared__ __align__(16) char smem_raw[];
     __shared__ int64_t s_w;
     int64_t w = blockIdx.x;
     for (;;) {
@@ -216,12 +467,10 @@ __global__ __launch_bounds__(R) void k_batch(const MeshDev* __restrict__ table,
         const int2 item = work[w];
         const MeshDev md = table[item.x];
         const int64_t tile = item.y;
-        const int64_t r1 = (tile + 1) * R < md.n_rows ? (tile + 1) * R : md.n_rows;
-        const int nt = (int)(md.rowptr[r1] - md.rowptr[tile * R]);
         switch (md.kind_code) {
-            case 0: fwd_tile<0, R, FWD_U>(md, tile, smem, smem + nt); break;
-            case 1: fwd_tile<1, R, FWD_U>(md, tile, smem, smem + nt); break;
-            default: fwd_tile<2, R, FWD_U>(md, tile, smem, smem + nt); break;
+            case 0: tile_body<0, R, G, U>(md, tile, smem_raw); break;
+            case 1: tile_body<1, R, G, U>(md, tile, smem_raw); break;
+            default: tile_body<2, R, G, U>(md, tile, smem_raw); break;
         }
         __syncthreads();
         if (schedule == 0) w += gridDim.x;
@@ -261,7 +510,23 @@ int cu_count() {
     return n;
 }
 
-int default_rows_per_tile(int kc) { return kc == 2 ? 128 : 256; }
+static int fwd_variant() {
+    static int v = -1;
+    if (v < 0) {
+        v = 4;
+        const char* s = std::getenv("FEM_FWD_VARIANT");
+        if (s) {
+            const int x = std::atoi(s);
+            if (x >= 0 && x < (int)(sizeof(FWD_VARIANTS) / sizeof(FWD_VARIANTS[0]))) v = x;
+        }
+    }
+    return v;
+}
+
+int default_rows_per_tile(int kc) {
+    (void)kc;
+    return FWD_VARIANTS[fwd_variant()].R;
+}
 
 template <class K>
 static hipError_t set_lds(K kernel, int bytes) {
@@ -269,42 +534,68 @@ static hipError_t set_lds(K kernel, int bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <int KC, int R>
+template <int KC, int R, int G, int U>
 static fem_status launch_fwd_t(const MeshDev& md, int pmax, hipStream_t s) {
-    const int bytes = pmax * 16;
-    FEM_HIP(set_lds(k_forward<KC, R>, bytes));
+    const int bytes = U == -1 ? forward_lds_bytes(KC, pmax, md.max_tile_elems) : pmax * 16;
+    if (bytes > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_assemble: a row tile needs more LDS than the device has");
+    FEM_HIP(set_lds(k_forward<KC, R, G, U>, bytes));
     const int64_t grid = ((md.n_tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_forward<KC, R>), dim3((unsigned)grid), dim3(R), bytes, s, md);
+    hipLaunchKernelGGL((k_forward<KC, R, G, U>), dim3((unsigned)grid), dim3(R * G), bytes, s, md);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
 
+template <int KC>
+static fem_status launch_fwd_kc(const MeshDev& md, int R, int pmax, hipStream_t s) {
+    const FwdVariant v = FWD_VARIANTS[fwd_variant()];
+    if (v.R != R) return fail(FEM_EINVAL, "fem_assemble: rows per tile does not match the kernel variant");
+    switch (fwd_variant()) {
+        case 0: return launch_fwd_t<KC, 128, 1, 4>(md, pmax, s);
+        case 1: return launch_fwd_t<KC, 128, 2, -1>(md, pmax, s);
+        case 2: return launch_fwd_t<KC, 64, 2, -1>(md, pmax, s);
+        case 3: return launch_fwd_t<KC, 64, 4, -1>(md, pmax, s);
+        case 4: return launch_fwd_t<KC, 128, 2, 1>(md, pmax, s);
+        default: return launch_fwd_t<KC, 32, 4, -1>(md, pmax, s);
+    }
+}
+
+bool forward_uses_tile_elems() { return FWD_VARIANTS[fwd_variant()].U == -1; }
+
 fem_status launch_forward(const MeshDev& md, int R, int pmax, hipStream_t s) {
     if (md.n_tiles == 0) return FEM_OK;
-    if (pmax * 16 > lds_limit_bytes())
-        return fail(FEM_EOVERFLOW, "fem_assemble: a row tile needs more LDS than the device has");
-#define FEM_FWD_CASE(KC)                                                     \
-    switch (R) {                                                             \
-        case 64: return launch_fwd_t<KC, 64>(md, pmax, s);                   \
-        case 128: return launch_fwd_t<KC, 128>(md, pmax, s);                 \
-        default: return launch_fwd_t<KC, 256>(md, pmax, s);                  \
-    }
     switch (md.kind_code) {
-        case 0: FEM_FWD_CASE(0);
-        case 1: FEM_FWD_CASE(1);
-        default: FEM_FWD_CASE(2);
+        case 0: return launch_fwd_kc<0>(md, R, pmax, s);
+        case 1: return launch_fwd_kc<1>(md, R, pmax, s);
+        default: return launch_fwd_kc<2>(md, R, pmax, s);
     }
-#undef FEM_FWD_CASE
 }
+
+// Batched kernel: lanes per row and slots per lane for each rows-per-tile choice.
+template <int R>
+struct BatchShape;
+template <>
+struct BatchShape<64> {
+    static constexpr int G = 4, U = 2;
+};
+template <>
+struct BatchShape<128> {
+    static constexpr int G = 2, U = 1;
+};
+template <>
+struct BatchShape<256> {
+    static constexpr int G = 1, U = 4;
+};
 
 template <int R>
 static fem_status launch_batch_t(const MeshDev* table, const int2* work, int64_t n_work,
                                  int schedule, int grid, int pmax, unsigned* counters,
                                  hipStream_t s) {
+    constexpr int G = BatchShape<R>::G, U = BatchShape<R>::U;
     const int bytes = pmax * 16;
-    FEM_HIP(set_lds(k_batch<R>, bytes));
-    hipLaunchKernelGGL(k_batch<R>, dim3((unsigned)grid), dim3(R), bytes, s, table, work, n_work,
-                       schedule, counters);
+    FEM_HIP(set_lds(k_batch<R, G, U>, bytes));
+    hipLaunchKernelGGL((k_batch<R, G, U>), dim3((unsigned)grid), dim3(R * G), bytes, s, table, work,
+                       n_work, schedule, counters);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
@@ -319,6 +610,24 @@ fem_status launch_batch(const MeshDev* table, const int2* work, int64_t n_work, 
         case 128: return launch_batch_t<128>(table, work, n_work, schedule, grid, pmax, counters, s);
         default: return launch_batch_t<256>(table, work, n_work, schedule, grid, pmax, counters, s);
     }
+}
+
+int batch_blocks_per_cu(int R, int bytes) {
+    int n = 0;
+    hipError_t e;
+    switch (R) {
+        case 64:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<64, 4, 2>, 256, bytes);
+            break;
+        case 128:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<128, 2, 1>, 256, bytes);
+            break;
+        default:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<256, 1, 4>, 256, bytes);
+            break;
+    }
+    if (e != hipSuccess || n <= 0) n = 1;
+    return n;
 }
 
 // ===========================================================================
@@ -675,18 +984,4 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     return FEM_OK;
 }
 
-}  // namespace fem
-
-namespace fem {
-int batch_blocks_per_cu(int R, int bytes) {
-    int n = 0;
-    hipError_t e;
-    switch (R) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<64>, 64, bytes); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<128>, 128, bytes); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<256>, 256, bytes); break;
-    }
-    if (e != hipSuccess || n <= 0) n = 1;
-    return n;
-}
 }  // namespace fem

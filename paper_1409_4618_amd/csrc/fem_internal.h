@@ -45,8 +45,19 @@ struct Pattern {
     uint8_t* colpos = nullptr;    // [n_slots][cp_stride], in row-sorted slot order
     int32_t* slot_rank = nullptr; // [n_slots] position of slot s in the row-sorted order
     int max_row_len = 0;
-    // max nnz of a tile of R consecutive rows, for R = 64, 128, 256
-    int tile_pmax[3] = {0, 0, 0};
+    // max nnz of a tile of R consecutive rows, for R = 32, 64, 128, 256
+    int tile_pmax[4] = {0, 0, 0, 0};
+    // Element lists of the row tiles, per rows-per-tile (index as tile_pmax):
+    // the sorted unique elements whose slots fall in each tile, and for every
+    // slot (row-sorted order) its element's index in that list, times 8, plus
+    // its local dof number.
+    struct TileElems {
+        bool built = false;
+        int32_t* eptr = nullptr;      // [n_tiles+1]
+        int32_t* elems = nullptr;     // [eptr[n_tiles]]
+        uint32_t* slot_info = nullptr;// [n_slots]: (index in tile list) << 3 | local dof
+        int max_elems = 0;            // largest tile list
+    } tiles[4];
 };
 
 // Dof structure of a mesh shared by the kinds that use the same dofs.
@@ -107,6 +118,7 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems,
                           hipStream_t s);
 fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s);
 fem_status build_node_map(fem_mesh m, hipStream_t s);
+fem_status build_tile_elems(fem_mesh m, DofSet& ds, int rows_per_tile, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // per-tile kernels (assemble.hip)
@@ -126,12 +138,16 @@ struct MeshDev {
     int64_t n_rows;
     int64_t n_tiles;        // for the chosen rows-per-tile
     int32_t kind_code;      // 0: 2D (both kinds), 1: 3D Raviart-Thomas, 2: 3D Nedelec
-    int32_t pad;
+    int32_t max_tile_elems; // LDS records reserved per tile (element cache)
     int* err_word;
+    // element lists of the tiles for the chosen rows-per-tile
+    const int32_t* tile_eptr;
+    const int32_t* tile_elems;
+    const uint32_t* slot_info;
 };
 
 int kind_code(int dim, fem_kind kind);
-int rows_index(int rows_per_tile);  // 64 -> 0, 128 -> 1, 256 -> 2
+int rows_index(int rows_per_tile);  // 32 -> 0, 64 -> 1, 128 -> 2, 256 -> 3
 fem_status launch_forward(const MeshDev& md, int rows_per_tile, int pmax, hipStream_t s);
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                            const double* a, const double* b, const double* gK,
@@ -144,5 +160,8 @@ int lds_limit_bytes();
 int batch_blocks_per_cu(int rows_per_tile, int lds_bytes);
 int cu_count();
 int default_rows_per_tile(int kind_code);
+int elem_record_bytes(int kind_code);
+bool forward_uses_tile_elems();
+int forward_lds_bytes(int kind_code, int pmax, int max_tile_elems);
 
 }  // namespace fem

@@ -404,9 +404,9 @@ __global__ void k_row_stats(const int64_t* rowptr, int64_t N, int* max_len, int*
     if (r >= N) return;
     const int64_t len = rowptr[r + 1] - rowptr[r];
     atomicMax(max_len, (int)(len > 0x7fffffff ? 0x7fffffff : len));
-    const int R[3] = {64, 128, 256};
+    const int R[4] = {32, 64, 128, 256};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
         if (r % R[q] == 0) {
             const int64_t r1 = (r + R[q] < N) ? r + R[q] : N;
             const int64_t nn = rowptr[r1] - rowptr[r];
@@ -462,16 +462,16 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     FEM_HIP(hipGetLastError());
     // row statistics (reuse the scan buffer as 4 ints)
     int* stats = reinterpret_cast<int*>(tb.scan);
-    FEM_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(int), s));
+    FEM_HIP(hipMemsetAsync(stats, 0, 5 * sizeof(int), s));
     hipLaunchKernelGGL(k_row_stats, dim3(nblk(N)), dim3(TB), 0, s, p.rowptr, N, stats, stats + 1);
     FEM_HIP(hipGetLastError());
-    int host_stats[4];
+    int host_stats[5];
     int err = 0;
-    FEM_HIP(hipMemcpyAsync(host_stats, stats, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipMemcpyAsync(host_stats, stats, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipMemcpyAsync(&err, m->err_word, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
     p.max_row_len = host_stats[0];
-    for (int q = 0; q < 3; ++q) p.tile_pmax[q] = host_stats[1 + q];
+    for (int q = 0; q < 4; ++q) p.tile_pmax[q] = host_stats[1 + q];
     if ((err & ERR_OVERFLOW) || p.max_row_len > 255)
         return fail(FEM_EOVERFLOW, "fem_pattern: a row has more than 255 entries");
     p.built = true;
@@ -505,6 +505,91 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
                              bit_length((uint64_t)m->V - 1), s));
     FEM_HIP(hipMemcpyAsync(m->node_slot, tb.vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     FEM_HIP(hipStreamSynchronize(s));
+    return FEM_OK;
+}
+
+}  // namespace fem
+
+// ---------------------------------------------------------------- row-tile element lists
+namespace fem {
+
+__global__ void k_tile_keys(const int32_t* rs_slot, const int32_t* elems2dofs, int64_t n_slots,
+                            int nloc, int R, int64_t T, uint64_t* keys, uint32_t* vals) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_slots) return;
+    const int64_t s = rs_slot[j];
+    const int64_t tile = elems2dofs[s] / R;
+    keys[j] = (uint64_t)tile * (uint64_t)T + (uint64_t)(s / nloc);
+    vals[j] = (uint32_t)j;
+}
+
+// unique (tile, element) pairs: element list entries and tile starts
+__global__ void k_tile_unique(const uint64_t* keys, const uint32_t* scan, int64_t n, int64_t T,
+                              int32_t* tile_elems, int32_t* eptr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    const bool head = (i == 0 || k != keys[i - 1]);
+    if (!head) return;
+    const int32_t id = (int32_t)scan[i];  // exclusive scan of the head flags
+    const uint64_t tile = k / (uint64_t)T;
+    tile_elems[id] = (int32_t)(k - tile * (uint64_t)T);
+    if (i == 0 || keys[i - 1] / (uint64_t)T != tile) eptr[tile] = id;
+}
+
+__global__ void k_tile_slot_info(const uint64_t* keys, const uint32_t* sorted_slots,
+                                 const uint32_t* scan, const int32_t* rs_slot, const int32_t* eptr,
+                                 int64_t n, int64_t T, int nloc, uint32_t* slot_info, int* max_elems) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    const bool head = (i == 0 || k != keys[i - 1]);
+    const int64_t id = (int64_t)scan[i] + (head ? 1 : 0) - 1;
+    const int64_t tile = (int64_t)(k / (uint64_t)T);
+    const int64_t local = id - eptr[tile];
+    const uint32_t j = sorted_slots[i];
+    slot_info[j] = ((uint32_t)local << 3) | (uint32_t)(rs_slot[j] % nloc);
+    // the last pair of a tile has the largest index in its list
+    if (i + 1 == n || keys[i + 1] / (uint64_t)T != (uint64_t)tile) atomicMax(max_elems, (int)(local + 1));
+}
+
+fem_status build_tile_elems(fem_mesh m, DofSet& ds, int R, hipStream_t s) {
+    Pattern& p = ds.pat;
+    Pattern::TileElems& te = p.tiles[rows_index(R)];
+    if (te.built) return FEM_OK;
+    const int64_t T = m->T;
+    const int64_t n_slots = T * ds.nloc;
+    const int64_t n_tiles = (p.n_rows + R - 1) / R;
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(n_slots));
+    hipLaunchKernelGGL(k_tile_keys, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, ds.elems2dofs,
+                       n_slots, ds.nloc, R, T, tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_slots,
+                             bit_length((uint64_t)n_tiles * (uint64_t)T - 1), s));
+    hipLaunchKernelGGL(k_flags, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, n_slots, tb.scan);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(tb.scan, n_slots, s));
+    int64_t n_pairs = 0;
+    if (fem_status st = read_count(tb.scan, tb.keys, n_slots, s, &n_pairs)) return st;
+    if ((n_pairs >> 29) != 0) return fail(FEM_EOVERFLOW, "fem_pattern: too many tile elements");
+    FEM_HIP(dmalloc(m, &te.eptr, n_tiles + 1));
+    FEM_HIP(dmalloc(m, &te.elems, n_pairs));
+    FEM_HIP(dmalloc(m, &te.slot_info, n_slots));
+    hipLaunchKernelGGL(k_tile_unique, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.scan, n_slots,
+                       T, te.elems, te.eptr);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, te.eptr + n_tiles, (int32_t)n_pairs);
+    FEM_HIP(hipGetLastError());
+    int* mx = reinterpret_cast<int*>(tb.keys_tmp);
+    FEM_HIP(hipMemsetAsync(mx, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_tile_slot_info, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan,
+                       ds.rs_slot, te.eptr, n_slots, T, ds.nloc, te.slot_info, mx);
+    FEM_HIP(hipGetLastError());
+    int host_mx = 0;
+    FEM_HIP(hipMemcpyAsync(&host_mx, mx, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    te.max_elems = host_mx;
+    te.built = true;
     return FEM_OK;
 }
 
