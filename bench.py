@@ -245,7 +245,7 @@ def main():
                    "rows": s64["n_rows"]},
         "roofline": {"bound": "hbm", "achieved": round(f64["gbs"], 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(f64["frac"], 4), "traffic": None,
-                     "kernel": "k_forward<2,128>", "bytes_per_launch": f64["bytes"]},
+                     "kernel": "fem::k_forward_ema<2, 256>", "bytes_per_launch": f64["bytes"]},
     }
     if args.calib_copy:
         # a plain device copy of known size (1 GiB read + 1 GiB written per launch),

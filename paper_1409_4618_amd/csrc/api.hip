@@ -43,6 +43,28 @@ static DofSet& dofset(fem_mesh m, fem_kind kind) {
 
 static int env_rows_per_tile(int kc) { return default_rows_per_tile(kc); }
 
+// The element-major tile kernel is the forward path; FEM_FWD_PATH=rows selects
+// the row-lane kernels instead (kept for comparison measurements).
+static bool use_row_path() {
+    static int v = -1;
+    if (v < 0) {
+        const char* s = std::getenv("FEM_FWD_PATH");
+        v = (s && std::strcmp(s, "rows") == 0) ? 1 : 0;
+    }
+    return v == 1;
+}
+
+static void fill_ema(const DofSet& ds, int nt, MeshDev* md) {
+    const Pattern::Ema& E = ds.pat.ema[ema_index(nt)];
+    md->n_tiles = E.n_tiles;
+    md->tile_eptr = E.eptr;
+    md->tile_elems = E.elems;
+    md->ema_joff = E.joff;
+    md->ema_R = E.R;
+    md->ema_pmax = E.pmax;
+    md->ema_max_slots = E.max_slots;
+}
+
 }  // namespace fem
 
 using namespace fem;
@@ -127,9 +149,13 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
     m->last_stream = s;
     DofSet& ds = dofset(m, kind);
     if (fem_status st = build_pattern(m, ds, s)) return st;
-    if (forward_uses_tile_elems())
-        if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
-            return st;
+    if (use_row_path()) {
+        if (forward_uses_tile_elems())
+            if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
+                return st;
+    } else {
+        if (fem_status st = build_ema(m, ds, default_ema_threads(), s)) return st;
+    }
     if (n_rows) *n_rows = ds.pat.n_rows;
     if (nnz) *nnz = ds.pat.nnz;
     if (rowptr) *rowptr = ds.pat.rowptr;
@@ -175,6 +201,15 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
     const int kc = kind_code(m->dim, kind);
+    if (!use_row_path()) {
+        const int nt = default_ema_threads();
+        if (!dofset(m, kind).pat.ema[ema_index(nt)].built)
+            return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+        MeshDev md;
+        if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md, false)) return st;
+        fill_ema(dofset(m, kind), nt, &md);
+        return launch_forward_ema(md, nt, s);
+    }
     const int R = env_rows_per_tile(kc);
     MeshDev md;
     if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md,

@@ -38,6 +38,13 @@ struct KT<2> {  // 3D Nedelec
     static constexpr int DIM = 3, NLOC = 6, NV = 4;
 };
 
+// The output values are written once and never read back by the kernel:
+// streaming (non-temporal) stores keep them from evicting the gathered inputs
+// (node coordinates, element records, scatter map) from L2 and the MALL.
+__device__ __forceinline__ void store_stream(double* p, double v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 int kind_code(int dim, fem_kind kind) {
     if (dim == 2) return 0;
     return kind == FEM_RAVIART_THOMAS ? 1 : 2;
@@ -191,8 +198,8 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
     double* M = md.M;
     for (int i = tid; i < nt; i += NT) {
         const double2 v = sKM[i];
-        if (K) K[p0 + i] = v.x;
-        if (M) M[p0 + i] = v.y;
+        if (K) store_stream(K + p0 + i, v.x);
+        if (M) store_stream(M + p0 + i, v.y);
     }
 }
 
@@ -288,8 +295,8 @@ __device__ __forceinline__ void fwd_tile_pf(const MeshDev& md, int64_t tile, dou
     double* M = md.M;
     for (int i = tid; i < nt; i += NT) {
         const double2 v = sKM[i];
-        if (K) K[p0 + i] = v.x;
-        if (M) M[p0 + i] = v.y;
+        if (K) store_stream(K + p0 + i, v.x);
+        if (M) store_stream(M + p0 + i, v.y);
     }
 }
 
@@ -412,8 +419,8 @@ __device__ __forceinline__ void fwd_tile_cached(const MeshDev& md, int64_t tile,
     double* M = md.M;
     for (int i = tid; i < nt; i += NT) {
         const double2 v = sKM[i];
-        if (K) K[p0 + i] = v.x;
-        if (M) M[p0 + i] = v.y;
+        if (K) store_stream(K + p0 + i, v.x);
+        if (M) store_stream(M + p0 + i, v.y);
     }
 }
 
@@ -628,6 +635,208 @@ int batch_blocks_per_cu(int R, int bytes) {
     }
     if (e != hipSuccess || n <= 0) n = 1;
     return n;
+}
+
+// ===========================================================================
+// Element-major tile ("ema"): the production forward path.
+//
+// A tile is R consecutive CSR rows (a contiguous value range) and the sorted
+// list of the elements that have a local dof among those rows. One lane takes
+// one element: it gathers the element once, forms its full local K and M
+// (compile-time indices, each symmetric pair computed once) and adds the rows
+// that belong to the tile into the tile's LDS copy of the values:
+//   * off-diagonal entries with LDS fp64 atomic adds. In a conforming mesh an
+//     off-diagonal entry has at most two contributions (the elements sharing
+//     the face through both dofs), and x + y == y + x bitwise, so the result
+//     does not depend on the order of the atomics;
+//   * diagonal entries (up to the number of elements around an edge) into a
+//     per-slot buffer, summed afterwards by one lane per row in slot order.
+// The tile is then written to HBM once, coalesced.
+// ===========================================================================
+int ema_lds_bytes(int kc, int R, int pmax, int max_slots) {
+    const int sd = kc == 2 ? max_slots : 0;
+    return 16 * (pmax + sd) + 4 * (3 * R + 1) + 2 * max_slots + 16;
+}
+
+template <int KC>
+__device__ __forceinline__ double elem_full(const int gid[KT<KC>::NV],
+                                            const double x[KT<KC>::NV][KT<KC>::DIM],
+                                            double K[KT<KC>::NLOC][KT<KC>::NLOC],
+                                            double M[KT<KC>::NLOC][KT<KC>::NLOC]) {
+    if constexpr (KC == 2) {
+        V3 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
+        return ned3_full(v, gid, K, M);
+    } else if constexpr (KC == 1) {
+        V3 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
+        return rt3_full(v, gid, K, M);
+    } else {
+        V2 v[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] = {x[q][0], x[q][1]};
+        return tri_full(v, gid, K, M);
+    }
+}
+
+template <int KC, int NT>
+__device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* smem) {
+    using Tr = KT<KC>;
+    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
+    const int tid = threadIdx.x;
+    const int R = md.ema_R;
+    const int64_t r0 = tile * R;
+    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
+    const int nrows = (int)(r1 - r0);
+    const int64_t p0 = md.rowptr[r0];
+    const int nt = (int)(md.rowptr[r1] - p0);
+    const int js0 = md.rs_ptr[r0];
+    const int ns = md.rs_ptr[r1] - js0;
+    const int e_beg = md.tile_eptr[tile];
+    const int ne = md.tile_eptr[tile + 1] - e_beg;
+    // LDS layout
+    double2* out = reinterpret_cast<double2*>(smem);
+    double2* sdiag = out + md.ema_pmax;
+    int* rowbase = reinterpret_cast<int*>(sdiag + (KC == 2 ? md.ema_max_slots : 0));
+    int* rowslot = rowbase + R;
+    int* rowdiag = rowslot + R + 1;
+    uint16_t* slotrow = reinterpret_cast<uint16_t*>(rowdiag + R);
+    // phase 0: clear the values, row bases, slot -> row table
+    for (int i = tid; i < nt; i += NT) out[i] = make_double2(0.0, 0.0);
+    for (int lr = tid; lr < nrows; lr += NT) {
+        rowbase[lr] = (int)(md.rowptr[r0 + lr] - p0);
+        const int a = md.rs_ptr[r0 + lr] - js0;
+        const int b = md.rs_ptr[r0 + lr + 1] - js0;
+        rowslot[lr] = a;
+        for (int j = a; j < b; ++j) slotrow[j] = (uint16_t)lr;
+    }
+    if (tid == 0) rowslot[nrows] = ns;
+    __syncthreads();
+    // phase 1: one element per lane
+    bool bad = false;
+    for (int i = tid; i < ne; i += NT) {
+        const int64_t e = md.tile_elems[e_beg + i];
+        const uint4 jq = reinterpret_cast<const uint4*>(md.ema_joff)[e_beg + i];
+        const uint32_t jw[4] = {jq.x, jq.y, jq.z, jq.w};
+        int gid[NV];
+        if constexpr (NV == 4) {
+            const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
+            gid[0] = q.x;
+            gid[1] = q.y;
+            gid[2] = q.z;
+            gid[3] = q.w;
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gid[v] = md.elems[e * NV + v];
+        }
+        const double ca = md.a ? md.a[e] : 1.0;
+        const double cb = md.b ? md.b[e] : 1.0;
+        double x[NV][DIM];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) x[v][c] = md.nodes[(int64_t)gid[v] * DIM + c];
+        double K[NLOC][NLOC], M[NLOC][NLOC];
+        const double J = elem_full<KC>(gid, x, K, M);
+        bad |= !(fabs(J) > 0.0) || !isfinite(J);
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k) {
+            const uint32_t jk = (jw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+            if (jk != 0xFFFFu) {
+                const int lr = slotrow[jk];
+                const int rb = rowbase[lr];
+                const uint64_t cp = load_colpos<NLOC>(md.colpos, (int64_t)js0 + jk);
+                const int dk = (int)((cp >> (8 * k)) & 0xFFu);
+                if constexpr (KC == 2) {
+                    sdiag[jk] = make_double2(ca * K[k][k], cb * M[k][k]);
+                    rowdiag[lr] = dk;
+                } else {
+                    atomicAdd(&out[rb + dk].x, ca * K[k][k]);
+                    atomicAdd(&out[rb + dk].y, cb * M[k][k]);
+                }
+#pragma unroll
+                for (int l = 0; l < NLOC; ++l) {
+                    if (l == k) continue;
+                    const int pos = rb + (int)((cp >> (8 * l)) & 0xFFu);
+                    atomicAdd(&out[pos].x, ca * K[k][l]);
+                    atomicAdd(&out[pos].y, cb * M[k][l]);
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
+    __syncthreads();
+    // phase 2 (3D Nedelec): diagonal entries, summed in slot order
+    if constexpr (KC == 2) {
+        for (int lr = tid; lr < nrows; lr += NT) {
+            double2 acc = make_double2(0.0, 0.0);
+            const int j1 = rowslot[lr + 1];
+            for (int j = rowslot[lr]; j < j1; ++j) {
+                const double2 v = sdiag[j];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            out[rowbase[lr] + rowdiag[lr]] = acc;
+        }
+        __syncthreads();
+    }
+    // phase 3: write the tile once
+    double* Kv = md.K;
+    double* Mv = md.M;
+    for (int i = tid; i < nt; i += NT) {
+        const double2 v = out[i];
+        if (Kv) store_stream(Kv + p0 + i, v.x);
+        if (Mv) store_stream(Mv + p0 + i, v.y);
+    }
+}
+
+template <int KC, int NT>
+__global__ __launch_bounds__(NT) void k_forward_ema(const MeshDev md) {
+    extern __shared__ __align__(16) char smem_raw[];
+    const int64_t per = gridDim.x / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= md.n_tiles) return;
+    tile_ema<KC, NT>(md, tile, smem_raw);
+}
+
+int default_ema_threads() {
+    static int v = 0;
+    if (!v) {
+        v = 256;
+        const char* s = std::getenv("FEM_EMA_THREADS");
+        if (s && std::atoi(s) == 128) v = 128;
+    }
+    return v;
+}
+
+template <int KC, int NT>
+static fem_status launch_ema_t(const MeshDev& md, hipStream_t s) {
+    const int bytes = ema_lds_bytes(KC, md.ema_R, md.ema_pmax, md.ema_max_slots);
+    if (bytes > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_assemble: a row tile needs more LDS than the device has");
+    FEM_HIP(set_lds(k_forward_ema<KC, NT>, bytes));
+    const int64_t grid = ((md.n_tiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_forward_ema<KC, NT>), dim3((unsigned)grid), dim3(NT), bytes, s, md);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
+fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s) {
+    if (md.n_tiles == 0) return FEM_OK;
+    if (nt == 128) {
+        switch (md.kind_code) {
+            case 0: return launch_ema_t<0, 128>(md, s);
+            case 1: return launch_ema_t<1, 128>(md, s);
+            default: return launch_ema_t<2, 128>(md, s);
+        }
+    }
+    switch (md.kind_code) {
+        case 0: return launch_ema_t<0, 256>(md, s);
+        case 1: return launch_ema_t<1, 256>(md, s);
+        default: return launch_ema_t<2, 256>(md, s);
+    }
 }
 
 // ===========================================================================

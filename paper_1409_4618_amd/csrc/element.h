@@ -298,3 +298,94 @@ __device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k,
 }
 
 }  // namespace fem
+
+namespace fem {
+
+// ---------------------------------------------------------------------------
+// Full local matrices with compile-time indices (no per-lane selection). Each
+// symmetric pair is computed once and stored in both (k,l) and (l,k), so the
+// local matrices are exactly symmetric. Returns J.
+__device__ __forceinline__ double ned3_full(const V3 x[4], const int gid[4], double K[6][6],
+                                            double M[6][6]) {
+    const Geo3 g = geo3(x);
+    V3 o[6];
+    ned3_o(g, o);
+    double s[6];
+    ned3_signs(gid, s);
+    const double inv = 1.0 / fabs(g.J);
+    const double kf = (2.0 / 3.0) * inv;
+    const double mf = (1.0 / 120.0) * inv;
+    double G[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) G[a][b] = G[b][a] = dot(g.c[a], g.c[b]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = nib(NED3_START, k), j = nib(NED3_END, k);
+#pragma unroll
+        for (int l = k; l < 6; ++l) {
+            const int m = nib(NED3_START, l), n = nib(NED3_END, l);
+            const double ss = s[k] * s[l];
+            K[k][l] = K[l][k] = kf * ss * dot(o[k], o[l]);
+            const double t = whitney_term(G[j][n] * (1.0 + (i == m)), G[i][m] * (1.0 + (j == n)),
+                                          G[j][m] * (1.0 + (i == n)), G[i][n] * (1.0 + (j == m)));
+            M[k][l] = M[l][k] = mf * ss * t;
+        }
+    }
+    return g.J;
+}
+
+__device__ __forceinline__ double rt3_full(const V3 x[4], const int gid[4], double K[4][4],
+                                           double M[4][4]) {
+    const GeoRT3 g = geo_rt3(x);
+    double s[4];
+    rt3_signs(gid, s);
+    const double inv = 1.0 / fabs(g.J);
+    const double kf = 1.5 * inv;
+    const double mf = (1.0 / 120.0) * inv;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pk = 3 - k;
+#pragma unroll
+        for (int l = k; l < 4; ++l) {
+            const int pl = 3 - l;
+            const double ss = s[k] * s[l];
+            K[k][l] = K[l][k] = kf * ss;
+            const double t = g.base - 5.0 * (g.u[pk] + g.u[pl]) + 20.0 * dot(g.y[pk], g.y[pl]);
+            M[k][l] = M[l][k] = mf * ss * t;
+        }
+    }
+    return g.J;
+}
+
+__device__ __forceinline__ double tri_full(const V2 x[3], const int gid[3], double K[3][3],
+                                           double M[3][3]) {
+    const Geo2 g = geo2(x);
+    double s[3];
+    tri_signs(gid, s);
+    const double inv = 1.0 / fabs(g.J);
+    const double kf = 2.0 * inv;
+    const double mf = (1.0 / 24.0) * inv;
+    double G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) G[a][b] = G[b][a] = dot2(g.c[a], g.c[b]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = nib(TRI_START, k), j = nib(TRI_END, k);
+#pragma unroll
+        for (int l = k; l < 3; ++l) {
+            const int m = nib(TRI_START, l), n = nib(TRI_END, l);
+            const double ss = s[k] * s[l];
+            K[k][l] = K[l][k] = kf * ss;
+            const double t = whitney_term(G[j][n] * (1.0 + (i == m)), G[i][m] * (1.0 + (j == n)),
+                                          G[j][m] * (1.0 + (i == n)), G[i][n] * (1.0 + (j == m)));
+            M[k][l] = M[l][k] = mf * ss * t;
+        }
+    }
+    return g.J;
+}
+
+}  // namespace fem

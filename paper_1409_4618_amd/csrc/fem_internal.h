@@ -58,6 +58,22 @@ struct Pattern {
         uint32_t* slot_info = nullptr;// [n_slots]: (index in tile list) << 3 | local dof
         int max_elems = 0;            // largest tile list
     } tiles[4];
+    // Element-major tiles (one per workgroup size NT = 128, 256): R consecutive
+    // rows per tile with R chosen so a tile's element list fits NT lanes; per
+    // tile element entry, the tile-local slot index of each local dof whose row
+    // is in the tile (0xFFFF otherwise).
+    struct Ema {
+        bool built = false;
+        int NT = 0;
+        int R = 0;
+        int64_t n_tiles = 0;
+        int32_t* eptr = nullptr;    // [n_tiles+1]
+        int32_t* elems = nullptr;   // [n_entries]
+        uint16_t* joff = nullptr;   // [n_entries][8]
+        int max_elems = 0;          // largest tile element list
+        int max_slots = 0;          // most slots of one tile
+        int pmax = 0;               // most matrix entries of one tile
+    } ema[2];
 };
 
 // Dof structure of a mesh shared by the kinds that use the same dofs.
@@ -119,6 +135,10 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems,
 fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s);
 fem_status build_node_map(fem_mesh m, hipStream_t s);
 fem_status build_tile_elems(fem_mesh m, DofSet& ds, int rows_per_tile, hipStream_t s);
+fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s);
+int ema_index(int nt);  // 128 -> 0, 256 -> 1
+int ema_lds_bytes(int kind_code, int R, int pmax, int max_slots);
+int default_ema_threads();
 
 // ---------------------------------------------------------------------------
 // per-tile kernels (assemble.hip)
@@ -144,6 +164,12 @@ struct MeshDev {
     const int32_t* tile_eptr;
     const int32_t* tile_elems;
     const uint32_t* slot_info;
+    // element-major tiles
+    const uint16_t* ema_joff;
+    int32_t ema_R;
+    int32_t ema_pmax;
+    int32_t ema_max_slots;
+    int32_t ema_pad;
 };
 
 int kind_code(int dim, fem_kind kind);
@@ -161,6 +187,7 @@ int batch_blocks_per_cu(int rows_per_tile, int lds_bytes);
 int cu_count();
 int default_rows_per_tile(int kind_code);
 int elem_record_bytes(int kind_code);
+fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s);
 bool forward_uses_tile_elems();
 int forward_lds_bytes(int kind_code, int pmax, int max_tile_elems);
 

@@ -594,3 +594,142 @@ fem_status build_tile_elems(fem_mesh m, DofSet& ds, int R, hipStream_t s) {
 }
 
 }  // namespace fem
+
+// ---------------------------------------------------------------- element-major tiles
+namespace fem {
+
+int ema_index(int nt) { return nt <= 128 ? 0 : 1; }
+
+// For each sorted (tile, element) pair: the tile-local slot index of the slot.
+__global__ void k_ema_joff(const uint64_t* keys, const uint32_t* sorted_slots, const uint32_t* scan,
+                           const int32_t* rs_slot, const int32_t* rs_ptr, const int32_t* eptr,
+                           int64_t n, int64_t T, int nloc, int R, uint16_t* joff, int* max_elems,
+                           int* overflow) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    const bool head = (i == 0 || k != keys[i - 1]);
+    const int64_t id = (int64_t)scan[i] + (head ? 1 : 0) - 1;
+    const int64_t tile = (int64_t)(k / (uint64_t)T);
+    const uint32_t j = sorted_slots[i];
+    const int64_t rel = (int64_t)j - rs_ptr[tile * R];
+    if (rel < 0 || rel >= 0xFFFF) atomicOr(overflow, 1);
+    joff[id * 8 + rs_slot[j] % nloc] = (uint16_t)rel;
+    if (i + 1 == n || keys[i + 1] / (uint64_t)T != (uint64_t)tile)
+        atomicMax(max_elems, (int)(id - eptr[tile] + 1));
+}
+
+__global__ void k_ema_stats(const int64_t* rowptr, const int32_t* rs_ptr, int64_t N, int R,
+                            int64_t n_tiles, int* pmax, int* max_slots) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t r0 = t * R;
+    const int64_t r1 = (r0 + R < N) ? r0 + R : N;
+    atomicMax(pmax, (int)(rowptr[r1] - rowptr[r0]));
+    atomicMax(max_slots, rs_ptr[r1] - rs_ptr[r0]);
+}
+
+__global__ void k_fill_u16(uint16_t* p, int64_t n, uint16_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// One attempt at tiles of R rows; allocations are plain (freed by the caller
+// unless adopted into the mesh).
+static fem_status ema_attempt(fem_mesh m, DofSet& ds, int R, hipStream_t s, Pattern::Ema& out) {
+    const int64_t T = m->T;
+    const int64_t n_slots = T * ds.nloc;
+    const int64_t n_tiles = (ds.pat.n_rows + R - 1) / R;
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(n_slots));
+    hipLaunchKernelGGL(k_tile_keys, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, ds.elems2dofs,
+                       n_slots, ds.nloc, R, T, tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_slots,
+                             bit_length((uint64_t)n_tiles * (uint64_t)T - 1), s));
+    hipLaunchKernelGGL(k_flags, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, n_slots, tb.scan);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(tb.scan, n_slots, s));
+    int64_t n_ent = 0;
+    if (fem_status st = read_count(tb.scan, tb.keys, n_slots, s, &n_ent)) return st;
+    out.R = R;
+    out.n_tiles = n_tiles;
+    FEM_HIP(hipMalloc((void**)&out.eptr, (n_tiles + 1) * sizeof(int32_t)));
+    FEM_HIP(hipMalloc((void**)&out.elems, n_ent * sizeof(int32_t)));
+    FEM_HIP(hipMalloc((void**)&out.joff, n_ent * 8 * sizeof(uint16_t)));
+    hipLaunchKernelGGL(k_tile_unique, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.scan, n_slots,
+                       T, out.elems, out.eptr);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, out.eptr + n_tiles, (int32_t)n_ent);
+    hipLaunchKernelGGL(k_fill_u16, dim3(nblk(n_ent * 8)), dim3(TB), 0, s, out.joff, n_ent * 8,
+                       (uint16_t)0xFFFF);
+    FEM_HIP(hipGetLastError());
+    int* stats = reinterpret_cast<int*>(tb.keys_tmp);  // [4]: max_elems, overflow, pmax, max_slots
+    FEM_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(int), s));
+    hipLaunchKernelGGL(k_ema_joff, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan,
+                       ds.rs_slot, ds.rs_ptr, out.eptr, n_slots, T, ds.nloc, R, out.joff, stats,
+                       stats + 1);
+    hipLaunchKernelGGL(k_ema_stats, dim3(nblk(n_tiles)), dim3(TB), 0, s, ds.pat.rowptr, ds.rs_ptr,
+                       ds.pat.n_rows, R, n_tiles, stats + 2, stats + 3);
+    FEM_HIP(hipGetLastError());
+    int h[4];
+    FEM_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    out.max_elems = h[0];
+    out.pmax = h[2];
+    out.max_slots = h[3];
+    if (h[1]) return fail(FEM_EOVERFLOW, "fem_pattern: a row tile has more than 65534 slots");
+    return FEM_OK;
+}
+
+static void ema_free(Pattern::Ema& e) {
+    if (e.eptr) (void)hipFree(e.eptr);
+    if (e.elems) (void)hipFree(e.elems);
+    if (e.joff) (void)hipFree(e.joff);
+    e.eptr = nullptr;
+    e.elems = nullptr;
+    e.joff = nullptr;
+}
+
+// Build the element-major tiles for workgroups of nt threads: pick the number of
+// rows per tile so that the largest tile element list fits in nt lanes (one
+// element per lane), within the LDS budget.
+fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
+    Pattern::Ema& E = ds.pat.ema[ema_index(nt)];
+    if (E.built) return FEM_OK;
+    const int kc = ds.nloc == 6 ? 2 : (ds.nloc == 4 ? 1 : 0);
+    // elements per row: about 2 (3D Nedelec), 0.9 (3D RT), 0.7 (2D)
+    int R = kc == 2 ? nt / 2 : nt;
+    if (R > 255) R = 255;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        Pattern::Ema cand;
+        fem_status st = ema_attempt(m, ds, R, s, cand);
+        if (st != FEM_OK) {
+            ema_free(cand);
+            return st;
+        }
+        const bool fits = cand.max_elems <= nt &&
+                          ema_lds_bytes(kc, R, cand.pmax, cand.max_slots) <= lds_limit_bytes() / 2;
+        if (fits || R <= 4 || attempt == 5) {
+            if (ema_lds_bytes(kc, R, cand.pmax, cand.max_slots) > lds_limit_bytes()) {
+                ema_free(cand);
+                return fail(FEM_EOVERFLOW, "fem_pattern: a row tile needs more LDS than the device has");
+            }
+            m->allocs.push_back(cand.eptr);
+            m->allocs.push_back(cand.elems);
+            m->allocs.push_back(cand.joff);
+            cand.NT = nt;
+            cand.built = true;
+            E = cand;
+            return FEM_OK;
+        }
+        // shrink the tile in proportion to the overshoot
+        const double f = cand.max_elems > nt ? (double)nt / cand.max_elems : 0.5;
+        int R2 = (int)(R * f * 0.97);
+        if (R2 >= R) R2 = R - 1;
+        R = R2 < 4 ? 4 : R2;
+        ema_free(cand);
+    }
+    return fail(FEM_EOVERFLOW, "fem_pattern: could not size the row tiles");
+}
+
+}  // namespace fem
