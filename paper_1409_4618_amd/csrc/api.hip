@@ -149,13 +149,16 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
     m->last_stream = s;
     DofSet& ds = dofset(m, kind);
     if (fem_status st = build_pattern(m, ds, s)) return st;
-    if (use_row_path()) {
-        if (forward_uses_tile_elems())
-            if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
-                return st;
-    } else {
+    bool rows = use_row_path();
+    if (!rows) {
         if (fem_status st = build_ema(m, ds, default_ema_threads(), s)) return st;
+        // a mesh with an edge or face shared by very many elements can leave a
+        // tile whose element list does not fit one workgroup: row path then
+        rows = !ds.pat.ema[ema_index(default_ema_threads())].usable;
     }
+    if (rows && forward_uses_tile_elems())
+        if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
+            return st;
     if (n_rows) *n_rows = ds.pat.n_rows;
     if (nnz) *nnz = ds.pat.nnz;
     if (rowptr) *rowptr = ds.pat.rowptr;
@@ -203,12 +206,15 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
     const int kc = kind_code(m->dim, kind);
     if (!use_row_path()) {
         const int nt = default_ema_threads();
-        if (!dofset(m, kind).pat.ema[ema_index(nt)].built)
-            return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
-        MeshDev md;
-        if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md, false)) return st;
-        fill_ema(dofset(m, kind), nt, &md);
-        return launch_forward_ema(md, nt, s);
+        const Pattern::Ema& E = dofset(m, kind).pat.ema[ema_index(nt)];
+        if (!E.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+        if (E.usable) {
+            MeshDev md;
+            if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md, false))
+                return st;
+            fill_ema(dofset(m, kind), nt, &md);
+            return launch_forward_ema(md, nt, s);
+        }
     }
     const int R = env_rows_per_tile(kc);
     MeshDev md;

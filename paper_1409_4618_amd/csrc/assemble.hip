@@ -17,6 +17,7 @@
 // element data between neighbouring rows.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "element.h"
 #include "fem_internal.h"
@@ -641,44 +642,137 @@ int batch_blocks_per_cu(int R, int bytes) {
 // Element-major tile ("ema"): the production forward path.
 //
 // A tile is R consecutive CSR rows (a contiguous value range) and the sorted
-// list of the elements that have a local dof among those rows. One lane takes
-// one element: it gathers the element once, forms its full local K and M
-// (compile-time indices, each symmetric pair computed once) and adds the rows
-// that belong to the tile into the tile's LDS copy of the values:
+// list of the elements that have a local dof among those rows; the tile's
+// element list fits in one workgroup, one lane per element. A lane gathers its
+// element once and keeps the element's geometry in registers (Ned3Elem,
+// Rt3Elem, TriElem); the workgroup then makes two passes over an LDS copy of
+// the tile's values, one for K and one for M. In a pass every lane forms the
+// entries of the rows of its element that belong to the tile (compile-time
+// indices) and adds them into the LDS copy:
 //   * off-diagonal entries with LDS fp64 atomic adds. In a conforming mesh an
 //     off-diagonal entry has at most two contributions (the elements sharing
 //     the face through both dofs), and x + y == y + x bitwise, so the result
 //     does not depend on the order of the atomics;
-//   * diagonal entries (up to the number of elements around an edge) into a
-//     per-slot buffer, summed afterwards by one lane per row in slot order.
-// The tile is then written to HBM once, coalesced.
+//   * diagonal entries: with at most two contributions likewise (Raviart-
+//     Thomas, 2D); in 3D Nedelec (one contribution per element around the
+//     edge) into a per-slot buffer, summed by one lane per row in slot order.
+// The pass ends with the tile written to HBM once, coalesced, while the LDS
+// copy is cleared for the next pass; the stores of the K pass drain while the
+// M pass computes. One value array in LDS instead of interleaved K and M
+// halves the LDS of a tile, and the element state instead of full local
+// matrices keeps the register count low: both set how many workgroups share a
+// compute unit, which is what hides the gather latency.
 // ===========================================================================
 int ema_lds_bytes(int kc, int R, int pmax, int max_slots) {
     const int sd = kc == 2 ? max_slots : 0;
-    return 16 * (pmax + sd) + 4 * (3 * R + 1) + 2 * max_slots + 16;
+    return 8 * (pmax + sd) + 4 * (3 * R + 1) + 2 * max_slots + 16;
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 template <int KC>
-__device__ __forceinline__ double elem_full(const int gid[KT<KC>::NV],
-                                            const double x[KT<KC>::NV][KT<KC>::DIM],
-                                            double K[KT<KC>::NLOC][KT<KC>::NLOC],
-                                            double M[KT<KC>::NLOC][KT<KC>::NLOC]) {
-    if constexpr (KC == 2) {
-        V3 v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
-        return ned3_full(v, gid, K, M);
-    } else if constexpr (KC == 1) {
-        V3 v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
-        return rt3_full(v, gid, K, M);
-    } else {
+struct EmaElem;
+template <>
+struct EmaElem<0> {
+    using T = TriElem;
+};
+template <>
+struct EmaElem<1> {
+    using T = Rt3Elem;
+};
+template <>
+struct EmaElem<2> {
+    using T = Ned3Elem;
+};
+
+template <int KC>
+__device__ __forceinline__ typename EmaElem<KC>::T ema_elem(const int gid[KT<KC>::NV],
+                                                            const double x[KT<KC>::NV][KT<KC>::DIM]) {
+    if constexpr (KC == 0) {
         V2 v[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) v[q] = {x[q][0], x[q][1]};
-        return tri_full(v, gid, K, M);
+        return tri_elem(v, gid);
+    } else {
+        V3 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
+        if constexpr (KC == 1) return rt3_elem(v, gid);
+        else return ned3_elem(v, gid);
     }
+}
+
+// State of one pass: the element state, except for the 3D Nedelec mass pass
+// (the Gram matrix, formed when that pass starts).
+template <int KC, bool MASS>
+struct EmaPass {
+    using T = typename EmaElem<KC>::T;
+};
+template <>
+struct EmaPass<2, true> {
+    using T = Ned3Mass;
+};
+
+template <int KC, bool MASS>
+__device__ __forceinline__ typename EmaPass<KC, MASS>::T ema_pass_state(
+    const typename EmaElem<KC>::T& st) {
+    if constexpr (KC == 2 && MASS) return ned3_mass(st);
+    else return st;
+}
+
+template <int KC, bool MASS, int k, int l>
+__device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T& st) {
+    if constexpr (KC == 2) {
+        if constexpr (MASS) return ned3_M<k, l>(st);
+        else return ned3_K<k, l>(st);
+    } else if constexpr (KC == 1) {
+        if constexpr (MASS) return rt3_M<k, l>(st);
+        else return rt3_K<k, l>(st);
+    } else {
+        if constexpr (MASS) return tri_M<k, l>(st);
+        else return tri_K<k, l>(st);
+    }
+}
+
+__device__ __forceinline__ uint32_t ema_jk(const uint32_t jw[4], int k) {
+    return (jw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+}
+
+// One pass (K or M) of a lane's element: rows k that belong to the tile.
+template <int KC, bool MASS>
+__device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, double coef,
+                                            const uint32_t jw[4], const int rb[KT<KC>::NLOC],
+                                            const uint64_t cp[KT<KC>::NLOC], double* out,
+                                            double* sdiag) {
+    constexpr int NLOC = KT<KC>::NLOC;
+    static_for<0, NLOC>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const uint32_t jk = ema_jk(jw, k);
+        if (jk != 0xFFFFu) {
+            pin_state<MASS>(st);
+            const typename EmaPass<KC, MASS>::T& sk = st;
+            const int base = rb[k];
+            const uint64_t c = cp[k];
+            const double d = coef * ema_entry<KC, MASS, k, k>(sk);
+            if constexpr (KC == 2) {
+                sdiag[jk] = d;
+            } else {
+                atomicAdd(&out[base + (int)((c >> (8 * k)) & 0xFFu)], d);
+            }
+            static_for<0, NLOC>([&](auto ll) {
+                constexpr int l = decltype(ll)::value;
+                if constexpr (l != k)
+                    atomicAdd(&out[base + (int)((c >> (8 * l)) & 0xFFu)],
+                              coef * ema_entry<KC, MASS, k, l>(sk));
+            });
+        }
+    });
 }
 
 template <int KC, int NT>
@@ -695,32 +789,30 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     const int js0 = md.rs_ptr[r0];
     const int ns = md.rs_ptr[r1] - js0;
     const int e_beg = md.tile_eptr[tile];
-    const int ne = md.tile_eptr[tile + 1] - e_beg;
+    const int ne = md.tile_eptr[tile + 1] - e_beg;  // <= NT (checked when the tiles are built)
     // LDS layout
-    double2* out = reinterpret_cast<double2*>(smem);
-    double2* sdiag = out + md.ema_pmax;
+    double* out = reinterpret_cast<double*>(smem);
+    double* sdiag = out + md.ema_pmax;
     int* rowbase = reinterpret_cast<int*>(sdiag + (KC == 2 ? md.ema_max_slots : 0));
     int* rowslot = rowbase + R;
     int* rowdiag = rowslot + R + 1;
     uint16_t* slotrow = reinterpret_cast<uint16_t*>(rowdiag + R);
-    // phase 0: clear the values, row bases, slot -> row table
-    for (int i = tid; i < nt; i += NT) out[i] = make_double2(0.0, 0.0);
-    for (int lr = tid; lr < nrows; lr += NT) {
-        rowbase[lr] = (int)(md.rowptr[r0 + lr] - p0);
-        const int a = md.rs_ptr[r0 + lr] - js0;
-        const int b = md.rs_ptr[r0 + lr + 1] - js0;
-        rowslot[lr] = a;
-        for (int j = a; j < b; ++j) slotrow[j] = (uint16_t)lr;
-    }
-    if (tid == 0) rowslot[nrows] = ns;
-    __syncthreads();
-    // phase 1: one element per lane
-    bool bad = false;
-    for (int i = tid; i < ne; i += NT) {
-        const int64_t e = md.tile_elems[e_beg + i];
-        const uint4 jq = reinterpret_cast<const uint4*>(md.ema_joff)[e_beg + i];
-        const uint32_t jw[4] = {jq.x, jq.y, jq.z, jq.w};
-        int gid[NV];
+
+    // this lane's element: record and node ids first, so their latency
+    // overlaps the LDS set-up below
+    const bool have = tid < ne;
+    int64_t e = 0;
+    uint32_t jw[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    int gid[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gid[v] = 0;
+    if (have) {
+        e = md.tile_elems[e_beg + tid];
+        const uint4 jq = reinterpret_cast<const uint4*>(md.ema_joff)[e_beg + tid];
+        jw[0] = jq.x;
+        jw[1] = jq.y;
+        jw[2] = jq.z;
+        jw[3] = jq.w;
         if constexpr (NV == 4) {
             const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
             gid[0] = q.x;
@@ -731,65 +823,79 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
 #pragma unroll
             for (int v = 0; v < NV; ++v) gid[v] = md.elems[e * NV + v];
         }
-        const double ca = md.a ? md.a[e] : 1.0;
-        const double cb = md.b ? md.b[e] : 1.0;
+    }
+    // phase 0: clear the values, row bases, slot -> row table
+    for (int i = tid; i < nt; i += NT) out[i] = 0.0;
+    for (int lr = tid; lr < nrows; lr += NT) {
+        rowbase[lr] = (int)(md.rowptr[r0 + lr] - p0);
+        const int a = md.rs_ptr[r0 + lr] - js0;
+        const int b = md.rs_ptr[r0 + lr + 1] - js0;
+        rowslot[lr] = a;
+        for (int j = a; j < b; ++j) slotrow[j] = (uint16_t)lr;
+    }
+    if (tid == 0) rowslot[nrows] = ns;
+    __syncthreads();
+
+    // gather (coordinates, coefficients, scatter offsets), then the element state
+    typename EmaElem<KC>::T st;
+    double ca = 1.0, cb = 1.0;
+    int rb[NLOC];
+    uint64_t cp[NLOC];
+    bool bad = false;
+    if (have) {
         double x[NV][DIM];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) x[v][c] = md.nodes[(int64_t)gid[v] * DIM + c];
-        double K[NLOC][NLOC], M[NLOC][NLOC];
-        const double J = elem_full<KC>(gid, x, K, M);
-        bad |= !(fabs(J) > 0.0) || !isfinite(J);
+        if (md.a) ca = md.a[e];
+        if (md.b) cb = md.b[e];
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) {
-            const uint32_t jk = (jw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+            const uint32_t jk = ema_jk(jw, k);
+            rb[k] = 0;
+            cp[k] = 0;
             if (jk != 0xFFFFu) {
+                cp[k] = load_colpos<NLOC>(md.colpos, (int64_t)js0 + jk);
                 const int lr = slotrow[jk];
-                const int rb = rowbase[lr];
-                const uint64_t cp = load_colpos<NLOC>(md.colpos, (int64_t)js0 + jk);
-                const int dk = (int)((cp >> (8 * k)) & 0xFFu);
-                if constexpr (KC == 2) {
-                    sdiag[jk] = make_double2(ca * K[k][k], cb * M[k][k]);
-                    rowdiag[lr] = dk;
-                } else {
-                    atomicAdd(&out[rb + dk].x, ca * K[k][k]);
-                    atomicAdd(&out[rb + dk].y, cb * M[k][k]);
-                }
-#pragma unroll
-                for (int l = 0; l < NLOC; ++l) {
-                    if (l == k) continue;
-                    const int pos = rb + (int)((cp >> (8 * l)) & 0xFFu);
-                    atomicAdd(&out[pos].x, ca * K[k][l]);
-                    atomicAdd(&out[pos].y, cb * M[k][l]);
-                }
+                rb[k] = rowbase[lr];
+                if constexpr (KC == 2) rowdiag[lr] = (int)((cp[k] >> (8 * k)) & 0xFFu);
             }
         }
+        st = ema_elem<KC>(gid, x);
+        bad = !(fabs(st.J) > 0.0) || !isfinite(st.J);
     }
     if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
-    __syncthreads();
-    // phase 2 (3D Nedelec): diagonal entries, summed in slot order
-    if constexpr (KC == 2) {
-        for (int lr = tid; lr < nrows; lr += NT) {
-            double2 acc = make_double2(0.0, 0.0);
-            const int j1 = rowslot[lr + 1];
-            for (int j = rowslot[lr]; j < j1; ++j) {
-                const double2 v = sdiag[j];
-                acc.x += v.x;
-                acc.y += v.y;
+
+    // two passes: K (coefficient a), then M (coefficient b)
+    static_for<0, 2>([&](auto pp) {
+        constexpr bool MASS = decltype(pp)::value == 1;
+        double* dst = MASS ? md.M : md.K;
+        if (dst) {
+            if (have) {
+                typename EmaPass<KC, MASS>::T ps = ema_pass_state<KC, MASS>(st);
+                ema_scatter<KC, MASS>(ps, MASS ? cb : ca, jw, rb, cp, out, sdiag);
             }
-            out[rowbase[lr] + rowdiag[lr]] = acc;
+            __syncthreads();
+            if constexpr (KC == 2) {
+                // diagonal entries, summed in slot order
+                for (int lr = tid; lr < nrows; lr += NT) {
+                    double acc = 0.0;
+                    const int j1 = rowslot[lr + 1];
+                    for (int j = rowslot[lr]; j < j1; ++j) acc += sdiag[j];
+                    out[rowbase[lr] + rowdiag[lr]] = acc;
+                }
+                __syncthreads();
+            }
+            // write the tile once; clear the LDS copy for the next pass
+            for (int i = tid; i < nt; i += NT) {
+                const double v = out[i];
+                out[i] = 0.0;
+                store_stream(dst + p0 + i, v);
+            }
+            if (!MASS) __syncthreads();
         }
-        __syncthreads();
-    }
-    // phase 3: write the tile once
-    double* Kv = md.K;
-    double* Mv = md.M;
-    for (int i = tid; i < nt; i += NT) {
-        const double2 v = out[i];
-        if (Kv) store_stream(Kv + p0 + i, v.x);
-        if (Mv) store_stream(Mv + p0 + i, v.y);
-    }
+    });
 }
 
 template <int KC, int NT>

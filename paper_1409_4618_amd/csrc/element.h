@@ -389,3 +389,261 @@ __device__ __forceinline__ double tri_full(const V2 x[3], const int gid[3], doub
 }
 
 }  // namespace fem
+
+namespace fem {
+
+// ---------------------------------------------------------------------------
+// Element state for the element-major kernel: the geometric quantities the
+// rows of K and M are formed from, kept in registers while the kernel makes
+// one pass for K and one for M. Entries are produced one at a time with
+// compile-time (k, l), by the same expressions as the *_full and *_row
+// functions above, so every entry is bitwise the value those produce (and
+// (k, l), (l, k) are bitwise equal).
+__host__ __device__ constexpr int tri_index(int a, int b) {  // packed upper triangle of a 4x4
+    return a <= b ? a * 4 - a * (a + 1) / 2 + b : b * 4 - b * (b + 1) / 2 + a;
+}
+
+struct Ned3Elem {
+    V3 b1, b2, b3;  // x_j - x_0
+    double kf, mf;  // 2/(3|J|), 1/(120|J|)
+    double J;
+    uint32_t sbits;  // bit l set iff s_l = +1
+};
+
+// What the mass rows need: the Gram matrix of the cofactor vectors. It is
+// formed from b_1..b_3 only when the mass pass starts, so the registers of the
+// stiffness pass and of the mass pass are not live at the same time.
+struct Ned3Mass {
+    double G[10];  // G_ab = c_a . c_b, packed upper triangle
+    double mf;
+    uint32_t sbits;
+};
+
+__device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4]) {
+    Ned3Elem e;
+    e.b1 = sub(x[1], x[0]);
+    e.b2 = sub(x[2], x[0]);
+    e.b3 = sub(x[3], x[0]);
+    e.J = dot(e.b1, cross(e.b2, e.b3));
+    const double inv = 1.0 / fabs(e.J);
+    e.kf = (2.0 / 3.0) * inv;
+    e.mf = (1.0 / 120.0) * inv;
+    e.sbits = 0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+        e.sbits |= (gid[nib(NED3_START, l)] > gid[nib(NED3_END, l)] ? 1u : 0u) << l;
+    return e;
+}
+
+// Same cofactor vectors and Gram entries as geo3 / ned3_full.
+__device__ __forceinline__ Ned3Mass ned3_mass(const Ned3Elem& e) {
+    V3 c[4];
+    c[1] = cross(e.b2, e.b3);
+    c[2] = cross(e.b3, e.b1);
+    c[3] = cross(e.b1, e.b2);
+    c[0] = neg(add(add(c[1], c[2]), c[3]));
+    Ned3Mass m;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) m.G[tri_index(a, b)] = dot(c[a], c[b]);
+    m.mf = e.mf;
+    m.sbits = e.sbits;
+    return m;
+}
+
+__device__ __forceinline__ double sgn_bit(uint32_t bits, int l) {
+    return ((bits >> l) & 1u) ? 1.0 : -1.0;
+}
+
+template <int k>
+__device__ __forceinline__ V3 ned3_o_of(const Ned3Elem& e) {
+    if constexpr (k == 0) return sub(e.b3, e.b2);
+    else if constexpr (k == 1) return sub(e.b1, e.b3);
+    else if constexpr (k == 2) return sub(e.b2, e.b1);
+    else if constexpr (k == 3) return e.b3;
+    else if constexpr (k == 4) return e.b1;
+    else return e.b2;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double ned3_K(const Ned3Elem& e) {
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    return e.kf * ss * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
+}
+
+template <int k, int l>
+__device__ __forceinline__ double ned3_M(const Ned3Mass& e) {
+    constexpr int i = nib(NED3_START, k), j = nib(NED3_END, k);
+    constexpr int m = nib(NED3_START, l), n = nib(NED3_END, l);
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    const double t = whitney_term(e.G[tri_index(j, n)] * (1.0 + (i == m)),
+                                  e.G[tri_index(i, m)] * (1.0 + (j == n)),
+                                  e.G[tri_index(j, m)] * (1.0 + (i == n)),
+                                  e.G[tri_index(i, n)] * (1.0 + (j == m)));
+    return e.mf * ss * t;
+}
+
+struct Rt3Elem {
+    V3 y1, y2, y3;  // x_a - x_0
+    double base;    // |S|^2 + tr Y
+    double u1, u2, u3;
+    double kf, mf;  // 3/(2|J|), 1/(120|J|)
+    double J;
+    uint32_t sbits;
+};
+
+__device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4]) {
+    const GeoRT3 g = geo_rt3(x);
+    Rt3Elem e;
+    e.y1 = g.y[1];
+    e.y2 = g.y[2];
+    e.y3 = g.y[3];
+    e.base = g.base;
+    e.u1 = g.u[1];
+    e.u2 = g.u[2];
+    e.u3 = g.u[3];
+    const double inv = 1.0 / fabs(g.J);
+    e.kf = 1.5 * inv;
+    e.mf = (1.0 / 120.0) * inv;
+    e.J = g.J;
+    double s[4];
+    rt3_signs(gid, s);
+    e.sbits = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) e.sbits |= (s[l] > 0.0 ? 1u : 0u) << l;
+    return e;
+}
+
+template <int p>
+__device__ __forceinline__ V3 rt3_y(const Rt3Elem& e) {
+    if constexpr (p == 0) return {0.0, 0.0, 0.0};
+    else if constexpr (p == 1) return e.y1;
+    else if constexpr (p == 2) return e.y2;
+    else return e.y3;
+}
+template <int p>
+__device__ __forceinline__ double rt3_u(const Rt3Elem& e) {
+    if constexpr (p == 0) return 0.0;
+    else if constexpr (p == 1) return e.u1;
+    else if constexpr (p == 2) return e.u2;
+    else return e.u3;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double rt3_K(const Rt3Elem& e) {
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    return e.kf * ss;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double rt3_M(const Rt3Elem& e) {
+    constexpr int pk = 3 - k, pl = 3 - l;
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    const double t = e.base - 5.0 * (rt3_u<pk>(e) + rt3_u<pl>(e)) + 20.0 * dot(rt3_y<pk>(e), rt3_y<pl>(e));
+    return e.mf * ss * t;
+}
+
+struct TriElem {
+    double G[6];  // packed upper triangle of the 3x3 Gram (indices as tri_index on 4x4, a,b < 3)
+    double kf, mf;  // 2/|J|, 1/(24|J|)
+    double J;
+    uint32_t sbits;
+};
+
+__host__ __device__ constexpr int tri3_index(int a, int b) {
+    return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
+}
+
+__device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3]) {
+    const Geo2 g = geo2(x);
+    TriElem e;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) e.G[tri3_index(a, b)] = dot2(g.c[a], g.c[b]);
+    const double inv = 1.0 / fabs(g.J);
+    e.kf = 2.0 * inv;
+    e.mf = (1.0 / 24.0) * inv;
+    e.J = g.J;
+    e.sbits = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+        e.sbits |= (gid[nib(TRI_START, l)] > gid[nib(TRI_END, l)] ? 1u : 0u) << l;
+    return e;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double tri_K(const TriElem& e) {
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    return e.kf * ss;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double tri_M(const TriElem& e) {
+    constexpr int i = nib(TRI_START, k), j = nib(TRI_END, k);
+    constexpr int m = nib(TRI_START, l), n = nib(TRI_END, l);
+    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
+    const double t = whitney_term(e.G[tri3_index(j, n)] * (1.0 + (i == m)),
+                                  e.G[tri3_index(i, m)] * (1.0 + (j == n)),
+                                  e.G[tri3_index(j, m)] * (1.0 + (i == n)),
+                                  e.G[tri3_index(i, n)] * (1.0 + (j == m)));
+    return e.mf * ss * t;
+}
+
+}  // namespace fem
+
+namespace fem {
+
+// Re-materialisation barrier: a value passed through this is, to the compiler,
+// a new value in each place it is called. The element-major kernel pins its
+// element state at the top of each local row, so the compiler forms that row's
+// entries there instead of hoisting the entries shared by two rows (the same
+// (k, l) pair) above both rows and holding all of them in registers.
+__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(V3& v) {
+    pin(v.x);
+    pin(v.y);
+    pin(v.z);
+}
+
+template <bool MASS>
+__device__ __forceinline__ void pin_state(Ned3Elem& e) {
+    pin(e.b1);
+    pin(e.b2);
+    pin(e.b3);
+    pin(e.kf);
+}
+template <bool MASS>
+__device__ __forceinline__ void pin_state(Ned3Mass& e) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) pin(e.G[q]);
+    pin(e.mf);
+}
+template <bool MASS>
+__device__ __forceinline__ void pin_state(Rt3Elem& e) {
+    if constexpr (MASS) {
+        pin(e.y1);
+        pin(e.y2);
+        pin(e.y3);
+        pin(e.base);
+        pin(e.u1);
+        pin(e.u2);
+        pin(e.u3);
+        pin(e.mf);
+    } else {
+        pin(e.kf);
+    }
+}
+template <bool MASS>
+__device__ __forceinline__ void pin_state(TriElem& e) {
+    if constexpr (MASS) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pin(e.G[q]);
+        pin(e.mf);
+    } else {
+        pin(e.kf);
+    }
+}
+
+}  // namespace fem

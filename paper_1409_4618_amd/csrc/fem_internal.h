@@ -64,6 +64,7 @@ struct Pattern {
     // is in the tile (0xFFFF otherwise).
     struct Ema {
         bool built = false;
+        bool usable = false;        // every tile's element list fits in NT lanes
         int NT = 0;
         int R = 0;
         int64_t n_tiles = 0;

@@ -719,6 +719,7 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             m->allocs.push_back(cand.joff);
             cand.NT = nt;
             cand.built = true;
+            cand.usable = cand.max_elems <= nt;
             E = cand;
             return FEM_OK;
         }
