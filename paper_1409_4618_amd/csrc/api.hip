@@ -149,16 +149,11 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
     m->last_stream = s;
     DofSet& ds = dofset(m, kind);
     if (fem_status st = build_pattern(m, ds, s)) return st;
-    bool rows = use_row_path();
-    if (!rows) {
+    // (a mesh with an edge or face shared by very many elements can leave a
+    // tile whose element list does not fit one workgroup: the row kernel then
+    // takes the mesh, see fem_assemble)
+    if (!use_row_path())
         if (fem_status st = build_ema(m, ds, default_ema_threads(), s)) return st;
-        // a mesh with an edge or face shared by very many elements can leave a
-        // tile whose element list does not fit one workgroup: row path then
-        rows = !ds.pat.ema[ema_index(default_ema_threads())].usable;
-    }
-    if (rows && forward_uses_tile_elems())
-        if (fem_status st = build_tile_elems(m, ds, default_rows_per_tile(kind_code(m->dim, kind)), s))
-            return st;
     if (n_rows) *n_rows = ds.pat.n_rows;
     if (nnz) *nnz = ds.pat.nnz;
     if (rowptr) *rowptr = ds.pat.rowptr;
@@ -167,8 +162,7 @@ fem_status fem_pattern(fem_mesh m, fem_kind kind, void* stream, int64_t* n_rows,
 }
 
 static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
-                               const double* b, double* K, double* M, int R, MeshDev* md,
-                               bool need_tile_elems) {
+                               const double* b, double* K, double* M, int R, MeshDev* md) {
     DofSet& ds = dofset(m, kind);
     if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
     md->elems = m->elems;
@@ -185,13 +179,6 @@ static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, c
     md->n_tiles = (ds.pat.n_rows + R - 1) / R;
     md->kind_code = kind_code(m->dim, kind);
     md->err_word = m->err_word;
-    const Pattern::TileElems& te = ds.pat.tiles[rows_index(R)];
-    md->max_tile_elems = te.built ? te.max_elems : 0;
-    md->tile_eptr = te.eptr;
-    md->tile_elems = te.elems;
-    md->slot_info = te.slot_info;
-    if (need_tile_elems && !te.built)
-        return fail(FEM_ENOTREADY, "row-tile element lists not built for this tile size");
     return FEM_OK;
 }
 
@@ -210,7 +197,7 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
         if (!E.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
         if (E.usable) {
             MeshDev md;
-            if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md, false))
+            if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md))
                 return st;
             fill_ema(dofset(m, kind), nt, &md);
             return launch_forward_ema(md, nt, s);
@@ -218,9 +205,7 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
     }
     const int R = env_rows_per_tile(kc);
     MeshDev md;
-    if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md,
-                                     forward_uses_tile_elems()))
-        return st;
+    if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, R, &md)) return st;
     const int pmax = dofset(m, kind).pat.tile_pmax[rows_index(R)];
     return launch_forward(md, R, pmax, s);
 }
@@ -452,7 +437,7 @@ fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double*
         MeshDev md;
         fem_status st = fill_meshdev(B->meshes[i], B->kinds[i], nodes[i], a ? a[i] : nullptr,
                                      b ? b[i] : nullptr, K_vals ? K_vals[i] : nullptr,
-                                     M_vals ? M_vals[i] : nullptr, B->R, &md, false);
+                                     M_vals ? M_vals[i] : nullptr, B->R, &md);
         if (st) return st;
         B->host_table[i] = md;
     }

@@ -62,10 +62,11 @@ struct SlotData {
     double x[KT<KC>::NV][KT<KC>::DIM];
 };
 
-// Row k of the local K, M of an element (no coefficients), sign-adjusted.
-// Returns the Jacobian determinant (for the error check).
+// Row k of the element's a K and b M (sign-adjusted, canonical rounding of
+// element.h). Returns the Jacobian determinant (for the error check).
 template <int KC>
-__device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double* Kr, double* Mr) {
+__device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double ca, double cb,
+                                           double* Kr, double* Mr) {
     if constexpr (KC == 2) {
         V3 x[4];
 #pragma unroll
@@ -73,7 +74,7 @@ __device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double*
         const Geo3 g = geo3(x);
         double s[6];
         ned3_signs(d.gid, s);
-        ned3_row(g, s, k, Kr, Mr);
+        ned3_row(g, s, k, ca, cb, Kr, Mr);
         return g.J;
     } else if constexpr (KC == 1) {
         V3 x[4];
@@ -82,7 +83,7 @@ __device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double*
         const GeoRT3 g = geo_rt3(x);
         double s[4];
         rt3_signs(d.gid, s);
-        rt3_row(g, s, k, Kr, Mr);
+        rt3_row(g, s, k, ca, cb, Kr, Mr);
         return g.J;
     } else {
         V2 x[3];
@@ -91,7 +92,7 @@ __device__ __forceinline__ double slot_row(const SlotData<KC>& d, int k, double*
         const Geo2 g = geo2(x);
         double s[3];
         tri_signs(d.gid, s);
-        tri_row(g, s, k, Kr, Mr);
+        tri_row(g, s, k, ca, cb, Kr, Mr);
         return g.J;
     }
 }
@@ -176,7 +177,7 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
             for (int u = 0; u < U; ++u) {
                 const int k = slot[u] - (slot[u] / NLOC) * NLOC;
                 double Kr[NLOC], Mr[NLOC];
-                const double J = slot_row<KC>(sd[u], k, Kr, Mr);
+                const double J = slot_row<KC>(sd[u], k, ca[u], cb[u], Kr, Mr);
                 bad |= live[u] && (!(fabs(J) > 0.0) || !isfinite(J));
                 // slot jb + g + G*u: sub-round g of step u, i.e. ascending slot order
 #pragma unroll
@@ -186,7 +187,7 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
                         for (int l = 0; l < NLOC; ++l) {
                             const int pos = rb + (int)((cp[u] >> (8 * l)) & 0xFFu);
                             const double2 o = sKM[pos];
-                            sKM[pos] = make_double2(o.x + ca[u] * Kr[l], o.y + cb[u] * Mr[l]);
+                            sKM[pos] = make_double2(o.x + Kr[l], o.y + Mr[l]);
                         }
                     }
                 }
@@ -204,242 +205,9 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
     }
 }
 
-// Same tile, one slot per lane per step, with the loads of the next step
-// (slot id, scatter offsets, element node ids, coefficients) issued before the
-// current step's coordinates are used: two of the three dependent gather
-// levels overlap the current element's arithmetic.
-template <int KC>
-struct SlotHead {
-    int slot;
-    uint64_t cp;
-    int gid[KT<KC>::NV];
-    double ca, cb;
-};
-
-template <int KC>
-__device__ __forceinline__ void load_head(const MeshDev& md, int j, SlotHead<KC>& h) {
-    constexpr int NLOC = KT<KC>::NLOC, NV = KT<KC>::NV;
-    h.slot = md.rs_slot[j];
-    h.cp = load_colpos<NLOC>(md.colpos, j);
-    const int64_t e = h.slot / NLOC;
-    if constexpr (NV == 4) {
-        const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
-        h.gid[0] = q.x;
-        h.gid[1] = q.y;
-        h.gid[2] = q.z;
-        h.gid[3] = q.w;
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) h.gid[v] = md.elems[e * NV + v];
-    }
-    h.ca = md.a ? md.a[e] : 1.0;
-    h.cb = md.b ? md.b[e] : 1.0;
-}
-
-template <int KC, int R, int G>
-__device__ __forceinline__ void fwd_tile_pf(const MeshDev& md, int64_t tile, double2* sKM) {
-    using Tr = KT<KC>;
-    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
-    constexpr int NT = R * G;
-    const int tid = threadIdx.x;
-    const int lrow = tid / G;
-    const int g = tid - lrow * G;
-    const int64_t r0 = tile * R;
-    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
-    const int64_t p0 = md.rowptr[r0];
-    const int nt = (int)(md.rowptr[r1] - p0);
-    for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
-    __syncthreads();
-    const int64_t r = r0 + lrow;
-    bool bad = false;
-    if (r < r1) {
-        const int rb = (int)(md.rowptr[r] - p0);
-        const int j0 = md.rs_ptr[r];
-        const int j1 = md.rs_ptr[r + 1];
-        const int steps = (j1 - j0 + G - 1) / G;  // same for the G lanes of a row
-        SlotHead<KC> cur;
-        int j = j0 + g;
-        load_head<KC>(md, j < j1 ? j : j1 - 1, cur);
-        for (int st = 0; st < steps; ++st, j += G) {
-            const bool live = j < j1;
-            SlotData<KC> sd;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                sd.gid[v] = cur.gid[v];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) sd.x[v][c] = md.nodes[(int64_t)cur.gid[v] * DIM + c];
-            }
-            SlotHead<KC> nxt;
-            const int jn = j + G;
-            load_head<KC>(md, jn < j1 ? jn : j1 - 1, nxt);
-            const int k = cur.slot - (cur.slot / NLOC) * NLOC;
-            double Kr[NLOC], Mr[NLOC];
-            const double J = slot_row<KC>(sd, k, Kr, Mr);
-            bad |= live && (!(fabs(J) > 0.0) || !isfinite(J));
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                if (g == gg && live) {
-#pragma unroll
-                    for (int l = 0; l < NLOC; ++l) {
-                        const int pos = rb + (int)((cur.cp >> (8 * l)) & 0xFFu);
-                        const double2 o = sKM[pos];
-                        sKM[pos] = make_double2(o.x + cur.ca * Kr[l], o.y + cur.cb * Mr[l]);
-                    }
-                }
-            }
-            cur = nxt;
-        }
-    }
-    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
-    __syncthreads();
-    double* K = md.K;
-    double* M = md.M;
-    for (int i = tid; i < nt; i += NT) {
-        const double2 v = sKM[i];
-        if (K) store_stream(K + p0 + i, v.x);
-        if (M) store_stream(M + p0 + i, v.y);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Row tile with an element cache in LDS. Phase 0: the workgroup loads every
-// element of the tile's list once (node ids, coordinates, coefficients) into
-// LDS records. Phase 1: lane g of a row walks the row's slots g, g+G, ...; a
-// slot carries only its element's index in the tile list and its local dof,
-// so the per-slot global traffic is two streaming loads and the element data
-// comes from LDS. Summation order as in fwd_tile (ascending slot order).
-template <int KC>
-struct ElemRec {
-    static constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM;
-    double x[NV][DIM];
-    double a, b;
-    int gid[NV];
-    // padding to an odd multiple of 16 bytes spreads the records over the LDS banks
-    int pad[KC == 0 ? 1 : 4];
-};
-static_assert(sizeof(ElemRec<2>) == 144, "3D record size");
-static_assert(sizeof(ElemRec<1>) == 144, "3D record size");
-static_assert(sizeof(ElemRec<0>) == 80, "2D record size");
-
-int elem_record_bytes(int kc) { return kc == 0 ? (int)sizeof(ElemRec<0>) : (int)sizeof(ElemRec<2>); }
-
-int forward_lds_bytes(int kc, int pmax, int max_tile_elems) {
-    return max_tile_elems * elem_record_bytes(kc) + pmax * 16;
-}
-
-template <int KC, int R, int G>
-__device__ __forceinline__ void fwd_tile_cached(const MeshDev& md, int64_t tile, char* smem) {
-    using Tr = KT<KC>;
-    constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
-    constexpr int NT = R * G;
-    ElemRec<KC>* rec = reinterpret_cast<ElemRec<KC>*>(smem);
-    double2* sKM = reinterpret_cast<double2*>(smem + (size_t)md.max_tile_elems * sizeof(ElemRec<KC>));
-    const int tid = threadIdx.x;
-    const int lrow = tid / G;
-    const int g = tid - lrow * G;
-    const int64_t r0 = tile * R;
-    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
-    const int64_t p0 = md.rowptr[r0];
-    const int nt = (int)(md.rowptr[r1] - p0);
-    const int e_beg = md.tile_eptr[tile];
-    const int ne = md.tile_eptr[tile + 1] - e_beg;
-    // phase 0: element records (one gather per element of the tile)
-    for (int i = tid; i < ne; i += NT) {
-        const int64_t e = md.tile_elems[e_beg + i];
-        ElemRec<KC> rr;
-        if constexpr (NV == 4) {
-            const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
-            rr.gid[0] = q.x;
-            rr.gid[1] = q.y;
-            rr.gid[2] = q.z;
-            rr.gid[3] = q.w;
-        } else {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) rr.gid[v] = md.elems[e * NV + v];
-        }
-        rr.a = md.a ? md.a[e] : 1.0;
-        rr.b = md.b ? md.b[e] : 1.0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) rr.x[v][c] = md.nodes[(int64_t)rr.gid[v] * DIM + c];
-        rec[i] = rr;
-    }
-    for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
-    __syncthreads();
-    // phase 1: rows
-    const int64_t r = r0 + lrow;
-    bool bad = false;
-    if (r < r1) {
-        const int rb = (int)(md.rowptr[r] - p0);
-        const int j0 = md.rs_ptr[r];
-        const int j1 = md.rs_ptr[r + 1];
-        const int steps = (j1 - j0 + G - 1) / G;  // same for the G lanes of a row
-        int j = j0 + g;
-        int jj = j < j1 ? j : j1 - 1;
-        uint32_t info = md.slot_info[jj];
-        uint64_t cp = load_colpos<NLOC>(md.colpos, jj);
-        for (int st = 0; st < steps; ++st, j += G) {
-            const bool live = j < j1;
-            // next slot's streaming loads, issued before this slot's arithmetic
-            const int jn = j + G;
-            const int jjn = jn < j1 ? jn : j1 - 1;
-            const uint32_t info_n = md.slot_info[jjn];
-            const uint64_t cp_n = load_colpos<NLOC>(md.colpos, jjn);
-            const ElemRec<KC>& er = rec[info >> 3];
-            SlotData<KC> sd;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                sd.gid[v] = er.gid[v];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) sd.x[v][c] = er.x[v][c];
-            }
-            const double ca = er.a, cb = er.b;
-            const int k = (int)(info & 7u);
-            double Kr[NLOC], Mr[NLOC];
-            const double J = slot_row<KC>(sd, k, Kr, Mr);
-            bad |= live && (!(fabs(J) > 0.0) || !isfinite(J));
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                if (g == gg && live) {
-#pragma unroll
-                    for (int l = 0; l < NLOC; ++l) {
-                        const int pos = rb + (int)((cp >> (8 * l)) & 0xFFu);
-                        const double2 o = sKM[pos];
-                        sKM[pos] = make_double2(o.x + ca * Kr[l], o.y + cb * Mr[l]);
-                    }
-                }
-            }
-            info = info_n;
-            cp = cp_n;
-        }
-    }
-    if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
-    __syncthreads();
-    double* K = md.K;
-    double* M = md.M;
-    for (int i = tid; i < nt; i += NT) {
-        const double2 v = sKM[i];
-        if (K) store_stream(K + p0 + i, v.x);
-        if (M) store_stream(M + p0 + i, v.y);
-    }
-}
-
-// Tile body: U = 0 selects the prefetching one-slot-per-step loop, U = -1 the
-// element-cached tile.
-template <int KC, int R, int G, int U>
-__device__ __forceinline__ void tile_body(const MeshDev& md, int64_t tile, char* smem) {
-    if constexpr (U == -1) fwd_tile_cached<KC, R, G>(md, tile, smem);
-    else if constexpr (U == 0) fwd_tile_pf<KC, R, G>(md, tile, reinterpret_cast<double2*>(smem));
-    else fwd_tile<KC, R, G, U>(md, tile, reinterpret_cast<double2*>(smem));
-}
-
-// Forward kernel variants: (rows per tile R, lanes per row G, slots per lane U).
-struct FwdVariant {
-    int R, G, U;
-};
-// index 0..5; FEM_FWD_VARIANT selects one for experiments.
-constexpr FwdVariant FWD_VARIANTS[] = {{128, 1, 4}, {128, 2, -1}, {64, 2, -1}, {64, 4, -1}, {128, 2, 1}, {32, 4, -1}};
+// Row kernel of the single-mesh forward path (used when a mesh's element-major
+// tiles do not fit a workgroup): 128 rows per tile, 2 lanes per row.
+constexpr int ROW_R = 128, ROW_G = 2, ROW_U = 1;
 
 template <int KC, int R, int G, int U>
 __global__ __launch_bounds__(R * G) void k_forward(const MeshDev md) {
@@ -449,7 +217,7 @@ __global__ __launch_bounds__(R * G) void k_forward(const MeshDev md) {
     const int64_t per = gridDim.x / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= md.n_tiles) return;
-    tile_body<KC, R, G, U>(md, tile, smem_raw);
+    fwd_tile<KC, R, G, U>(md, tile, reinterpret_cast<double2*>(smem_raw));
 }
 
 // Batched persistent kernel: every workgroup pulls (mesh, tile) work items.
@@ -476,9 +244,9 @@ __global__ __launch_bounds__(R * G) void k_batch(const MeshDev* __restrict__ tab
         const MeshDev md = table[item.x];
         const int64_t tile = item.y;
         switch (md.kind_code) {
-            case 0: tile_body<0, R, G, U>(md, tile, smem_raw); break;
-            case 1: tile_body<1, R, G, U>(md, tile, smem_raw); break;
-            default: tile_body<2, R, G, U>(md, tile, smem_raw); break;
+            case 0: fwd_tile<0, R, G, U>(md, tile, reinterpret_cast<double2*>(smem_raw)); break;
+            case 1: fwd_tile<1, R, G, U>(md, tile, reinterpret_cast<double2*>(smem_raw)); break;
+            default: fwd_tile<2, R, G, U>(md, tile, reinterpret_cast<double2*>(smem_raw)); break;
         }
         __syncthreads();
         if (schedule == 0) w += gridDim.x;
@@ -518,22 +286,9 @@ int cu_count() {
     return n;
 }
 
-static int fwd_variant() {
-    static int v = -1;
-    if (v < 0) {
-        v = 4;
-        const char* s = std::getenv("FEM_FWD_VARIANT");
-        if (s) {
-            const int x = std::atoi(s);
-            if (x >= 0 && x < (int)(sizeof(FWD_VARIANTS) / sizeof(FWD_VARIANTS[0]))) v = x;
-        }
-    }
-    return v;
-}
-
 int default_rows_per_tile(int kc) {
     (void)kc;
-    return FWD_VARIANTS[fwd_variant()].R;
+    return ROW_R;
 }
 
 template <class K>
@@ -542,40 +297,26 @@ static hipError_t set_lds(K kernel, int bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <int KC, int R, int G, int U>
-static fem_status launch_fwd_t(const MeshDev& md, int pmax, hipStream_t s) {
-    const int bytes = U == -1 ? forward_lds_bytes(KC, pmax, md.max_tile_elems) : pmax * 16;
+template <int KC>
+static fem_status launch_fwd_kc(const MeshDev& md, int pmax, hipStream_t s) {
+    const int bytes = pmax * 16;
     if (bytes > lds_limit_bytes())
         return fail(FEM_EOVERFLOW, "fem_assemble: a row tile needs more LDS than the device has");
-    FEM_HIP(set_lds(k_forward<KC, R, G, U>, bytes));
+    FEM_HIP(set_lds(k_forward<KC, ROW_R, ROW_G, ROW_U>, bytes));
     const int64_t grid = ((md.n_tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_forward<KC, R, G, U>), dim3((unsigned)grid), dim3(R * G), bytes, s, md);
+    hipLaunchKernelGGL((k_forward<KC, ROW_R, ROW_G, ROW_U>), dim3((unsigned)grid), dim3(ROW_R * ROW_G),
+                       bytes, s, md);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
 
-template <int KC>
-static fem_status launch_fwd_kc(const MeshDev& md, int R, int pmax, hipStream_t s) {
-    const FwdVariant v = FWD_VARIANTS[fwd_variant()];
-    if (v.R != R) return fail(FEM_EINVAL, "fem_assemble: rows per tile does not match the kernel variant");
-    switch (fwd_variant()) {
-        case 0: return launch_fwd_t<KC, 128, 1, 4>(md, pmax, s);
-        case 1: return launch_fwd_t<KC, 128, 2, -1>(md, pmax, s);
-        case 2: return launch_fwd_t<KC, 64, 2, -1>(md, pmax, s);
-        case 3: return launch_fwd_t<KC, 64, 4, -1>(md, pmax, s);
-        case 4: return launch_fwd_t<KC, 128, 2, 1>(md, pmax, s);
-        default: return launch_fwd_t<KC, 32, 4, -1>(md, pmax, s);
-    }
-}
-
-bool forward_uses_tile_elems() { return FWD_VARIANTS[fwd_variant()].U == -1; }
-
 fem_status launch_forward(const MeshDev& md, int R, int pmax, hipStream_t s) {
     if (md.n_tiles == 0) return FEM_OK;
+    if (R != ROW_R) return fail(FEM_EINVAL, "fem_assemble: rows per tile does not match the row kernel");
     switch (md.kind_code) {
-        case 0: return launch_fwd_kc<0>(md, R, pmax, s);
-        case 1: return launch_fwd_kc<1>(md, R, pmax, s);
-        default: return launch_fwd_kc<2>(md, R, pmax, s);
+        case 0: return launch_fwd_kc<0>(md, pmax, s);
+        case 1: return launch_fwd_kc<1>(md, pmax, s);
+        default: return launch_fwd_kc<2>(md, pmax, s);
     }
 }
 
@@ -693,18 +434,19 @@ struct EmaElem<2> {
 
 template <int KC>
 __device__ __forceinline__ typename EmaElem<KC>::T ema_elem(const int gid[KT<KC>::NV],
-                                                            const double x[KT<KC>::NV][KT<KC>::DIM]) {
+                                                            const double x[KT<KC>::NV][KT<KC>::DIM],
+                                                            double ca, double cb) {
     if constexpr (KC == 0) {
         V2 v[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) v[q] = {x[q][0], x[q][1]};
-        return tri_elem(v, gid);
+        return tri_elem(v, gid, ca, cb);
     } else {
         V3 v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = {x[q][0], x[q][1], x[q][2]};
-        if constexpr (KC == 1) return rt3_elem(v, gid);
-        else return ned3_elem(v, gid);
+        if constexpr (KC == 1) return rt3_elem(v, gid, ca, cb);
+        else return ned3_elem(v, gid, ca, cb);
     }
 }
 
@@ -726,17 +468,32 @@ __device__ __forceinline__ typename EmaPass<KC, MASS>::T ema_pass_state(
     else return st;
 }
 
-template <int KC, bool MASS, int k, int l>
-__device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T& st) {
+// Row scale s_k * (coefficient * factor) of row k, then entry (k, l).
+template <int KC, bool MASS, int k>
+__device__ __forceinline__ double ema_row(const typename EmaPass<KC, MASS>::T& st) {
     if constexpr (KC == 2) {
-        if constexpr (MASS) return ned3_M<k, l>(st);
-        else return ned3_K<k, l>(st);
+        if constexpr (MASS) return ned3_mrow<k>(st);
+        else return ned3_krow<k>(st);
     } else if constexpr (KC == 1) {
-        if constexpr (MASS) return rt3_M<k, l>(st);
-        else return rt3_K<k, l>(st);
+        if constexpr (MASS) return rt3_mrow<k>(st);
+        else return rt3_krow<k>(st);
     } else {
-        if constexpr (MASS) return tri_M<k, l>(st);
-        else return tri_K<k, l>(st);
+        if constexpr (MASS) return tri_mrow<k>(st);
+        else return tri_krow<k>(st);
+    }
+}
+
+template <int KC, bool MASS, int k, int l>
+__device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T& st, double r) {
+    if constexpr (KC == 2) {
+        if constexpr (MASS) return ned3_M<k, l>(st, r);
+        else return ned3_K<k, l>(st, r);
+    } else if constexpr (KC == 1) {
+        if constexpr (MASS) return rt3_M<k, l>(st, r);
+        else return rt3_K<k, l>(st, r);
+    } else {
+        if constexpr (MASS) return tri_M<k, l>(st, r);
+        else return tri_K<k, l>(st, r);
     }
 }
 
@@ -746,8 +503,8 @@ __device__ __forceinline__ uint32_t ema_jk(const uint32_t jw[4], int k) {
 
 // One pass (K or M) of a lane's element: rows k that belong to the tile.
 template <int KC, bool MASS>
-__device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, double coef,
-                                            const uint32_t jw[4], const int rb[KT<KC>::NLOC],
+__device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, const uint32_t jw[4],
+                                            const int rb[KT<KC>::NLOC],
                                             const uint64_t cp[KT<KC>::NLOC], double* out,
                                             double* sdiag) {
     constexpr int NLOC = KT<KC>::NLOC;
@@ -759,7 +516,8 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, d
             const typename EmaPass<KC, MASS>::T& sk = st;
             const int base = rb[k];
             const uint64_t c = cp[k];
-            const double d = coef * ema_entry<KC, MASS, k, k>(sk);
+            const double r = ema_row<KC, MASS, k>(sk);
+            const double d = ema_entry<KC, MASS, k, k>(sk, r);
             if constexpr (KC == 2) {
                 sdiag[jk] = d;
             } else {
@@ -769,7 +527,7 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, d
                 constexpr int l = decltype(ll)::value;
                 if constexpr (l != k)
                     atomicAdd(&out[base + (int)((c >> (8 * l)) & 0xFFu)],
-                              coef * ema_entry<KC, MASS, k, l>(sk));
+                              ema_entry<KC, MASS, k, l>(sk, r));
             });
         }
     });
@@ -862,7 +620,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
                 if constexpr (KC == 2) rowdiag[lr] = (int)((cp[k] >> (8 * k)) & 0xFFu);
             }
         }
-        st = ema_elem<KC>(gid, x);
+        st = ema_elem<KC>(gid, x, ca, cb);
         bad = !(fabs(st.J) > 0.0) || !isfinite(st.J);
     }
     if (bad) atomicOr(md.err_word, ERR_DEGENERATE);
@@ -874,7 +632,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if (dst) {
             if (have) {
                 typename EmaPass<KC, MASS>::T ps = ema_pass_state<KC, MASS>(st);
-                ema_scatter<KC, MASS>(ps, MASS ? cb : ca, jw, rb, cp, out, sdiag);
+                ema_scatter<KC, MASS>(ps, jw, rb, cp, out, sdiag);
             }
             __syncthreads();
             if constexpr (KC == 2) {

@@ -143,13 +143,13 @@ __device__ __forceinline__ void ned3_signs(const int gid[4], double s[6]) {
     for (int l = 0; l < 6; ++l) s[l] = gid[nib(NED3_START, l)] > gid[nib(NED3_END, l)] ? 1.0 : -1.0;
 }
 
-// Row k (runtime) of the 3D Nedelec local K and M (without coefficients).
-__device__ __forceinline__ void ned3_row(const Geo3& g, const double s[6], int k, double Kr[6],
-                                         double Mr[6]) {
+// Row k (runtime) of the 3D Nedelec local a K and b M, in the canonical
+// rounding described at the end of this file.
+__device__ __forceinline__ void ned3_row(const Geo3& g, const double s[6], int k, double ca,
+                                         double cb, double Kr[6], double Mr[6]) {
     V3 o[6];
     ned3_o(g, o);
-    const double aJ = fabs(g.J);
-    const double inv = 1.0 / aJ;
+    const double inv = 1.0 / fabs(g.J);
     const double sk = pick6d(s, k);
     const V3 ok = pick6(o, k);
     const int i = nib(NED3_START, k);
@@ -168,16 +168,16 @@ __device__ __forceinline__ void ned3_row(const Geo3& g, const double s[6], int k
         Gi[a] = pick4d(col, i);
         Gj[a] = pick4d(col, j);
     }
-    const double kf = sk * (2.0 / 3.0) * inv;
-    const double mf = sk * (1.0 / 120.0) * inv;
+    const double kr = sk * (ca * ((2.0 / 3.0) * inv));
+    const double mr = sk * (cb * ((1.0 / 120.0) * inv));
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
         const int m = nib(NED3_START, l);
         const int n = nib(NED3_END, l);
-        Kr[l] = kf * s[l] * dot(ok, o[l]);
+        Kr[l] = (s[l] * kr) * dot(ok, o[l]);
         const double t = whitney_term(Gj[n] * (1.0 + (i == m)), Gi[m] * (1.0 + (j == n)),
                                       Gj[m] * (1.0 + (i == n)), Gi[n] * (1.0 + (j == m)));
-        Mr[l] = mf * s[l] * t;
+        Mr[l] = (s[l] * mr) * t;
     }
 }
 
@@ -218,21 +218,21 @@ __device__ __forceinline__ GeoRT3 geo_rt3(const V3 x[4]) {
     return g;
 }
 
-__device__ __forceinline__ void rt3_row(const GeoRT3& g, const double s[4], int k, double Kr[4],
-                                        double Mr[4]) {
+__device__ __forceinline__ void rt3_row(const GeoRT3& g, const double s[4], int k, double ca,
+                                        double cb, double Kr[4], double Mr[4]) {
     const double inv = 1.0 / fabs(g.J);
     const double sk = pick4d(s, k);
     const int pk = 3 - k;
     const V3 ypk = pick4(g.y, pk);
     const double upk = pick4d(g.u, pk);
-    const double kf = sk * 1.5 * inv;
-    const double mf = sk * (1.0 / 120.0) * inv;
+    const double kr = sk * (ca * (1.5 * inv));
+    const double mr = sk * (cb * ((1.0 / 120.0) * inv));
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
         const int pl = 3 - l;
-        Kr[l] = kf * s[l];
+        Kr[l] = s[l] * kr;
         const double t = g.base - 5.0 * (upk + g.u[pl]) + 20.0 * dot(ypk, g.y[pl]);
-        Mr[l] = mf * s[l] * t;
+        Mr[l] = (s[l] * mr) * t;
     }
 }
 
@@ -265,8 +265,8 @@ __device__ __forceinline__ void tri_signs(const int gid[3], double s[3]) {
 
 __device__ __forceinline__ double dot2(V2 a, V2 b) { return a.x * b.x + a.y * b.y; }
 
-__device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k, double Kr[3],
-                                        double Mr[3]) {
+__device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k, double ca,
+                                        double cb, double Kr[3], double Mr[3]) {
     const double inv = 1.0 / fabs(g.J);
     const double sk = onehot(k, 0) * s[0] + onehot(k, 1) * s[1] + onehot(k, 2) * s[2];
     const int i = nib(TRI_START, k);
@@ -284,16 +284,16 @@ __device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k,
         Gi[a] = onehot(i, 0) * G[0][a] + onehot(i, 1) * G[1][a] + onehot(i, 2) * G[2][a];
         Gj[a] = onehot(j, 0) * G[0][a] + onehot(j, 1) * G[1][a] + onehot(j, 2) * G[2][a];
     }
-    const double kf = sk * 2.0 * inv;
-    const double mf = sk * (1.0 / 24.0) * inv;
+    const double kr = sk * (ca * (2.0 * inv));
+    const double mr = sk * (cb * ((1.0 / 24.0) * inv));
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const int m = nib(TRI_START, l);
         const int n = nib(TRI_END, l);
-        Kr[l] = kf * s[l];
+        Kr[l] = s[l] * kr;
         const double t = whitney_term(Gj[n] * (1.0 + (i == m)), Gi[m] * (1.0 + (j == n)),
                                       Gj[m] * (1.0 + (i == n)), Gi[n] * (1.0 + (j == m)));
-        Mr[l] = mf * s[l] * t;
+        Mr[l] = (s[l] * mr) * t;
     }
 }
 
@@ -302,110 +302,30 @@ __device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k,
 namespace fem {
 
 // ---------------------------------------------------------------------------
-// Full local matrices with compile-time indices (no per-lane selection). Each
-// symmetric pair is computed once and stored in both (k,l) and (l,k), so the
-// local matrices are exactly symmetric. Returns J.
-__device__ __forceinline__ double ned3_full(const V3 x[4], const int gid[4], double K[6][6],
-                                            double M[6][6]) {
-    const Geo3 g = geo3(x);
-    V3 o[6];
-    ned3_o(g, o);
-    double s[6];
-    ned3_signs(gid, s);
-    const double inv = 1.0 / fabs(g.J);
-    const double kf = (2.0 / 3.0) * inv;
-    const double mf = (1.0 / 120.0) * inv;
-    double G[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b) G[a][b] = G[b][a] = dot(g.c[a], g.c[b]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int i = nib(NED3_START, k), j = nib(NED3_END, k);
-#pragma unroll
-        for (int l = k; l < 6; ++l) {
-            const int m = nib(NED3_START, l), n = nib(NED3_END, l);
-            const double ss = s[k] * s[l];
-            K[k][l] = K[l][k] = kf * ss * dot(o[k], o[l]);
-            const double t = whitney_term(G[j][n] * (1.0 + (i == m)), G[i][m] * (1.0 + (j == n)),
-                                          G[j][m] * (1.0 + (i == n)), G[i][n] * (1.0 + (j == m)));
-            M[k][l] = M[l][k] = mf * ss * t;
-        }
-    }
-    return g.J;
-}
-
-__device__ __forceinline__ double rt3_full(const V3 x[4], const int gid[4], double K[4][4],
-                                           double M[4][4]) {
-    const GeoRT3 g = geo_rt3(x);
-    double s[4];
-    rt3_signs(gid, s);
-    const double inv = 1.0 / fabs(g.J);
-    const double kf = 1.5 * inv;
-    const double mf = (1.0 / 120.0) * inv;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int pk = 3 - k;
-#pragma unroll
-        for (int l = k; l < 4; ++l) {
-            const int pl = 3 - l;
-            const double ss = s[k] * s[l];
-            K[k][l] = K[l][k] = kf * ss;
-            const double t = g.base - 5.0 * (g.u[pk] + g.u[pl]) + 20.0 * dot(g.y[pk], g.y[pl]);
-            M[k][l] = M[l][k] = mf * ss * t;
-        }
-    }
-    return g.J;
-}
-
-__device__ __forceinline__ double tri_full(const V2 x[3], const int gid[3], double K[3][3],
-                                           double M[3][3]) {
-    const Geo2 g = geo2(x);
-    double s[3];
-    tri_signs(gid, s);
-    const double inv = 1.0 / fabs(g.J);
-    const double kf = 2.0 * inv;
-    const double mf = (1.0 / 24.0) * inv;
-    double G[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b) G[a][b] = G[b][a] = dot2(g.c[a], g.c[b]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int i = nib(TRI_START, k), j = nib(TRI_END, k);
-#pragma unroll
-        for (int l = k; l < 3; ++l) {
-            const int m = nib(TRI_START, l), n = nib(TRI_END, l);
-            const double ss = s[k] * s[l];
-            K[k][l] = K[l][k] = kf * ss;
-            const double t = whitney_term(G[j][n] * (1.0 + (i == m)), G[i][m] * (1.0 + (j == n)),
-                                          G[j][m] * (1.0 + (i == n)), G[i][n] * (1.0 + (j == m)));
-            M[k][l] = M[l][k] = mf * ss * t;
-        }
-    }
-    return g.J;
-}
-
-}  // namespace fem
-
-namespace fem {
-
-// ---------------------------------------------------------------------------
+// Canonical rounding of the scaled local entries (shared by the row functions
+// above and the element states below, so every kernel produces bitwise the
+// same values):
+//   a K_kl = (s_l * (s_k * (a * kf))) * q_kl,   b M_kl = (s_l * (s_k * (b * mf))) * t_kl
+// with kf, mf the kind's factors times 1/|J| (rounded once), q_kl the
+// curl/div term (o_k . o_l for 3D Nedelec, 1 otherwise) and t_kl the mass
+// term. Sign factors are +-1, so multiplying by them is exact and (k, l),
+// (l, k) give bitwise equal values; q and t are symmetric by construction.
+//
 // Element state for the element-major kernel: the geometric quantities the
-// rows of K and M are formed from, kept in registers while the kernel makes
-// one pass for K and one for M. Entries are produced one at a time with
-// compile-time (k, l), by the same expressions as the *_full and *_row
-// functions above, so every entry is bitwise the value those produce (and
-// (k, l), (l, k) are bitwise equal).
+// rows are formed from, kept in registers while the kernel makes one pass for
+// K and one for M. Entries are produced one at a time with compile-time
+// (k, l).
 __host__ __device__ constexpr int tri_index(int a, int b) {  // packed upper triangle of a 4x4
     return a <= b ? a * 4 - a * (a + 1) / 2 + b : b * 4 - b * (b + 1) / 2 + a;
 }
 
+__device__ __forceinline__ double sgn_bit(uint32_t bits, int l) {
+    return ((bits >> l) & 1u) ? 1.0 : -1.0;
+}
+
 struct Ned3Elem {
     V3 b1, b2, b3;  // x_j - x_0
-    double kf, mf;  // 2/(3|J|), 1/(120|J|)
+    double ka, mb;  // a * 2/(3|J|), b * 1/(120|J|)
     double J;
     uint32_t sbits;  // bit l set iff s_l = +1
 };
@@ -415,19 +335,20 @@ struct Ned3Elem {
 // stiffness pass and of the mass pass are not live at the same time.
 struct Ned3Mass {
     double G[10];  // G_ab = c_a . c_b, packed upper triangle
-    double mf;
+    double mb;
     uint32_t sbits;
 };
 
-__device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4]) {
+__device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4], double ca,
+                                              double cb) {
     Ned3Elem e;
     e.b1 = sub(x[1], x[0]);
     e.b2 = sub(x[2], x[0]);
     e.b3 = sub(x[3], x[0]);
     e.J = dot(e.b1, cross(e.b2, e.b3));
     const double inv = 1.0 / fabs(e.J);
-    e.kf = (2.0 / 3.0) * inv;
-    e.mf = (1.0 / 120.0) * inv;
+    e.ka = ca * ((2.0 / 3.0) * inv);
+    e.mb = cb * ((1.0 / 120.0) * inv);
     e.sbits = 0;
 #pragma unroll
     for (int l = 0; l < 6; ++l)
@@ -435,7 +356,7 @@ __device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4]) {
     return e;
 }
 
-// Same cofactor vectors and Gram entries as geo3 / ned3_full.
+// Same cofactor vectors and Gram entries as geo3 / ned3_row.
 __device__ __forceinline__ Ned3Mass ned3_mass(const Ned3Elem& e) {
     V3 c[4];
     c[1] = cross(e.b2, e.b3);
@@ -447,13 +368,9 @@ __device__ __forceinline__ Ned3Mass ned3_mass(const Ned3Elem& e) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = a; b < 4; ++b) m.G[tri_index(a, b)] = dot(c[a], c[b]);
-    m.mf = e.mf;
+    m.mb = e.mb;
     m.sbits = e.sbits;
     return m;
-}
-
-__device__ __forceinline__ double sgn_bit(uint32_t bits, int l) {
-    return ((bits >> l) & 1u) ? 1.0 : -1.0;
 }
 
 template <int k>
@@ -466,34 +383,43 @@ __device__ __forceinline__ V3 ned3_o_of(const Ned3Elem& e) {
     else return e.b2;
 }
 
-template <int k, int l>
-__device__ __forceinline__ double ned3_K(const Ned3Elem& e) {
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
-    return e.kf * ss * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
+// row scale s_k * (a kf) of the stiffness pass, s_k * (b mf) of the mass pass
+template <int k>
+__device__ __forceinline__ double ned3_krow(const Ned3Elem& e) {
+    return sgn_bit(e.sbits, k) * e.ka;
+}
+template <int k>
+__device__ __forceinline__ double ned3_mrow(const Ned3Mass& e) {
+    return sgn_bit(e.sbits, k) * e.mb;
 }
 
 template <int k, int l>
-__device__ __forceinline__ double ned3_M(const Ned3Mass& e) {
+__device__ __forceinline__ double ned3_K(const Ned3Elem& e, double kr) {
+    return (sgn_bit(e.sbits, l) * kr) * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
+}
+
+template <int k, int l>
+__device__ __forceinline__ double ned3_M(const Ned3Mass& e, double mr) {
     constexpr int i = nib(NED3_START, k), j = nib(NED3_END, k);
     constexpr int m = nib(NED3_START, l), n = nib(NED3_END, l);
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
     const double t = whitney_term(e.G[tri_index(j, n)] * (1.0 + (i == m)),
                                   e.G[tri_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri_index(i, n)] * (1.0 + (j == m)));
-    return e.mf * ss * t;
+    return (sgn_bit(e.sbits, l) * mr) * t;
 }
 
 struct Rt3Elem {
     V3 y1, y2, y3;  // x_a - x_0
     double base;    // |S|^2 + tr Y
     double u1, u2, u3;
-    double kf, mf;  // 3/(2|J|), 1/(120|J|)
+    double ka, mb;  // a * 3/(2|J|), b * 1/(120|J|)
     double J;
     uint32_t sbits;
 };
 
-__device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4]) {
+__device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4], double ca,
+                                            double cb) {
     const GeoRT3 g = geo_rt3(x);
     Rt3Elem e;
     e.y1 = g.y[1];
@@ -504,8 +430,8 @@ __device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4]) {
     e.u2 = g.u[2];
     e.u3 = g.u[3];
     const double inv = 1.0 / fabs(g.J);
-    e.kf = 1.5 * inv;
-    e.mf = (1.0 / 120.0) * inv;
+    e.ka = ca * (1.5 * inv);
+    e.mb = cb * ((1.0 / 120.0) * inv);
     e.J = g.J;
     double s[4];
     rt3_signs(gid, s);
@@ -530,23 +456,30 @@ __device__ __forceinline__ double rt3_u(const Rt3Elem& e) {
     else return e.u3;
 }
 
-template <int k, int l>
-__device__ __forceinline__ double rt3_K(const Rt3Elem& e) {
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
-    return e.kf * ss;
+template <int k>
+__device__ __forceinline__ double rt3_krow(const Rt3Elem& e) {
+    return sgn_bit(e.sbits, k) * e.ka;
+}
+template <int k>
+__device__ __forceinline__ double rt3_mrow(const Rt3Elem& e) {
+    return sgn_bit(e.sbits, k) * e.mb;
 }
 
 template <int k, int l>
-__device__ __forceinline__ double rt3_M(const Rt3Elem& e) {
+__device__ __forceinline__ double rt3_K(const Rt3Elem& e, double kr) {
+    return sgn_bit(e.sbits, l) * kr;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double rt3_M(const Rt3Elem& e, double mr) {
     constexpr int pk = 3 - k, pl = 3 - l;
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
     const double t = e.base - 5.0 * (rt3_u<pk>(e) + rt3_u<pl>(e)) + 20.0 * dot(rt3_y<pk>(e), rt3_y<pl>(e));
-    return e.mf * ss * t;
+    return (sgn_bit(e.sbits, l) * mr) * t;
 }
 
 struct TriElem {
-    double G[6];  // packed upper triangle of the 3x3 Gram (indices as tri_index on 4x4, a,b < 3)
-    double kf, mf;  // 2/|J|, 1/(24|J|)
+    double G[6];  // packed upper triangle of the 3x3 Gram of the cofactor vectors
+    double ka, mb;  // a * 2/|J|, b * 1/(24|J|)
     double J;
     uint32_t sbits;
 };
@@ -555,7 +488,7 @@ __host__ __device__ constexpr int tri3_index(int a, int b) {
     return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
 }
 
-__device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3]) {
+__device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3], double ca, double cb) {
     const Geo2 g = geo2(x);
     TriElem e;
 #pragma unroll
@@ -563,8 +496,8 @@ __device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3]) {
 #pragma unroll
         for (int b = a; b < 3; ++b) e.G[tri3_index(a, b)] = dot2(g.c[a], g.c[b]);
     const double inv = 1.0 / fabs(g.J);
-    e.kf = 2.0 * inv;
-    e.mf = (1.0 / 24.0) * inv;
+    e.ka = ca * (2.0 * inv);
+    e.mb = cb * ((1.0 / 24.0) * inv);
     e.J = g.J;
     e.sbits = 0;
 #pragma unroll
@@ -573,22 +506,29 @@ __device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3]) {
     return e;
 }
 
-template <int k, int l>
-__device__ __forceinline__ double tri_K(const TriElem& e) {
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
-    return e.kf * ss;
+template <int k>
+__device__ __forceinline__ double tri_krow(const TriElem& e) {
+    return sgn_bit(e.sbits, k) * e.ka;
+}
+template <int k>
+__device__ __forceinline__ double tri_mrow(const TriElem& e) {
+    return sgn_bit(e.sbits, k) * e.mb;
 }
 
 template <int k, int l>
-__device__ __forceinline__ double tri_M(const TriElem& e) {
+__device__ __forceinline__ double tri_K(const TriElem& e, double kr) {
+    return sgn_bit(e.sbits, l) * kr;
+}
+
+template <int k, int l>
+__device__ __forceinline__ double tri_M(const TriElem& e, double mr) {
     constexpr int i = nib(TRI_START, k), j = nib(TRI_END, k);
     constexpr int m = nib(TRI_START, l), n = nib(TRI_END, l);
-    const double ss = sgn_bit(e.sbits, k) * sgn_bit(e.sbits, l);
     const double t = whitney_term(e.G[tri3_index(j, n)] * (1.0 + (i == m)),
                                   e.G[tri3_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri3_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri3_index(i, n)] * (1.0 + (j == m)));
-    return e.mf * ss * t;
+    return (sgn_bit(e.sbits, l) * mr) * t;
 }
 
 }  // namespace fem
@@ -612,13 +552,13 @@ __device__ __forceinline__ void pin_state(Ned3Elem& e) {
     pin(e.b1);
     pin(e.b2);
     pin(e.b3);
-    pin(e.kf);
+    pin(e.ka);
 }
 template <bool MASS>
 __device__ __forceinline__ void pin_state(Ned3Mass& e) {
 #pragma unroll
     for (int q = 0; q < 10; ++q) pin(e.G[q]);
-    pin(e.mf);
+    pin(e.mb);
 }
 template <bool MASS>
 __device__ __forceinline__ void pin_state(Rt3Elem& e) {
@@ -630,9 +570,9 @@ __device__ __forceinline__ void pin_state(Rt3Elem& e) {
         pin(e.u1);
         pin(e.u2);
         pin(e.u3);
-        pin(e.mf);
+        pin(e.mb);
     } else {
-        pin(e.kf);
+        pin(e.ka);
     }
 }
 template <bool MASS>
@@ -640,9 +580,9 @@ __device__ __forceinline__ void pin_state(TriElem& e) {
     if constexpr (MASS) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) pin(e.G[q]);
-        pin(e.mf);
+        pin(e.mb);
     } else {
-        pin(e.kf);
+        pin(e.ka);
     }
 }
 

@@ -47,17 +47,6 @@ struct Pattern {
     int max_row_len = 0;
     // max nnz of a tile of R consecutive rows, for R = 32, 64, 128, 256
     int tile_pmax[4] = {0, 0, 0, 0};
-    // Element lists of the row tiles, per rows-per-tile (index as tile_pmax):
-    // the sorted unique elements whose slots fall in each tile, and for every
-    // slot (row-sorted order) its element's index in that list, times 8, plus
-    // its local dof number.
-    struct TileElems {
-        bool built = false;
-        int32_t* eptr = nullptr;      // [n_tiles+1]
-        int32_t* elems = nullptr;     // [eptr[n_tiles]]
-        uint32_t* slot_info = nullptr;// [n_slots]: (index in tile list) << 3 | local dof
-        int max_elems = 0;            // largest tile list
-    } tiles[4];
     // Element-major tiles (one per workgroup size NT = 128, 256): R consecutive
     // rows per tile with R chosen so a tile's element list fits NT lanes; per
     // tile element entry, the tile-local slot index of each local dof whose row
@@ -135,7 +124,6 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems,
                           hipStream_t s);
 fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s);
 fem_status build_node_map(fem_mesh m, hipStream_t s);
-fem_status build_tile_elems(fem_mesh m, DofSet& ds, int rows_per_tile, hipStream_t s);
 fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s);
 int ema_index(int nt);  // 128 -> 0, 256 -> 1
 int ema_lds_bytes(int kind_code, int R, int pmax, int max_slots);
@@ -159,13 +147,12 @@ struct MeshDev {
     int64_t n_rows;
     int64_t n_tiles;        // for the chosen rows-per-tile
     int32_t kind_code;      // 0: 2D (both kinds), 1: 3D Raviart-Thomas, 2: 3D Nedelec
-    int32_t max_tile_elems; // LDS records reserved per tile (element cache)
+    int32_t pad0;
     int* err_word;
-    // element lists of the tiles for the chosen rows-per-tile
+    // element-major tiles: element list of each tile, tile-local slot of each
+    // local dof of an entry
     const int32_t* tile_eptr;
     const int32_t* tile_elems;
-    const uint32_t* slot_info;
-    // element-major tiles
     const uint16_t* ema_joff;
     int32_t ema_R;
     int32_t ema_pmax;
@@ -187,9 +174,6 @@ int lds_limit_bytes();
 int batch_blocks_per_cu(int rows_per_tile, int lds_bytes);
 int cu_count();
 int default_rows_per_tile(int kind_code);
-int elem_record_bytes(int kind_code);
 fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s);
-bool forward_uses_tile_elems();
-int forward_lds_bytes(int kind_code, int pmax, int max_tile_elems);
 
 }  // namespace fem

@@ -537,61 +537,6 @@ __global__ void k_tile_unique(const uint64_t* keys, const uint32_t* scan, int64_
     if (i == 0 || keys[i - 1] / (uint64_t)T != tile) eptr[tile] = id;
 }
 
-__global__ void k_tile_slot_info(const uint64_t* keys, const uint32_t* sorted_slots,
-                                 const uint32_t* scan, const int32_t* rs_slot, const int32_t* eptr,
-                                 int64_t n, int64_t T, int nloc, uint32_t* slot_info, int* max_elems) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t k = keys[i];
-    const bool head = (i == 0 || k != keys[i - 1]);
-    const int64_t id = (int64_t)scan[i] + (head ? 1 : 0) - 1;
-    const int64_t tile = (int64_t)(k / (uint64_t)T);
-    const int64_t local = id - eptr[tile];
-    const uint32_t j = sorted_slots[i];
-    slot_info[j] = ((uint32_t)local << 3) | (uint32_t)(rs_slot[j] % nloc);
-    // the last pair of a tile has the largest index in its list
-    if (i + 1 == n || keys[i + 1] / (uint64_t)T != (uint64_t)tile) atomicMax(max_elems, (int)(local + 1));
-}
-
-fem_status build_tile_elems(fem_mesh m, DofSet& ds, int R, hipStream_t s) {
-    Pattern& p = ds.pat;
-    Pattern::TileElems& te = p.tiles[rows_index(R)];
-    if (te.built) return FEM_OK;
-    const int64_t T = m->T;
-    const int64_t n_slots = T * ds.nloc;
-    const int64_t n_tiles = (p.n_rows + R - 1) / R;
-    TmpBufs tb;
-    FEM_HIP(tb.alloc(n_slots));
-    hipLaunchKernelGGL(k_tile_keys, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, ds.elems2dofs,
-                       n_slots, ds.nloc, R, T, tb.keys, tb.vals);
-    FEM_HIP(hipGetLastError());
-    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_slots,
-                             bit_length((uint64_t)n_tiles * (uint64_t)T - 1), s));
-    hipLaunchKernelGGL(k_flags, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, n_slots, tb.scan);
-    FEM_HIP(hipGetLastError());
-    FEM_HIP(scan_exclusive_u32(tb.scan, n_slots, s));
-    int64_t n_pairs = 0;
-    if (fem_status st = read_count(tb.scan, tb.keys, n_slots, s, &n_pairs)) return st;
-    if ((n_pairs >> 29) != 0) return fail(FEM_EOVERFLOW, "fem_pattern: too many tile elements");
-    FEM_HIP(dmalloc(m, &te.eptr, n_tiles + 1));
-    FEM_HIP(dmalloc(m, &te.elems, n_pairs));
-    FEM_HIP(dmalloc(m, &te.slot_info, n_slots));
-    hipLaunchKernelGGL(k_tile_unique, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.scan, n_slots,
-                       T, te.elems, te.eptr);
-    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, te.eptr + n_tiles, (int32_t)n_pairs);
-    FEM_HIP(hipGetLastError());
-    int* mx = reinterpret_cast<int*>(tb.keys_tmp);
-    FEM_HIP(hipMemsetAsync(mx, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_tile_slot_info, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan,
-                       ds.rs_slot, te.eptr, n_slots, T, ds.nloc, te.slot_info, mx);
-    FEM_HIP(hipGetLastError());
-    int host_mx = 0;
-    FEM_HIP(hipMemcpyAsync(&host_mx, mx, sizeof(int), hipMemcpyDeviceToHost, s));
-    FEM_HIP(hipStreamSynchronize(s));
-    te.max_elems = host_mx;
-    te.built = true;
-    return FEM_OK;
-}
 
 }  // namespace fem
 
@@ -681,6 +626,69 @@ static fem_status ema_attempt(fem_mesh m, DofSet& ds, int R, hipStream_t s, Patt
     return FEM_OK;
 }
 
+// Order key of an entry within its tile: the lowest local dof the entry has in
+// the tile, then the set of those dofs (6 bits), then (stable sort) the
+// element. Entries with the same rows in the tile become neighbours, so the
+// lanes of a wavefront mostly form the same local rows.
+__global__ void k_ema_order_keys(const int32_t* eptr, int64_t n_tiles, const uint16_t* joff,
+                                 int nloc, uint64_t* keys, uint32_t* vals) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    for (int32_t i = eptr[t]; i < eptr[t + 1]; ++i) {
+        uint32_t mask = 0;
+        for (int k = 0; k < nloc; ++k)
+            if (joff[(int64_t)i * 8 + k] != 0xFFFFu) mask |= 1u << k;
+        const uint32_t low = mask ? (uint32_t)(__ffs(mask) - 1) : 7u;
+        keys[i] = ((uint64_t)t << 9) | (low << 6) | mask;
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_ema_permute(const uint32_t* perm, int64_t n, const int32_t* elems_in,
+                              const uint4* joff_in, int32_t* elems_out, uint4* joff_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = perm[i];
+    elems_out[i] = elems_in[j];
+    joff_out[i] = joff_in[j];
+}
+
+static fem_status ema_order(Pattern::Ema& E, int nloc, hipStream_t s) {
+    int32_t n_ent = 0;
+    FEM_HIP(hipMemcpyAsync(&n_ent, E.eptr + E.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    if (n_ent <= 1) return FEM_OK;
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(n_ent));
+    hipLaunchKernelGGL(k_ema_order_keys, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.eptr, E.n_tiles,
+                       E.joff, nloc, tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_ent,
+                             bit_length((((uint64_t)E.n_tiles - 1) << 9) | 511u), s));
+    int32_t* elems = nullptr;
+    uint16_t* joff = nullptr;
+    FEM_HIP(hipMalloc((void**)&elems, (size_t)n_ent * sizeof(int32_t)));
+    if (hipMalloc((void**)&joff, (size_t)n_ent * 8 * sizeof(uint16_t)) != hipSuccess) {
+        (void)hipFree(elems);
+        return fail(FEM_ENOMEM, "fem_pattern: out of device memory");
+    }
+    hipLaunchKernelGGL(k_ema_permute, dim3(nblk(n_ent)), dim3(TB), 0, s, tb.vals, (int64_t)n_ent,
+                       E.elems, reinterpret_cast<const uint4*>(E.joff), elems,
+                       reinterpret_cast<uint4*>(joff));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(elems);
+        (void)hipFree(joff);
+        FEM_HIP(e);
+    }
+    (void)hipFree(E.elems);
+    (void)hipFree(E.joff);
+    E.elems = elems;
+    E.joff = joff;
+    return FEM_OK;
+}
+
 static void ema_free(Pattern::Ema& e) {
     if (e.eptr) (void)hipFree(e.eptr);
     if (e.elems) (void)hipFree(e.elems);
@@ -713,6 +721,10 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             if (ema_lds_bytes(kc, R, cand.pmax, cand.max_slots) > lds_limit_bytes()) {
                 ema_free(cand);
                 return fail(FEM_EOVERFLOW, "fem_pattern: a row tile needs more LDS than the device has");
+            }
+            if (fem_status so = ema_order(cand, ds.nloc, s)) {
+                ema_free(cand);
+                return so;
             }
             m->allocs.push_back(cand.eptr);
             m->allocs.push_back(cand.elems);
