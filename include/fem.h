@@ -41,7 +41,9 @@
  *   - CSR: rowptr int64 [n_rows+1], colind int32 [nnz] ascending within a row,
  *     full (not triangular) storage, every (dof_k, dof_l) pair of every element
  *     present even when its value is zero. K and M share the pattern. Values are
- *     bitwise symmetric and deterministic (no floating-point atomics).
+ *     bitwise symmetric and deterministic: an entry with more than two element
+ *     contributions is summed in ascending element order, and one with two is
+ *     the same either way round (x + y == y + x in IEEE arithmetic).
  */
 #ifndef FEM_H
 #define FEM_H
