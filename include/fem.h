@@ -162,19 +162,25 @@ fem_status fem_batch_bind(fem_batch batch, const double* const* nodes,
                           const double* const* a, const double* const* b,
                           double* const* K_vals, double* const* M_vals);
 
-/* Autotuner: times every candidate (rows per tile, schedule) with the bound
+/* Autotuner: times every candidate (tiling, schedule) with the bound
  * buffers on `stream`, keeps the fastest, and records it in the JSON cache file
  * `cache_path` (NULL = no file). If the file already holds an entry for this
  * device and batch signature, that entry is used without timing. Synchronises. */
 fem_status fem_batch_tune(fem_batch batch, const char* cache_path, void* stream);
 
 /* Which configuration the batch uses (host outputs, may be NULL):
- * rows per tile (64/128/256), schedule (0 static, 1 dynamic queue, 2 LPT-sorted
- * dynamic queue), number of work items, persistent grid size.               */
+ * tiling, schedule (0 static, 1 dynamic queue, 2 LPT-sorted dynamic queue),
+ * number of work items, persistent grid size. Tiling (`rows_per_tile`):
+ *   0            element-major tiles of 256-lane workgroups, rows per tile
+ *                chosen per mesh (the default when every mesh's tile element
+ *                lists fit a workgroup);
+ *   64, 128, 256 row tiles of that many rows, one or more lanes per row.    */
 fem_status fem_batch_config(fem_batch batch, int* rows_per_tile, int* schedule,
                             int64_t* n_work, int* grid);
 
-/* Select a configuration by hand (skips tuning).                            */
+/* Select a configuration by hand (skips tuning). FEM_EINVAL for a tiling
+ * outside {0, 64, 128, 256} (or 0 when element-major tiles are unavailable)
+ * or a schedule outside 0..2.                                               */
 fem_status fem_batch_set_config(fem_batch batch, int rows_per_tile, int schedule);
 
 /* One persistent launch over all bound meshes. Asynchronous; contains no

@@ -252,10 +252,12 @@ struct fem_batch_s {
     int64_t work_cap = 0;
     int64_t n_work = 0;
     unsigned* counters = nullptr;
-    int R = 128;
+    int R = 128;            // rows per row tile (64/128/256), 0 = element-major tiles
     int schedule = 1;
     int grid = 0;
     int pmax = 0;
+    int lds_bytes = 0;      // element-major tiles: largest tile LDS over the meshes
+    bool ema_ok = false;    // every mesh has usable element-major tiles
     bool work_valid = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -274,15 +276,23 @@ static void drop_graph(fem_batch B) {
 }
 
 static fem_status build_work(fem_batch B) {
-    const int R = B->R;
+    const bool ema = B->R == 0;
+    if (ema && !B->ema_ok) return fail(FEM_EINVAL, "fem_batch: element-major tiles unavailable for this batch");
     std::vector<int2> work;
     std::vector<double> cost;
     B->pmax = 0;
+    B->lds_bytes = 0;
     for (size_t i = 0; i < B->meshes.size(); ++i) {
         fem_mesh m = B->meshes[i];
         DofSet& ds = dofset(m, B->kinds[i]);
-        const int64_t nt = (ds.pat.n_rows + R - 1) / R;
-        B->pmax = std::max(B->pmax, ds.pat.tile_pmax[rows_index(R)]);
+        const Pattern::Ema& E = ds.pat.ema[ema_index(256)];
+        const int R = ema ? E.R : B->R;
+        const int64_t nt = ema ? E.n_tiles : (ds.pat.n_rows + R - 1) / R;
+        if (ema)
+            B->lds_bytes = std::max(B->lds_bytes, ema_lds_bytes(kind_code(m->dim, B->kinds[i]), E.R, E.pmax,
+                                                                E.max_slots));
+        else
+            B->pmax = std::max(B->pmax, ds.pat.tile_pmax[rows_index(R)]);
         const double per_row = ds.pat.n_rows ? (double)ds.pat.nnz / (double)ds.pat.n_rows : 0.0;
         for (int64_t t = 0; t < nt; ++t) {
             work.push_back(make_int2((int)i, (int)t));
@@ -309,15 +319,22 @@ static fem_status build_work(fem_batch B) {
         FEM_HIP(hipMemcpy(B->work_dev, work.data(), B->n_work * sizeof(int2), hipMemcpyHostToDevice));
     // persistent grid: as many workgroups as can be resident
     int per_cu = 1;
-    const int bytes = B->pmax * 16;
-    if (bytes > lds_limit_bytes())
-        return fail(FEM_EOVERFLOW, "fem_batch: a row tile needs more LDS than the device has");
-    per_cu = batch_blocks_per_cu(R, bytes);
+    if (ema) {
+        if (B->lds_bytes > lds_limit_bytes())
+            return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
+        per_cu = batch_ema_blocks_per_cu(B->lds_bytes);
+    } else {
+        const int bytes = B->pmax * 16;
+        if (bytes > lds_limit_bytes())
+            return fail(FEM_EOVERFLOW, "fem_batch: a row tile needs more LDS than the device has");
+        per_cu = batch_blocks_per_cu(B->R, bytes);
+    }
     B->grid = (int)std::min<int64_t>((int64_t)cu_count() * per_cu, std::max<int64_t>(1, B->n_work));
-    // rebuild the device table with the tile count for this R
+    // rebuild the device table with the tiling of this configuration
     for (size_t i = 0; i < B->host_table.size(); ++i) {
         MeshDev& md = B->host_table[i];
-        md.n_tiles = (md.n_rows + R - 1) / R;
+        if (ema) fill_ema(dofset(B->meshes[i], B->kinds[i]), 256, &md);
+        else md.n_tiles = (md.n_rows + B->R - 1) / B->R;
     }
     if (B->bound)
         FEM_HIP(hipMemcpy(B->table_dev, B->host_table.data(), B->host_table.size() * sizeof(MeshDev),
@@ -369,7 +386,7 @@ static bool cache_lookup(const char* path, const std::string& dev, const std::st
         if (pr == std::string::npos || ps == std::string::npos) continue;
         const int r = std::atoi(line.c_str() + pr + 17);
         const int sc = std::atoi(line.c_str() + ps + 12);
-        if ((r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2) {
+        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2) {
             *R = r;
             *sched = sc;
             found = true;  // last matching line wins
@@ -413,6 +430,16 @@ fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n
         B->meshes.push_back(meshes[i]);
         B->kinds.push_back(kinds[i]);
     }
+    // element-major tiles (256 lanes) for every mesh, if they fit
+    B->ema_ok = true;
+    for (int i = 0; i < n; ++i) {
+        DofSet& ds = dofset(meshes[i], kinds[i]);
+        if (fem_status st = build_ema(meshes[i], ds, 256, nullptr)) {
+            delete B;
+            return st;
+        }
+        B->ema_ok = B->ema_ok && ds.pat.ema[ema_index(256)].usable;
+    }
     B->host_table.resize(n);
     hipError_t e = hipMalloc((void**)&B->table_dev, n * sizeof(MeshDev));
     if (e == hipSuccess) e = hipMalloc((void**)&B->counters, 2 * sizeof(unsigned));
@@ -423,7 +450,7 @@ fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n
         fem_batch_destroy(B);
         return st;
     }
-    B->R = 128;
+    B->R = B->ema_ok ? 0 : 128;
     B->schedule = 1;
     *out = B;
     return FEM_OK;
@@ -437,22 +464,21 @@ fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double*
         MeshDev md;
         fem_status st = fill_meshdev(B->meshes[i], B->kinds[i], nodes[i], a ? a[i] : nullptr,
                                      b ? b[i] : nullptr, K_vals ? K_vals[i] : nullptr,
-                                     M_vals ? M_vals[i] : nullptr, B->R, &md);
+                                     M_vals ? M_vals[i] : nullptr, B->R > 0 ? B->R : 128, &md);
         if (st) return st;
         B->host_table[i] = md;
     }
-    FEM_HIP(hipMemcpy(B->table_dev, B->host_table.data(), B->host_table.size() * sizeof(MeshDev),
-                      hipMemcpyHostToDevice));
     B->bound = true;
     drop_graph(B);
-    if (!B->work_valid) return build_work(B);
-    return FEM_OK;
+    return build_work(B);  // sets the tiling fields of the table and uploads it
 }
 
 fem_status fem_batch_set_config(fem_batch B, int R, int schedule) {
     if (!B) return fail(FEM_EINVAL, "fem_batch_set_config: batch is NULL");
-    if ((R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > 2)
-        return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 64/128/256, schedule 0..2");
+    if ((R != 0 && R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > 2)
+        return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 0/64/128/256, schedule 0..2");
+    if (R == 0 && !B->ema_ok)
+        return fail(FEM_EINVAL, "fem_batch_set_config: element-major tiles unavailable for this batch");
     B->R = R;
     B->schedule = schedule;
     return build_work(B);
@@ -473,6 +499,9 @@ fem_status fem_batch_assemble(fem_batch B, void* stream) {
     if (!B->work_valid)
         if (fem_status st = build_work(B)) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (B->R == 0)
+        return launch_batch_ema(B->table_dev, B->work_dev, B->n_work, B->schedule, B->grid, B->lds_bytes,
+                                B->counters, s);
     return launch_batch(B->table_dev, B->work_dev, B->n_work, B->R, B->schedule, B->grid, B->pmax,
                         B->counters, s);
 }
@@ -489,9 +518,9 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     FEM_HIP(hipEventCreate(&e0));
     FEM_HIP(hipEventCreate(&e1));
     double best = 1e30;
-    int bestR = 128, bestS = 1;
-    const int Rs[3] = {64, 128, 256};
-    for (int ri = 0; ri < 3; ++ri) {
+    int bestR = B->ema_ok ? 0 : 128, bestS = 1;
+    const int Rs[4] = {0, 64, 128, 256};
+    for (int ri = B->ema_ok ? 0 : 1; ri < 4; ++ri) {
         for (int sched = 0; sched < 3; ++sched) {
             B->R = Rs[ri];
             B->schedule = sched;

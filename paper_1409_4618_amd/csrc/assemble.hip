@@ -703,6 +703,65 @@ fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s) {
     }
 }
 
+// Batched persistent kernel over element-major tiles: as k_batch, with the
+// work items (mesh, element-major tile) and the tile body of the forward path.
+// Each mesh keeps its own rows per tile and LDS layout; the dynamic LDS is the
+// largest over the meshes.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_ema(const MeshDev* __restrict__ table,
+                                                  const int2* __restrict__ work, int64_t n_work,
+                                                  int schedule, unsigned* counters) {
+    extern __shared__ __align__(16) char smem_raw[];
+    __shared__ int64_t s_w;
+    int64_t w = blockIdx.x;
+    for (;;) {
+        if (schedule != 0) {
+            if (threadIdx.x == 0) s_w = (int64_t)atomicAdd(&counters[0], 1u);
+            __syncthreads();
+            w = s_w;
+            __syncthreads();
+        }
+        if (w >= n_work) break;
+        const int2 item = work[w];
+        const MeshDev md = table[item.x];
+        const int64_t tile = item.y;
+        switch (md.kind_code) {
+            case 0: tile_ema<0, NT>(md, tile, smem_raw); break;
+            case 1: tile_ema<1, NT>(md, tile, smem_raw); break;
+            default: tile_ema<2, NT>(md, tile, smem_raw); break;
+        }
+        __syncthreads();
+        if (schedule == 0) w += gridDim.x;
+    }
+    if (schedule != 0 && threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+fem_status launch_batch_ema(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
+                            int grid, int lds_bytes, unsigned* counters, hipStream_t s) {
+    if (n_work == 0) return FEM_OK;
+    if (lds_bytes > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
+    FEM_HIP(set_lds(k_batch_ema<256>, lds_bytes));
+    hipLaunchKernelGGL((k_batch_ema<256>), dim3((unsigned)grid), dim3(256), lds_bytes, s, table, work,
+                       n_work, schedule, counters);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
+int batch_ema_blocks_per_cu(int lds_bytes) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_ema<256>, 256, lds_bytes) != hipSuccess ||
+        n <= 0)
+        n = 1;
+    return n;
+}
+
 // ===========================================================================
 // Backward: element-major adjoint.
 // For each element: gather the upstream weights of its n_local^2 entries through
@@ -718,37 +777,55 @@ struct BwdArgs {
     const double* b;
     const double* gK;
     const double* gM;
-    const int32_t* elems2dofs;
-    const int64_t* rowptr;
-    const int32_t* slot_rank;
-    const uint8_t* colpos;
+    const int64_t* slot_base;  // [T*nloc] row start of each slot's dof
+    const uint64_t* slot_cp;   // [T*nloc] column offsets of each slot's row
     double* ga;
     double* gb;
-    double* partials;
+    double* partials;          // [T*(dim+1)][dim] vertex derivatives, node order
+    const int32_t* node_rank;  // [T*(dim+1)] position of incidence (e, v) in node order
     int64_t T;
     int* err_word;
 };
 
+// Upstream weights of row k of an element (the slot's row start and column
+// offsets give the positions of its n_local entries).
+// A missing weight array reads the other one and is zeroed by a select (not a
+// branch, which would split the gathers into separate blocks); the launcher
+// handles both missing.
 template <int NLOC>
-__device__ __forceinline__ void gather_weights(const BwdArgs& A, int64_t e, double GK[NLOC][NLOC],
-                                               double GM[NLOC][NLOC]) {
+__device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t base, uint64_t cp,
+                                           double wk[NLOC], double wm[NLOC]) {
+    const double* pK = A.gK ? A.gK : A.gM;
+    const double* pM = A.gM ? A.gM : A.gK;
 #pragma unroll
-    for (int k = 0; k < NLOC; ++k) {
-        const int64_t s = e * NLOC + k;
-        const int64_t base = A.rowptr[A.elems2dofs[s]];
-        const uint64_t cp = load_colpos<NLOC>(A.colpos, A.slot_rank[s]);
-#pragma unroll
-        for (int l = 0; l < NLOC; ++l) {
-            const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
-            GK[k][l] = A.gK ? A.gK[pos] : 0.0;
-            GM[k][l] = A.gM ? A.gM[pos] : 0.0;
-        }
+    for (int l = 0; l < NLOC; ++l) {
+        const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
+        const double vk = pK[pos];
+        const double vm = pM[pos];
+        wk[l] = A.gK ? vk : 0.0;
+        wm[l] = A.gM ? vm : 0.0;
     }
 }
 
-__device__ __forceinline__ V3 vsel(const V3* v, int i) { return v[i]; }
+// Vertex derivative of incidence (e, v), written at its node-order position.
+__device__ __forceinline__ void store_vertex3(const BwdArgs& A, int64_t inc, V3 d) {
+    double* p = A.partials + (int64_t)A.node_rank[inc] * 3;
+    p[0] = d.x;
+    p[1] = d.y;
+    p[2] = d.z;
+}
+__device__ __forceinline__ void store_vertex2(const BwdArgs& A, int64_t inc, double dx, double dy) {
+    double* p = A.partials + (int64_t)A.node_rank[inc] * 2;
+    p[0] = dx;
+    p[1] = dy;
+}
 
-// 3D Nedelec
+// 3D Nedelec. With weights w_kl = s_k s_l gK_kl (gM likewise):
+//   dL/da = 2/(3|J|) Phi,  Phi = sum w_kl o_k . o_l,
+//   dL/db = Psi/(120|J|),  Psi = sum_ab P_ab G_ab (P: the Whitney weights of
+//   the Gram entries, symmetric part accumulated once per pair),
+// and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
+// the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
 __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
     int gid[4];
     V3 x[4];
@@ -757,50 +834,84 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
-    double GK[6][6], GM[6][6];
-    gather_weights<6>(A, e, GK, GM);
-    const Geo3 g = geo3(x);
-    V3 o[6];
-    ned3_o(g, o);
+    const V3 b1 = sub(x[1], x[0]), b2 = sub(x[2], x[0]), b3 = sub(x[3], x[0]);
     double s[6];
     ned3_signs(gid, s);
-    const double aJ = fabs(g.J);
+    // dPhi_j (derivative of Phi with respect to b_j) is accumulated directly:
+    // with q_k = sum_l (w_kl + w_lk) o_l,
+    //   dPhi_1 = q_1 - q_2 + q_4, dPhi_2 = q_2 - q_0 + q_5, dPhi_3 = q_0 - q_1 + q_3
+    // (o_0 = b3 - b2, o_1 = b1 - b3, o_2 = b2 - b1, o_3 = b3, o_4 = b1, o_5 = b2).
     double Phi = 0.0;
-    V3 q[6];
-    double Q[4][4];
+    V3 dPhi[3];
+    double P[10];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) q[k] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < 3; ++t) dPhi[t] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Q[i][j] = 0.0;
+    for (int t = 0; t < 10; ++t) P[t] = 0.0;
+    const V3 o[6] = {sub(b3, b2), sub(b1, b3), sub(b2, b1), b3, b1, b2};
+    // sign pattern of q_k in dPhi_1..3
+    constexpr int QSGN[6][3] = {{0, -1, 1}, {1, 0, -1}, {-1, 1, 0}, {0, 0, 1}, {1, 0, 0}, {0, 1, 0}};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
+        // one row of weights at a time: the scheduler would otherwise issue all
+        // 72 gathers up front and hold them, at one wavefront per SIMD
+        __builtin_amdgcn_sched_barrier(0);
+        double gk[6], gm[6];
+        gather_row<6>(A, A.slot_base[e * 6 + k], A.slot_cp[e * 6 + k], gk, gm);
         const int i = nib(NED3_START, k), j = nib(NED3_END, k);
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
             const int m = nib(NED3_START, l), n = nib(NED3_END, l);
             const double ss = s[k] * s[l];
-            const double gk = GK[k][l] * ss;
-            const double gm = GM[k][l] * ss;
-            Phi += gk * dot(o[k], o[l]);
-            q[k] = add(q[k], scale(o[l], gk));
-            q[l] = add(q[l], scale(o[k], gk));
-            Q[j][n] += gm * (1.0 + (i == m));
-            Q[j][m] -= gm * (1.0 + (i == n));
-            Q[i][n] -= gm * (1.0 + (j == m));
-            Q[i][m] += gm * (1.0 + (j == n));
+            const double wk = gk[l] * ss;
+            const double wm = gm[l] * ss;
+            Phi += wk * dot(o[k], o[l]);
+            // q_k += wk o_l and q_l += wk o_k, folded into dPhi
+            const V3 ol = scale(o[l], wk), ok = scale(o[k], wk);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                if (QSGN[k][t] > 0) dPhi[t] = add(dPhi[t], ol);
+                if (QSGN[k][t] < 0) dPhi[t] = sub(dPhi[t], ol);
+                if (QSGN[l][t] > 0) dPhi[t] = add(dPhi[t], ok);
+                if (QSGN[l][t] < 0) dPhi[t] = sub(dPhi[t], ok);
+            }
+            P[tri_index(j, n)] += wm * (1.0 + (i == m));
+            P[tri_index(j, m)] -= wm * (1.0 + (i == n));
+            P[tri_index(i, n)] -= wm * (1.0 + (j == m));
+            P[tri_index(i, m)] += wm * (1.0 + (j == n));
         }
+        // fold this row in now (the sums would otherwise be sunk into the
+        // conditional output blocks with all 72 weights live until there)
+        pin(Phi);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) pin(dPhi[t]);
+#pragma unroll
+        for (int t = 0; t < 10; ++t) pin(P[t]);
     }
+    // cofactor vectors after the weight loop (not live during it)
+    V3 c[4];
+    c[1] = cross(b2, b3);
+    c[2] = cross(b3, b1);
+    c[3] = cross(b1, b2);
+    c[0] = neg(add(add(c[1], c[2]), c[3]));
+    const double J = dot(b1, c[1]);
+    const double aJ = fabs(J);
     double Psi = 0.0;
     V3 w[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        w[a] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 4; ++a) w[a] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-            Psi += Q[a][bb] * dot(g.c[a], g.c[bb]);
-            w[a] = add(w[a], scale(g.c[bb], Q[a][bb] + Q[bb][a]));
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int bb = a; bb < 4; ++bb) {
+            const double p = P[tri_index(a, bb)];
+            Psi += p * dot(c[a], c[bb]);
+            if (a == bb) {
+                w[a] = add(w[a], scale(c[a], 2.0 * p));
+            } else {
+                w[a] = add(w[a], scale(c[bb], p));
+                w[bb] = add(w[bb], scale(c[a], p));
+            }
         }
     }
     const double ca = A.a ? A.a[e] : 1.0;
@@ -808,30 +919,23 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
     if (A.ga) A.ga[e] = (2.0 / 3.0) * Phi / aJ;
     if (A.gb) A.gb[e] = Psi / (120.0 * aJ);
     if (A.partials) {
-        const V3 dPhi[3] = {add(sub(q[1], q[2]), q[4]), add(sub(q[2], q[0]), q[5]),
-                            add(sub(q[0], q[1]), q[3])};
         const V3 w1 = sub(w[1], w[0]), w2 = sub(w[2], w[0]), w3 = sub(w[3], w[0]);
-        const V3 dPsi[3] = {add(cross(w2, g.b3), cross(g.b2, w3)), add(cross(g.b3, w1), cross(w3, g.b1)),
-                            add(cross(w1, g.b2), cross(g.b1, w2))};
+        const V3 dPsi[3] = {add(cross(w2, b3), cross(b2, w3)), add(cross(b3, w1), cross(w3, b1)),
+                            add(cross(w1, b2), cross(b1, w2))};
         const double fk = ca * (2.0 / 3.0) / aJ;
         const double fm = cb * (1.0 / 120.0) / aJ;
         V3 d0 = {0.0, 0.0, 0.0};
-        double* out = A.partials + e * 12;
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) {
-            const V3 cj = g.c[jj + 1];
-            const V3 dj = add(scale(sub(dPhi[jj], scale(cj, Phi / g.J)), fk),
-                              scale(sub(dPsi[jj], scale(cj, Psi / g.J)), fm));
-            out[3 * (jj + 1)] = dj.x;
-            out[3 * (jj + 1) + 1] = dj.y;
-            out[3 * (jj + 1) + 2] = dj.z;
+            const V3 cj = c[jj + 1];
+            const V3 dj = add(scale(sub(dPhi[jj], scale(cj, Phi / J)), fk),
+                              scale(sub(dPsi[jj], scale(cj, Psi / J)), fm));
+            store_vertex3(A, e * 4 + jj + 1, dj);
             d0 = sub(d0, dj);
         }
-        out[0] = d0.x;
-        out[1] = d0.y;
-        out[2] = d0.z;
+        store_vertex3(A, e * 4, d0);
     }
-    if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+    if (!(aJ > 0.0) || !isfinite(J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
 // 3D Raviart-Thomas
@@ -844,7 +948,8 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
     double GK[4][4], GM[4][4];
-    gather_weights<4>(A, e, GK, GM);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gather_row<4>(A, A.slot_base[e * 4 + k], A.slot_cp[e * 4 + k], GK[k], GM[k]);
     const GeoRT3 g = geo_rt3(x);
     double s[4];
     rt3_signs(gid, s);
@@ -887,7 +992,6 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
         for (int p = 1; p < 4; ++p) rp = add(rp, scale(g.y[p], rho[p]));
         const V3 c[3] = {cross(g.y[2], g.y[3]), cross(g.y[3], g.y[1]), cross(g.y[1], g.y[2])};
         V3 d0 = {0.0, 0.0, 0.0};
-        double* out = A.partials + e * 12;
 #pragma unroll
         for (int a = 1; a < 4; ++a) {
             const V3 dOm = add(sub(scale(add(S, g.y[a]), 2.0 * hM), scale(add(scale(S, rho[a]), rp), 5.0)),
@@ -896,14 +1000,10 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
             const V3 dK = scale(ck, -ca * 1.5 * hK / (aJ * g.J));
             const V3 dM = scale(sub(dOm, scale(ck, Omega / g.J)), cb / (120.0 * aJ));
             const V3 da = add(dK, dM);
-            out[3 * a] = da.x;
-            out[3 * a + 1] = da.y;
-            out[3 * a + 2] = da.z;
+            store_vertex3(A, e * 4 + a, da);
             d0 = sub(d0, da);
         }
-        out[0] = d0.x;
-        out[1] = d0.y;
-        out[2] = d0.z;
+        store_vertex3(A, e * 4, d0);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
@@ -918,7 +1018,8 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
         x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
     }
     double GK[3][3], GM[3][3];
-    gather_weights<3>(A, e, GK, GM);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gather_row<3>(A, A.slot_base[e * 3 + k], A.slot_cp[e * 3 + k], GK[k], GM[k]);
     const Geo2 g = geo2(x);
     double s[3];
     tri_signs(gid, s);
@@ -966,50 +1067,65 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
         const V2 dPsi[2] = {{w2.y, -w2.x}, {-w1.y, w1.x}};
         const double fk = -ca * 2.0 * hK / (aJ * g.J);
         const double fm = cb / (24.0 * aJ);
-        double* out = A.partials + e * 6;
         double d0x = 0.0, d0y = 0.0;
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
             const V2 cj = g.c[jj + 1];
             const double dx = fk * cj.x + fm * (dPsi[jj].x - cj.x * Psi / g.J);
             const double dy = fk * cj.y + fm * (dPsi[jj].y - cj.y * Psi / g.J);
-            out[2 * (jj + 1)] = dx;
-            out[2 * (jj + 1) + 1] = dy;
+            store_vertex2(A, e * 3 + jj + 1, dx, dy);
             d0x -= dx;
             d0y -= dy;
         }
-        out[0] = d0x;
-        out[1] = d0y;
+        store_vertex2(A, e * 3, d0x, d0y);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
 template <int KC>
 __global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
+    // a contiguous range of elements; neighbouring elements share rows of the
+    // upstream weights, and that reuse then stays in one L2.
+    const int64_t per = gridDim.x / 8;
+    const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t e = blk * blockDim.x + threadIdx.x;
     if (e >= A.T) return;
     if constexpr (KC == 2) bwd_ned3(A, e);
     else if constexpr (KC == 1) bwd_rt3(A, e);
     else bwd_tri(A, e);
 }
 
-// gnodes[v] = sum of the per-element vertex derivatives, ascending element order.
+// gnodes[v] = sum of the vertex derivatives of the node's incidences, which
+// are stored contiguously in node order (ascending element within a node).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const int32_t* node_slot,
-                                                      const double* partials, int64_t V, double* gnodes) {
+__global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const double* partials,
+                                                      int64_t V, double* gnodes) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     double acc[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
-    const int j1 = node_ptr[v + 1];
-    for (int j = node_ptr[v]; j < j1; ++j) {
-        const int64_t q = node_slot[j];
+    const int64_t j1 = node_ptr[v + 1];
+#pragma unroll 4
+    for (int64_t j = node_ptr[v]; j < j1; ++j) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] += partials[q * DIM + c];
+        for (int c = 0; c < DIM; ++c) acc[c] += partials[j * DIM + c];
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) gnodes[v * DIM + c] = acc[c];
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static fem_status zero_f64(double* p, int64_t n, hipStream_t s) {
+    if (!p || n <= 0) return FEM_OK;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, 0.0);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
 }
 
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
@@ -1017,10 +1133,16 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
                            double* ga, double* gb, double* gnodes, hipStream_t s) {
     const int kc = kind_code(m->dim, kind);
     const int nv = m->dim + 1;
+    if (!gK && !gM) {  // L = 0: every derivative is zero
+        if (fem_status st = zero_f64(ga, m->T, s)) return st;
+        if (fem_status st = zero_f64(gb, m->T, s)) return st;
+        return zero_f64(gnodes, m->V * m->dim, s);
+    }
     if (gnodes) {
         if (fem_status st = build_node_map(m, s)) return st;
         if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, m->T * nv * m->dim));
     }
+    if (fem_status st = build_slot_map(m, ds, s)) return st;
     BwdArgs A;
     A.elems = m->elems;
     A.nodes = nodes;
@@ -1028,16 +1150,15 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.b = b;
     A.gK = gK;
     A.gM = gM;
-    A.elems2dofs = ds.elems2dofs;
-    A.rowptr = ds.pat.rowptr;
-    A.slot_rank = ds.pat.slot_rank;
-    A.colpos = ds.pat.colpos;
+    A.slot_base = ds.slot_base;
+    A.slot_cp = ds.slot_cp;
     A.ga = ga;
     A.gb = gb;
     A.partials = gnodes ? m->elem_partials : nullptr;
+    A.node_rank = m->node_rank;
     A.T = m->T;
     A.err_word = m->err_word;
-    const unsigned grid = (unsigned)((m->T + 255) / 256);
+    const unsigned grid = (unsigned)(((m->T + 255) / 256 + 7) / 8 * 8);
     if (m->T > 0) {
         if (kc == 2) hipLaunchKernelGGL(k_backward<2>, dim3(grid), dim3(256), 0, s, A);
         else if (kc == 1) hipLaunchKernelGGL(k_backward<1>, dim3(grid), dim3(256), 0, s, A);
@@ -1047,10 +1168,10 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     if (gnodes && m->V > 0) {
         const unsigned gv = (unsigned)((m->V + 255) / 256);
         if (m->dim == 3)
-            hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->node_slot,
+            hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr,
                                m->elem_partials, m->V, gnodes);
         else
-            hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->node_slot,
+            hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr,
                                m->elem_partials, m->V, gnodes);
         FEM_HIP(hipGetLastError());
     }

@@ -74,6 +74,10 @@ struct DofSet {
     int32_t* rs_ptr = nullptr;     // [n+1] start of each dof's run of slots
     int32_t* rs_slot = nullptr;    // [T*nloc] slots (e*nloc + k) sorted by (dof, slot)
     Pattern pat;
+    // adjoint gather map, element-major: for slot e*nloc + k, the CSR position
+    // of its row's first entry and its column-offset record (built on first use)
+    int64_t* slot_base = nullptr;  // [T*nloc]
+    uint64_t* slot_cp = nullptr;   // [T*nloc]
 };
 
 }  // namespace fem
@@ -90,9 +94,9 @@ struct fem_mesh_s {
     fem::DofSet edges;
     fem::DofSet faces;
     // backward scratch
-    double* elem_partials = nullptr; // [T][(dim+1)*dim]
+    double* elem_partials = nullptr; // [T*(dim+1)][dim], incidences in node order
     int32_t* node_ptr = nullptr;     // [V+1]
-    int32_t* node_slot = nullptr;    // [T*(dim+1)] (e*(dim+1)+v) sorted by node
+    int32_t* node_rank = nullptr;    // [T*(dim+1)] position of incidence e*(dim+1)+v in node order
     int* err_word = nullptr;         // device error word
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;       // everything to free
@@ -124,6 +128,7 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems,
                           hipStream_t s);
 fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s);
 fem_status build_node_map(fem_mesh m, hipStream_t s);
+fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s);
 fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s);
 int ema_index(int nt);  // 128 -> 0, 256 -> 1
 int ema_lds_bytes(int kind_code, int R, int pmax, int max_slots);
@@ -175,5 +180,10 @@ int batch_blocks_per_cu(int rows_per_tile, int lds_bytes);
 int cu_count();
 int default_rows_per_tile(int kind_code);
 fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s);
+// batched element-major tiles (workgroups of 256 lanes)
+fem_status launch_batch_ema(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
+                            int schedule, int grid, int lds_bytes, unsigned* counters,
+                            hipStream_t s);
+int batch_ema_blocks_per_cu(int lds_bytes);
 
 }  // namespace fem

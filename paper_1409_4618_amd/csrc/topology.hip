@@ -489,13 +489,51 @@ __global__ void k_node_keys(const int32_t* elems, int64_t n, uint64_t* keys, uin
     atomicAdd(&counts[v], 1);
 }
 
+// Adjoint gather map: per slot (element-major order) the row start of the
+// slot's dof and the slot's column-offset record, so the adjoint reaches the
+// n_local^2 positions of an element with one level of indirection.
+__global__ void k_slot_map(const int32_t* elems2dofs, const int64_t* rowptr, const int32_t* slot_rank,
+                           const uint8_t* colpos, int cp_stride, int64_t n, int64_t* base,
+                           uint64_t* cp) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    base[s] = rowptr[elems2dofs[s]];
+    const int64_t j = slot_rank[s];
+    cp[s] = cp_stride == 8 ? reinterpret_cast<const uint64_t*>(colpos)[j]
+                           : (uint64_t)reinterpret_cast<const uint32_t*>(colpos)[j];
+}
+
+fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
+    if (ds.slot_base) return FEM_OK;
+    const int64_t n = m->T * ds.nloc;
+    FEM_HIP(dmalloc(m, &ds.slot_base, n > 0 ? n : 1));
+    FEM_HIP(dmalloc(m, &ds.slot_cp, n > 0 ? n : 1));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_slot_map, dim3(nblk(n)), dim3(TB), 0, s, ds.elems2dofs, ds.pat.rowptr,
+                           ds.pat.slot_rank, ds.pat.colpos, ds.pat.cp_stride, n, ds.slot_base,
+                           ds.slot_cp);
+        FEM_HIP(hipGetLastError());
+    }
+    return FEM_OK;
+}
+
+// rank[perm[i]] = i
+__global__ void k_invert_perm(const uint32_t* perm, int64_t n, int32_t* rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rank[perm[i]] = (int32_t)i;
+}
+
+// Node map of the adjoint: the (element, vertex) incidences sorted by node
+// (stable, so ascending element within a node); node_ptr delimits each node's
+// run and node_rank gives each incidence its position in that order, where the
+// adjoint writes the incidence's vertex derivative.
 fem_status build_node_map(fem_mesh m, hipStream_t s) {
     if (m->node_ptr) return FEM_OK;
     const int64_t n = m->T * (m->dim + 1);
     TmpBufs tb;
     FEM_HIP(tb.alloc(n));
     FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
-    FEM_HIP(dmalloc(m, &m->node_slot, n));
+    FEM_HIP(dmalloc(m, &m->node_rank, n));
     FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_node_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, tb.keys, tb.vals,
                        m->node_ptr);
@@ -503,7 +541,8 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
     FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->node_ptr), m->V + 1, s));
     FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n,
                              bit_length((uint64_t)m->V - 1), s));
-    FEM_HIP(hipMemcpyAsync(m->node_slot, tb.vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_invert_perm, dim3(nblk(n)), dim3(TB), 0, s, tb.vals, n, m->node_rank);
+    FEM_HIP(hipGetLastError());
     FEM_HIP(hipStreamSynchronize(s));
     return FEM_OK;
 }

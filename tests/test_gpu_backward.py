@@ -115,3 +115,37 @@ def test_adjoint_matches_central_differences(case):
         am[e] -= h
         fd = (L(tn, ap, tb) - L(tn, am, tb)) / (2 * h)
         assert abs(fd - ga[e].item()) <= 1e-6 * max(1.0, ga.abs().max().item())
+
+
+@pytest.mark.parametrize("case", ["ned3", "rt3", "ned2"])
+def test_adjoint_separate_and_missing_weights(case):
+    """gK and gM independent, then gM absent (NULL: its part is zero), then both
+    absent (L = 0, every derivative zero)."""
+    import torch
+    import paper_1409_4618_amd as fem
+    nodes, elems, kind, a, b, rng = make_case(case, 23)
+    say(f"[gpu] adjoint with separate / missing weights: {case}")
+    csr, topo = oracle.assemble(nodes, elems, kind, a=a, b=b)
+    wK = rng.normal(size=csr.nnz)
+    wM = rng.normal(size=csr.nnz)
+    pos = positions(csr, oracle.element_dofs(topo, kind))
+    tn, te, ta, tb = dev_tensors(nodes, elems, a, b)
+    mesh = fem.Mesh(tn, te)
+    mesh.pattern(kind)
+    for wm, tag in ((wM, "gK, gM"), (None, "gK only")):
+        wm_o = np.zeros_like(wK) if wm is None else wm
+        ga_o, gb_o = grad_coefficients(nodes, elems, kind, topo, pos, wK, wm_o)
+        gn_o = grad_nodes(nodes, elems, kind, topo, pos, wK, wm_o, a, b)
+        tK = torch.tensor(wK, device=tn.device)
+        tM = None if wm is None else torch.tensor(wm, device=tn.device)
+        gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, tK, tM)
+        mesh.status()
+        for got, ref, nm in ((ga, ga_o, "a"), (gb, gb_o, "b"), (gn, gn_o, "x")):
+            got = got.cpu().numpy()
+            denom = max(np.abs(ref).max(), 1e-300)
+            err = np.abs(got - ref).max() / denom if np.abs(ref).max() > 0 else np.abs(got).max()
+            say(f"    {tag}: dL/d{nm} max rel err {err:.2e}")
+            assert err <= GTOL, (tag, nm, err)
+    gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, None, None)
+    mesh.status()
+    assert not bool(gn.abs().max() > 0) and not bool(ga.abs().max() > 0) and not bool(gb.abs().max() > 0)

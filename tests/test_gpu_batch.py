@@ -47,7 +47,7 @@ def test_single_meshes_match_oracle(batch_setup):
         assert rel_fro(M.cpu().numpy(), csr.Mv) <= TOL
 
 
-@pytest.mark.parametrize("rows", [64, 128, 256])
+@pytest.mark.parametrize("rows", [0, 64, 128, 256])
 @pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_batch_equals_single_launches(batch_setup, rows, schedule):
     import torch
