@@ -58,8 +58,9 @@ static void fill_ema(const DofSet& ds, int nt, MeshDev* md) {
     const Pattern::Ema& E = ds.pat.ema[ema_index(nt)];
     md->n_tiles = E.n_tiles;
     md->tile_eptr = E.eptr;
-    md->tile_elems = E.elems;
-    md->ema_joff = E.joff;
+
+    md->ema_ent = E.ent;
+    md->ema_rec = E.rec;
     md->ema_R = E.R;
     md->ema_pmax = E.pmax;
     md->ema_max_slots = E.max_slots;

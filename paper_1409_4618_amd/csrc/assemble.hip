@@ -406,7 +406,7 @@ int batch_blocks_per_cu(int R, int bytes) {
 // ===========================================================================
 int ema_lds_bytes(int kc, int R, int pmax, int max_slots) {
     const int sd = kc == 2 ? max_slots : 0;
-    return 8 * (pmax + sd) + 4 * (3 * R + 1) + 2 * max_slots + 16;
+    return 8 * (pmax + sd) + 4 * (3 * R + 1) + 16;
 }
 
 template <int B, int E, class F>
@@ -497,21 +497,18 @@ __device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T&
     }
 }
 
-__device__ __forceinline__ uint32_t ema_jk(const uint32_t jw[4], int k) {
-    return (jw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-}
-
-// One pass (K or M) of a lane's element: rows k that belong to the tile.
+// One pass (K or M) of a lane's element: rows k that belong to the tile
+// (bit k of mask). rb: LDS base of row k, cp: its column offsets, jk (3D
+// Nedelec): the slot's index in the tile's diagonal buffer.
 template <int KC, bool MASS>
-__device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, const uint32_t jw[4],
-                                            const int rb[KT<KC>::NLOC],
+__device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, uint32_t mask,
+                                            const int jk[KT<KC>::NLOC], const int rb[KT<KC>::NLOC],
                                             const uint64_t cp[KT<KC>::NLOC], double* out,
                                             double* sdiag) {
     constexpr int NLOC = KT<KC>::NLOC;
     static_for<0, NLOC>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        const uint32_t jk = ema_jk(jw, k);
-        if (jk != 0xFFFFu) {
+        if ((mask >> k) & 1u) {
             pin_state<MASS>(st);
             const typename EmaPass<KC, MASS>::T& sk = st;
             const int base = rb[k];
@@ -519,7 +516,7 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, c
             const double r = ema_row<KC, MASS, k>(sk);
             const double d = ema_entry<KC, MASS, k, k>(sk, r);
             if constexpr (KC == 2) {
-                sdiag[jk] = d;
+                sdiag[jk[k]] = d;
             } else {
                 atomicAdd(&out[base + (int)((c >> (8 * k)) & 0xFFu)], d);
             }
@@ -545,7 +542,6 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     const int64_t p0 = md.rowptr[r0];
     const int nt = (int)(md.rowptr[r1] - p0);
     const int js0 = md.rs_ptr[r0];
-    const int ns = md.rs_ptr[r1] - js0;
     const int e_beg = md.tile_eptr[tile];
     const int ne = md.tile_eptr[tile + 1] - e_beg;  // <= NT (checked when the tiles are built)
     // LDS layout
@@ -554,23 +550,26 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     int* rowbase = reinterpret_cast<int*>(sdiag + (KC == 2 ? md.ema_max_slots : 0));
     int* rowslot = rowbase + R;
     int* rowdiag = rowslot + R + 1;
-    uint16_t* slotrow = reinterpret_cast<uint16_t*>(rowdiag + R);
 
-    // this lane's element: record and node ids first, so their latency
-    // overlaps the LDS set-up below
+    // this lane's element: entry, node ids and slot records first, so their
+    // latency overlaps the LDS set-up below
     const bool have = tid < ne;
     int64_t e = 0;
-    uint32_t jw[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    uint32_t mask = 0;
     int gid[NV];
+    uint64_t cp[NLOC];
 #pragma unroll
     for (int v = 0; v < NV; ++v) gid[v] = 0;
+#pragma unroll
+    for (int k = 0; k < NLOC; ++k) cp[k] = 0;
     if (have) {
-        e = md.tile_elems[e_beg + tid];
-        const uint4 jq = reinterpret_cast<const uint4*>(md.ema_joff)[e_beg + tid];
-        jw[0] = jq.x;
-        jw[1] = jq.y;
-        jw[2] = jq.z;
-        jw[3] = jq.w;
+        const int2 en = md.ema_ent[e_beg + tid];
+        e = en.x;
+        mask = (uint32_t)en.y & 0x3Fu;
+        const int64_t roff = (int64_t)js0 + ((uint32_t)en.y >> 8);
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k)
+            if ((mask >> k) & 1u) cp[k] = md.ema_rec[roff + __popc(mask & ((1u << k) - 1u))];
         if constexpr (NV == 4) {
             const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
             gid[0] = q.x;
@@ -582,23 +581,19 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
             for (int v = 0; v < NV; ++v) gid[v] = md.elems[e * NV + v];
         }
     }
-    // phase 0: clear the values, row bases, slot -> row table
+    // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;
     for (int lr = tid; lr < nrows; lr += NT) {
         rowbase[lr] = (int)(md.rowptr[r0 + lr] - p0);
-        const int a = md.rs_ptr[r0 + lr] - js0;
-        const int b = md.rs_ptr[r0 + lr + 1] - js0;
-        rowslot[lr] = a;
-        for (int j = a; j < b; ++j) slotrow[j] = (uint16_t)lr;
+        if constexpr (KC == 2) rowslot[lr] = md.rs_ptr[r0 + lr] - js0;
     }
-    if (tid == 0) rowslot[nrows] = ns;
+    if (KC == 2 && tid == 0) rowslot[nrows] = md.rs_ptr[r1] - js0;
     __syncthreads();
 
-    // gather (coordinates, coefficients, scatter offsets), then the element state
+    // gather (coordinates, coefficients), then the element state
     typename EmaElem<KC>::T st;
     double ca = 1.0, cb = 1.0;
-    int rb[NLOC];
-    uint64_t cp[NLOC];
+    int rb[NLOC], jk[NLOC];
     bool bad = false;
     if (have) {
         double x[NV][DIM];
@@ -610,14 +605,15 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if (md.b) cb = md.b[e];
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) {
-            const uint32_t jk = ema_jk(jw, k);
             rb[k] = 0;
-            cp[k] = 0;
-            if (jk != 0xFFFFu) {
-                cp[k] = load_colpos<NLOC>(md.colpos, (int64_t)js0 + jk);
-                const int lr = slotrow[jk];
+            jk[k] = 0;
+            if ((mask >> k) & 1u) {
+                const int lr = (int)((cp[k] >> 48) & 0xFFu);
                 rb[k] = rowbase[lr];
-                if constexpr (KC == 2) rowdiag[lr] = (int)((cp[k] >> (8 * k)) & 0xFFu);
+                if constexpr (KC == 2) {
+                    jk[k] = rowslot[lr] + (int)(cp[k] >> 56);
+                    rowdiag[lr] = (int)((cp[k] >> (8 * k)) & 0xFFu);
+                }
             }
         }
         st = ema_elem<KC>(gid, x, ca, cb);
@@ -632,7 +628,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if (dst) {
             if (have) {
                 typename EmaPass<KC, MASS>::T ps = ema_pass_state<KC, MASS>(st);
-                ema_scatter<KC, MASS>(ps, jw, rb, cp, out, sdiag);
+                ema_scatter<KC, MASS>(ps, mask, jk, rb, cp, out, sdiag);
             }
             __syncthreads();
             if constexpr (KC == 2) {

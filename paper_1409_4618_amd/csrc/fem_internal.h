@@ -58,8 +58,15 @@ struct Pattern {
         int R = 0;
         int64_t n_tiles = 0;
         int32_t* eptr = nullptr;    // [n_tiles+1]
-        int32_t* elems = nullptr;   // [n_entries]
-        uint16_t* joff = nullptr;   // [n_entries][8]
+        int32_t* elems = nullptr;   // [n_entries] (build only)
+        uint16_t* joff = nullptr;   // [n_entries][8] (build only)
+        // entry i of a tile: (element, in-tile local dofs (6 bits) | offset of
+        // its first record in the tile << 8)
+        int2* ent = nullptr;        // [n_entries]
+        // record of an in-tile slot, grouped by entry, ascending local dof:
+        // column offsets (bits 0..47), tile-local row (48..55), rank of the
+        // slot in its row's slot list (56..63)
+        uint64_t* rec = nullptr;    // [n_slots]
         int max_elems = 0;          // largest tile element list
         int max_slots = 0;          // most slots of one tile
         int pmax = 0;               // most matrix entries of one tile
@@ -154,11 +161,10 @@ struct MeshDev {
     int32_t kind_code;      // 0: 2D (both kinds), 1: 3D Raviart-Thomas, 2: 3D Nedelec
     int32_t pad0;
     int* err_word;
-    // element-major tiles: element list of each tile, tile-local slot of each
-    // local dof of an entry
+    // element-major tiles: entry range of each tile, entries, slot records
     const int32_t* tile_eptr;
-    const int32_t* tile_elems;
-    const uint16_t* ema_joff;
+    const int2* ema_ent;
+    const uint64_t* ema_rec;
     int32_t ema_R;
     int32_t ema_pmax;
     int32_t ema_max_slots;

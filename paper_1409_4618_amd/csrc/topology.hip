@@ -16,6 +16,8 @@
 // pairs get their CSR position (the scatter map). The map is stored compactly
 // as, for each slot in row-sorted order, the byte offsets of its n_local
 // columns inside the row.
+#include <algorithm>
+
 #include "element.h"
 #include "fem_internal.h"
 
@@ -732,9 +734,82 @@ static void ema_free(Pattern::Ema& e) {
     if (e.eptr) (void)hipFree(e.eptr);
     if (e.elems) (void)hipFree(e.elems);
     if (e.joff) (void)hipFree(e.joff);
+    if (e.ent) (void)hipFree(e.ent);
+    if (e.rec) (void)hipFree(e.rec);
     e.eptr = nullptr;
     e.elems = nullptr;
     e.joff = nullptr;
+    e.ent = nullptr;
+    e.rec = nullptr;
+}
+
+// Row of every slot in row-sorted order.
+__global__ void k_slot_rows(const int32_t* rs_ptr, int64_t n_rows, int32_t* slot_row) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    for (int32_t j = rs_ptr[r]; j < rs_ptr[r + 1]; ++j) slot_row[j] = (int32_t)r;
+}
+
+// Entries and slot records of the element-major tiles (one thread per tile,
+// entries in their final order).
+__global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_t* elems,
+                              const uint16_t* joff, const int32_t* rs_ptr, const int32_t* slot_row,
+                              const uint8_t* colpos, int cp_stride, int nloc, int R, int2* ent,
+                              uint64_t* rec, int* overflow) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int32_t js0 = rs_ptr[t * R];
+    uint32_t off = 0;
+    for (int32_t i = eptr[t]; i < eptr[t + 1]; ++i) {
+        uint32_t mask = 0, cnt = 0;
+        for (int k = 0; k < nloc; ++k) {
+            const uint32_t jk = joff[(int64_t)i * 8 + k];
+            if (jk == 0xFFFFu) continue;
+            const int32_t j = js0 + (int32_t)jk;
+            const int32_t r = slot_row[j];
+            const uint64_t lr = (uint64_t)(r - t * R);
+            const uint64_t rank = (uint64_t)(j - rs_ptr[r]);
+            if (lr > 255u || rank > 255u) atomicOr(overflow, 1);
+            const uint64_t cp = cp_stride == 8 ? reinterpret_cast<const uint64_t*>(colpos)[j]
+                                               : (uint64_t)reinterpret_cast<const uint32_t*>(colpos)[j];
+            rec[js0 + off + cnt] = (cp & 0xFFFFFFFFFFFFull) | (lr << 48) | (rank << 56);
+            mask |= 1u << k;
+            ++cnt;
+        }
+        if (off > 0xFFFFFFu) atomicOr(overflow, 1);
+        ent[i] = make_int2(elems[i], (int)(mask | (off << 8)));
+        off += cnt;
+    }
+}
+
+static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream_t s) {
+    const int64_t n_slots = m->T * ds.nloc;
+    int32_t n_ent = 0;
+    FEM_HIP(hipMemcpyAsync(&n_ent, E.eptr + E.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    FEM_HIP(hipMalloc((void**)&E.ent, (size_t)std::max<int32_t>(n_ent, 1) * sizeof(int2)));
+    FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * sizeof(uint64_t)));
+    TmpBufs tb;
+    FEM_HIP(tb.alloc(std::max<int64_t>(n_slots, 1)));
+    int32_t* slot_row = reinterpret_cast<int32_t*>(tb.vals);
+    int* overflow = reinterpret_cast<int*>(tb.scan);
+    FEM_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_slot_rows, dim3(nblk(ds.pat.n_rows)), dim3(TB), 0, s, ds.rs_ptr, ds.pat.n_rows,
+                       slot_row);
+    hipLaunchKernelGGL(k_ema_records, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.eptr, E.n_tiles, E.elems,
+                       E.joff, ds.rs_ptr, slot_row, ds.pat.colpos, ds.pat.cp_stride, ds.nloc, E.R,
+                       E.ent, E.rec, overflow);
+    FEM_HIP(hipGetLastError());
+    int h = 0;
+    FEM_HIP(hipMemcpyAsync(&h, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    if (h) return fail(FEM_EOVERFLOW, "fem_pattern: a tile row or slot index exceeds its record field");
+    // the build-only arrays
+    (void)hipFree(E.elems);
+    (void)hipFree(E.joff);
+    E.elems = nullptr;
+    E.joff = nullptr;
+    return FEM_OK;
 }
 
 // Build the element-major tiles for workgroups of nt threads: pick the number of
@@ -761,13 +836,15 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
                 ema_free(cand);
                 return fail(FEM_EOVERFLOW, "fem_pattern: a row tile needs more LDS than the device has");
             }
-            if (fem_status so = ema_order(cand, ds.nloc, s)) {
+            fem_status so = ema_order(cand, ds.nloc, s);
+            if (so == FEM_OK) so = ema_records(m, ds, cand, s);
+            if (so != FEM_OK) {
                 ema_free(cand);
                 return so;
             }
             m->allocs.push_back(cand.eptr);
-            m->allocs.push_back(cand.elems);
-            m->allocs.push_back(cand.joff);
+            m->allocs.push_back(cand.ent);
+            m->allocs.push_back(cand.rec);
             cand.NT = nt;
             cand.built = true;
             cand.usable = cand.max_elems <= nt;
