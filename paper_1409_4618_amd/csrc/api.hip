@@ -57,7 +57,7 @@ static bool use_row_path() {
 static void fill_ema(const DofSet& ds, int nt, MeshDev* md) {
     const Pattern::Ema& E = ds.pat.ema[ema_index(nt)];
     md->n_tiles = E.n_tiles;
-    md->tile_eptr = E.eptr;
+    md->ema_hdr = E.hdr;
 
     md->ema_ent = E.ent;
     md->ema_rec = E.rec;

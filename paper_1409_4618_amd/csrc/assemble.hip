@@ -536,14 +536,17 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
     const int tid = threadIdx.x;
     const int R = md.ema_R;
-    const int64_t r0 = tile * R;
-    const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
-    const int nrows = (int)(r1 - r0);
-    const int64_t p0 = md.rowptr[r0];
-    const int nt = (int)(md.rowptr[r1] - p0);
-    const int js0 = md.rs_ptr[r0];
-    const int e_beg = md.tile_eptr[tile];
-    const int ne = md.tile_eptr[tile + 1] - e_beg;  // <= NT (checked when the tiles are built)
+    // header of the tile
+    const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile];
+    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile + 1];
+    const int64_t r0 = h0.x;
+    const int nrows = h0.y;
+    const int64_t r1 = r0 + nrows;
+    const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)h0.w << 32) | (uint64_t)(uint32_t)h0.z);
+    const int nt = h1.x;
+    const int js0 = h1.y;
+    const int e_beg = h1.z;
+    const int ne = h1.w;  // <= NT (checked when the tiles are built)
     // LDS layout
     double* out = reinterpret_cast<double*>(smem);
     double* sdiag = out + md.ema_pmax;

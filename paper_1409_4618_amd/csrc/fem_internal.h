@@ -67,6 +67,9 @@ struct Pattern {
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)
         uint64_t* rec = nullptr;    // [n_slots]
+        // per-tile header, 8 ints: r0, rows, p0 (lo, hi), values, first
+        // slot, first entry, entries
+        int32_t* hdr = nullptr;     // [n_tiles][8]
         int max_elems = 0;          // largest tile element list
         int max_slots = 0;          // most slots of one tile
         int pmax = 0;               // most matrix entries of one tile
@@ -161,8 +164,8 @@ struct MeshDev {
     int32_t kind_code;      // 0: 2D (both kinds), 1: 3D Raviart-Thomas, 2: 3D Nedelec
     int32_t pad0;
     int* err_word;
-    // element-major tiles: entry range of each tile, entries, slot records
-    const int32_t* tile_eptr;
+    // element-major tiles: headers, entries, slot records
+    const int32_t* ema_hdr;
     const int2* ema_ent;
     const uint64_t* ema_rec;
     int32_t ema_R;

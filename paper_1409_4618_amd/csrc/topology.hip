@@ -17,6 +17,7 @@
 // as, for each slot in row-sorted order, the byte offsets of its n_local
 // columns inside the row.
 #include <algorithm>
+#include <vector>
 
 #include "element.h"
 #include "fem_internal.h"
@@ -736,6 +737,8 @@ static void ema_free(Pattern::Ema& e) {
     if (e.joff) (void)hipFree(e.joff);
     if (e.ent) (void)hipFree(e.ent);
     if (e.rec) (void)hipFree(e.rec);
+    if (e.hdr) (void)hipFree(e.hdr);
+    e.hdr = nullptr;
     e.eptr = nullptr;
     e.elems = nullptr;
     e.joff = nullptr;
@@ -782,6 +785,37 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
     }
 }
 
+// Per-tile headers (8 ints: r0, rows, p0 lo/hi, values, first slot, first
+// entry, entries), so a workgroup reads its tile's bounds with one load.
+__global__ void k_tile_headers(int64_t n_tiles, int R, int64_t n_rows, const int64_t* rowptr,
+                               const int32_t* rs_ptr, const int32_t* eptr, int32_t* hdr) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t r0 = t * R;
+    const int64_t r1 = (r0 + R < n_rows) ? r0 + R : n_rows;
+    const int64_t p0 = rowptr[r0];
+    int32_t* h = hdr + t * 8;
+    h[0] = (int32_t)r0;
+    h[1] = (int32_t)(r1 - r0);
+    h[2] = (int32_t)(uint32_t)(uint64_t)p0;
+    h[3] = (int32_t)((uint64_t)p0 >> 32);
+    h[4] = (int32_t)(rowptr[r1] - p0);
+    h[5] = rs_ptr[r0];
+    h[6] = eptr[t];
+    h[7] = eptr[t + 1] - eptr[t];
+}
+
+static fem_status ema_headers(DofSet& ds, Pattern::Ema& E, hipStream_t s) {
+    if (ds.pat.n_rows >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 rows");
+    FEM_HIP(hipMalloc((void**)&E.hdr, (size_t)std::max<int64_t>(E.n_tiles, 1) * 8 * sizeof(int32_t)));
+    if (E.n_tiles == 0) return FEM_OK;
+    hipLaunchKernelGGL(k_tile_headers, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.n_tiles, E.R,
+                       ds.pat.n_rows, ds.pat.rowptr, ds.rs_ptr, E.eptr, E.hdr);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
 static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream_t s) {
     const int64_t n_slots = m->T * ds.nloc;
     int32_t n_ent = 0;
@@ -804,6 +838,7 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream
     FEM_HIP(hipMemcpyAsync(&h, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
     if (h) return fail(FEM_EOVERFLOW, "fem_pattern: a tile row or slot index exceeds its record field");
+    if (fem_status st = ema_headers(ds, E, s)) return st;
     // the build-only arrays
     (void)hipFree(E.elems);
     (void)hipFree(E.joff);
@@ -845,6 +880,7 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             m->allocs.push_back(cand.eptr);
             m->allocs.push_back(cand.ent);
             m->allocs.push_back(cand.rec);
+            m->allocs.push_back(cand.hdr);
             cand.NT = nt;
             cand.built = true;
             cand.usable = cand.max_elems <= nt;
