@@ -402,19 +402,39 @@ __global__ void k_colpos(const int32_t* rs_slot, const int32_t* elems2dofs, cons
     for (int l = 0; l < cp; ++l) colpos[i * cp + l] = out[l];
 }
 
-__global__ void k_row_stats(const int64_t* rowptr, int64_t N, int* max_len, int* tile_pmax) {
+// Longest row and, for R = 32, 64, 128, 256, the most values of a tile of R
+// rows: block-wide maxima, one atomic per block and statistic.
+__global__ __launch_bounds__(256) void k_row_stats(const int64_t* rowptr, int64_t N, int* max_len,
+                                                   int* tile_pmax) {
+    __shared__ int red[5][256];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    const int64_t len = rowptr[r + 1] - rowptr[r];
-    atomicMax(max_len, (int)(len > 0x7fffffff ? 0x7fffffff : len));
-    const int R[4] = {32, 64, 128, 256};
+    int v[5] = {0, 0, 0, 0, 0};
+    if (r < N) {
+        const int64_t len = rowptr[r + 1] - rowptr[r];
+        v[0] = (int)(len > 0x7fffffff ? 0x7fffffff : len);
+        const int R[4] = {32, 64, 128, 256};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (r % R[q] == 0) {
-            const int64_t r1 = (r + R[q] < N) ? r + R[q] : N;
-            const int64_t nn = rowptr[r1] - rowptr[r];
-            atomicMax(&tile_pmax[q], (int)(nn > 0x7fffffff ? 0x7fffffff : nn));
+        for (int q = 0; q < 4; ++q) {
+            if (r % R[q] == 0) {
+                const int64_t r1 = (r + R[q] < N) ? r + R[q] : N;
+                const int64_t nn = rowptr[r1] - rowptr[r];
+                v[1 + q] = (int)(nn > 0x7fffffff ? 0x7fffffff : nn);
+            }
         }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = max(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(max_len, red[0][0]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) atomicMax(&tile_pmax[q], red[1 + q][0]);
     }
 }
 
