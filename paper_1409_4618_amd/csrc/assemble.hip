@@ -498,25 +498,26 @@ __device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T&
 }
 
 // One pass (K or M) of a lane's element: rows k that belong to the tile
-// (bit k of mask). rb: LDS base of row k, cp: its column offsets, jk (3D
-// Nedelec): the slot's index in the tile's diagonal buffer.
+// (bit k of mask). The slot record cp[k] gives the row's column offsets, its
+// tile-local row (LDS base of the row's values) and, for the 3D Nedelec
+// diagonal, the slot's rank in the row (index in the tile's diagonal buffer).
 template <int KC, bool MASS>
 __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, uint32_t mask,
-                                            const int jk[KT<KC>::NLOC], const int rb[KT<KC>::NLOC],
-                                            const uint64_t cp[KT<KC>::NLOC], double* out,
-                                            double* sdiag) {
+                                            const uint64_t cp[KT<KC>::NLOC], const int* rowbase,
+                                            const int* rowslot, double* out, double* sdiag) {
     constexpr int NLOC = KT<KC>::NLOC;
     static_for<0, NLOC>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         if ((mask >> k) & 1u) {
             pin_state<MASS>(st);
             const typename EmaPass<KC, MASS>::T& sk = st;
-            const int base = rb[k];
             const uint64_t c = cp[k];
+            const int lr = (int)((c >> 48) & 0xFFu);
+            const int base = rowbase[lr];
             const double r = ema_row<KC, MASS, k>(sk);
             const double d = ema_entry<KC, MASS, k, k>(sk, r);
             if constexpr (KC == 2) {
-                sdiag[jk[k]] = d;
+                sdiag[rowslot[lr] + (int)(c >> 56)] = d;
             } else {
                 atomicAdd(&out[base + (int)((c >> (8 * k)) & 0xFFu)], d);
             }
@@ -596,7 +597,6 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     // gather (coordinates, coefficients), then the element state
     typename EmaElem<KC>::T st;
     double ca = 1.0, cb = 1.0;
-    int rb[NLOC], jk[NLOC];
     bool bad = false;
     if (have) {
         double x[NV][DIM];
@@ -606,18 +606,11 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
             for (int c = 0; c < DIM; ++c) x[v][c] = md.nodes[(int64_t)gid[v] * DIM + c];
         if (md.a) ca = md.a[e];
         if (md.b) cb = md.b[e];
+        if constexpr (KC == 2) {
 #pragma unroll
-        for (int k = 0; k < NLOC; ++k) {
-            rb[k] = 0;
-            jk[k] = 0;
-            if ((mask >> k) & 1u) {
-                const int lr = (int)((cp[k] >> 48) & 0xFFu);
-                rb[k] = rowbase[lr];
-                if constexpr (KC == 2) {
-                    jk[k] = rowslot[lr] + (int)(cp[k] >> 56);
-                    rowdiag[lr] = (int)((cp[k] >> (8 * k)) & 0xFFu);
-                }
-            }
+            for (int k = 0; k < NLOC; ++k)
+                if ((mask >> k) & 1u)
+                    rowdiag[(int)((cp[k] >> 48) & 0xFFu)] = (int)((cp[k] >> (8 * k)) & 0xFFu);
         }
         st = ema_elem<KC>(gid, x, ca, cb);
         bad = !(fabs(st.J) > 0.0) || !isfinite(st.J);
@@ -631,7 +624,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if (dst) {
             if (have) {
                 typename EmaPass<KC, MASS>::T ps = ema_pass_state<KC, MASS>(st);
-                ema_scatter<KC, MASS>(ps, mask, jk, rb, cp, out, sdiag);
+                ema_scatter<KC, MASS>(ps, mask, cp, rowbase, rowslot, out, sdiag);
             }
             __syncthreads();
             if constexpr (KC == 2) {
