@@ -783,8 +783,9 @@ struct BwdArgs {
 // offsets give the positions of its n_local entries).
 // A missing weight array reads the other one and is zeroed by a select (not a
 // branch, which would split the gathers into separate blocks); the launcher
-// handles both missing.
-template <int NLOC>
+// handles both missing. SAME: gK and gM are the same array (L = u^T (K + M) u
+// has equal weights), gathered once.
+template <int NLOC, bool SAME>
 __device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t base, uint64_t cp,
                                            double wk[NLOC], double wm[NLOC]) {
     const double* pK = A.gK ? A.gK : A.gM;
@@ -792,10 +793,14 @@ __device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t base, uint6
 #pragma unroll
     for (int l = 0; l < NLOC; ++l) {
         const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
-        const double vk = pK[pos];
-        const double vm = pM[pos];
-        wk[l] = A.gK ? vk : 0.0;
-        wm[l] = A.gM ? vm : 0.0;
+        if constexpr (SAME) {
+            wk[l] = wm[l] = pK[pos];
+        } else {
+            const double vk = pK[pos];
+            const double vm = pM[pos];
+            wk[l] = A.gK ? vk : 0.0;
+            wm[l] = A.gM ? vm : 0.0;
+        }
     }
 }
 
@@ -818,6 +823,7 @@ __device__ __forceinline__ void store_vertex2(const BwdArgs& A, int64_t inc, dou
 //   the Gram entries, symmetric part accumulated once per pair),
 // and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
+template <bool SAME>
 __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
     int gid[4];
     V3 x[4];
@@ -849,7 +855,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
         // 72 gathers up front and hold them, at one wavefront per SIMD
         __builtin_amdgcn_sched_barrier(0);
         double gk[6], gm[6];
-        gather_row<6>(A, A.slot_base[e * 6 + k], A.slot_cp[e * 6 + k], gk, gm);
+        gather_row<6, SAME>(A, A.slot_base[e * 6 + k], A.slot_cp[e * 6 + k], gk, gm);
         const int i = nib(NED3_START, k), j = nib(NED3_END, k);
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
@@ -931,6 +937,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
 }
 
 // 3D Raviart-Thomas
+template <bool SAME>
 __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
     int gid[4];
     V3 x[4];
@@ -941,7 +948,7 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
     double GK[4][4], GM[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gather_row<4>(A, A.slot_base[e * 4 + k], A.slot_cp[e * 4 + k], GK[k], GM[k]);
+    for (int k = 0; k < 4; ++k) gather_row<4, SAME>(A, A.slot_base[e * 4 + k], A.slot_cp[e * 4 + k], GK[k], GM[k]);
     const GeoRT3 g = geo_rt3(x);
     double s[4];
     rt3_signs(gid, s);
@@ -1001,6 +1008,7 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
 }
 
 // 2D (both kinds)
+template <bool SAME>
 __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
     int gid[3];
     V2 x[3];
@@ -1011,7 +1019,7 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
     }
     double GK[3][3], GM[3][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gather_row<3>(A, A.slot_base[e * 3 + k], A.slot_cp[e * 3 + k], GK[k], GM[k]);
+    for (int k = 0; k < 3; ++k) gather_row<3, SAME>(A, A.slot_base[e * 3 + k], A.slot_cp[e * 3 + k], GK[k], GM[k]);
     const Geo2 g = geo2(x);
     double s[3];
     tri_signs(gid, s);
@@ -1074,7 +1082,7 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
-template <int KC>
+template <int KC, bool SAME>
 __global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the
@@ -1083,9 +1091,9 @@ __global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
     const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     const int64_t e = blk * blockDim.x + threadIdx.x;
     if (e >= A.T) return;
-    if constexpr (KC == 2) bwd_ned3(A, e);
-    else if constexpr (KC == 1) bwd_rt3(A, e);
-    else bwd_tri(A, e);
+    if constexpr (KC == 2) bwd_ned3<SAME>(A, e);
+    else if constexpr (KC == 1) bwd_rt3<SAME>(A, e);
+    else bwd_tri<SAME>(A, e);
 }
 
 // gnodes[v] = sum of the vertex derivatives of the node's incidences, which
@@ -1152,9 +1160,15 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.err_word = m->err_word;
     const unsigned grid = (unsigned)(((m->T + 255) / 256 + 7) / 8 * 8);
     if (m->T > 0) {
-        if (kc == 2) hipLaunchKernelGGL(k_backward<2>, dim3(grid), dim3(256), 0, s, A);
-        else if (kc == 1) hipLaunchKernelGGL(k_backward<1>, dim3(grid), dim3(256), 0, s, A);
-        else hipLaunchKernelGGL(k_backward<0>, dim3(grid), dim3(256), 0, s, A);
+        if (gK == gM) {
+            if (kc == 2) hipLaunchKernelGGL((k_backward<2, true>), dim3(grid), dim3(256), 0, s, A);
+            else if (kc == 1) hipLaunchKernelGGL((k_backward<1, true>), dim3(grid), dim3(256), 0, s, A);
+            else hipLaunchKernelGGL((k_backward<0, true>), dim3(grid), dim3(256), 0, s, A);
+        } else {
+            if (kc == 2) hipLaunchKernelGGL((k_backward<2, false>), dim3(grid), dim3(256), 0, s, A);
+            else if (kc == 1) hipLaunchKernelGGL((k_backward<1, false>), dim3(grid), dim3(256), 0, s, A);
+            else hipLaunchKernelGGL((k_backward<0, false>), dim3(grid), dim3(256), 0, s, A);
+        }
         FEM_HIP(hipGetLastError());
     }
     if (gnodes && m->V > 0) {
