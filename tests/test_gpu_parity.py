@@ -151,3 +151,55 @@ def test_error_codes():
         mesh.status()
     assert ei.value.status == 3
     mesh.status()                       # the error word was cleared
+
+
+def fan_mesh(axes, n_rim):
+    """Tetrahedra fanned around the edges (0, a) for a = 1..axes: n_rim tets per
+    axis edge, each (0, a, r_i, r_{i+1}) with the rim r closed into a ring. Row
+    (0, a) then has 1 + 3 n_rim entries and n_rim elements."""
+    nodes = [[0.0, 0.0, 0.0]]
+    dirs = np.array([[1.0, 0.1, 0.2], [0.1, 1.0, 0.3], [0.2, 0.3, 1.0], [-1.0, 0.2, 0.1]])[:axes]
+    for d in dirs:
+        nodes.append(list(d / np.linalg.norm(d)))
+    elems = []
+    for a, d in enumerate(dirs, start=1):
+        d = d / np.linalg.norm(d)
+        u = np.cross(d, [0.3, -0.5, 0.8])
+        u /= np.linalg.norm(u)
+        w = np.cross(d, u)
+        base = len(nodes)
+        for i in range(n_rim):
+            t = 2 * np.pi * i / n_rim
+            nodes.append(list(0.5 * d + np.cos(t) * u + np.sin(t) * w))
+        for i in range(n_rim):
+            elems.append([0, a, base + i, base + (i + 1) % n_rim])
+    return np.array(nodes), np.array(elems, dtype=np.int32)
+
+
+@pytest.mark.parametrize("kind", ["ned", "rt"])
+def test_dense_fans_take_the_row_kernel(kind):
+    """Four 84-tet fans around the edges (0, 1) .. (0, 4). Nedelec: those edges
+    are the first four rows, so no element-major tile of 4 or more rows fits 256
+    lanes and the mesh is assembled by the row kernel; row (0, a) has 253
+    entries (near the 255 limit). Raviart-Thomas: the same mesh through the
+    element-major kernel (face rows of at most 7 entries)."""
+    nodes, elems = fan_mesh(4, 84)
+    rng = np.random.default_rng(31)
+    a = rng.uniform(0.5, 2.0, elems.shape[0])
+    b = rng.uniform(0.5, 2.0, elems.shape[0])
+    g = run_case(f"fans 4x84 {kind}", nodes, elems, kind, a, b)
+    check_against_oracle(g, nodes, elems, kind, a, b)
+    if kind == "ned":
+        assert int(np.diff(g["rowptr"]).max()) == 253
+
+
+def test_row_longer_than_255_is_rejected():
+    import paper_1409_4618_amd as fem
+    from paper_1409_4618_amd import FemError
+    nodes, elems = fan_mesh(1, 86)      # row (0, 1): 1 + 3 * 86 = 259 entries
+    say("[gpu] row length 259 -> FEM_EOVERFLOW")
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    with pytest.raises(FemError) as ei:
+        mesh.pattern("ned")
+    assert ei.value.status == 5
