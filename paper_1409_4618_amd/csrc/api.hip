@@ -60,6 +60,7 @@ static void fill_ema(const DofSet& ds, int nt, MeshDev* md) {
     md->ema_hdr = E.hdr;
 
     md->ema_ent = E.ent;
+    md->ema_gid = reinterpret_cast<const int4*>(E.egid);
     md->ema_rec = E.rec;
     md->ema_R = E.R;
     md->ema_pmax = E.pmax;

@@ -574,16 +574,11 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
 #pragma unroll
         for (int k = 0; k < NLOC; ++k)
             if ((mask >> k) & 1u) cp[k] = md.ema_rec[roff + __popc(mask & ((1u << k) - 1u))];
-        if constexpr (NV == 4) {
-            const int4 q = reinterpret_cast<const int4*>(md.elems)[e];
-            gid[0] = q.x;
-            gid[1] = q.y;
-            gid[2] = q.z;
-            gid[3] = q.w;
-        } else {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) gid[v] = md.elems[e * NV + v];
-        }
+        const int4 q = md.ema_gid[e_beg + tid];  // the element's node ids, streamed with the entry
+        gid[0] = q.x;
+        gid[1] = q.y;
+        gid[2] = q.z;
+        if constexpr (NV == 4) gid[3] = q.w;
     }
     // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;

@@ -63,6 +63,7 @@ struct Pattern {
         // entry i of a tile: (element, in-tile local dofs (6 bits) | offset of
         // its first record in the tile << 8)
         int2* ent = nullptr;        // [n_entries]
+        int32_t* egid = nullptr;    // [n_entries][4] node ids of the entry's element (zero-padded in 2D)
         // record of an in-tile slot, grouped by entry, ascending local dof:
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)
@@ -167,6 +168,7 @@ struct MeshDev {
     // element-major tiles: headers, entries, slot records
     const int32_t* ema_hdr;
     const int2* ema_ent;
+    const int4* ema_gid;
     const uint64_t* ema_rec;
     int32_t ema_R;
     int32_t ema_pmax;

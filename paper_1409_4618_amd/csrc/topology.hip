@@ -756,6 +756,8 @@ static void ema_free(Pattern::Ema& e) {
     if (e.elems) (void)hipFree(e.elems);
     if (e.joff) (void)hipFree(e.joff);
     if (e.ent) (void)hipFree(e.ent);
+    if (e.egid) (void)hipFree(e.egid);
+    e.egid = nullptr;
     if (e.rec) (void)hipFree(e.rec);
     if (e.hdr) (void)hipFree(e.hdr);
     e.hdr = nullptr;
@@ -777,7 +779,8 @@ __global__ void k_slot_rows(const int32_t* rs_ptr, int64_t n_rows, int32_t* slot
 // entries in their final order).
 __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_t* elems,
                               const uint16_t* joff, const int32_t* rs_ptr, const int32_t* slot_row,
-                              const uint8_t* colpos, int cp_stride, int nloc, int R, int2* ent,
+                              const uint8_t* colpos, int cp_stride, int nloc, int R,
+                              const int32_t* elem_nodes, int nv, int2* ent, int4* egid,
                               uint64_t* rec, int* overflow) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
@@ -800,7 +803,10 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
             ++cnt;
         }
         if (off > 0xFFFFFFu) atomicOr(overflow, 1);
-        ent[i] = make_int2(elems[i], (int)(mask | (off << 8)));
+        const int64_t e = elems[i];
+        ent[i] = make_int2((int)e, (int)(mask | (off << 8)));
+        const int32_t* q = elem_nodes + e * nv;
+        egid[i] = make_int4(q[0], q[1], q[2], nv == 4 ? q[3] : 0);
         off += cnt;
     }
 }
@@ -842,6 +848,7 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream
     FEM_HIP(hipMemcpyAsync(&n_ent, E.eptr + E.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
     FEM_HIP(hipMalloc((void**)&E.ent, (size_t)std::max<int32_t>(n_ent, 1) * sizeof(int2)));
+    FEM_HIP(hipMalloc((void**)&E.egid, (size_t)std::max<int32_t>(n_ent, 1) * sizeof(int4)));
     FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * sizeof(uint64_t)));
     TmpBufs tb;
     FEM_HIP(tb.alloc(std::max<int64_t>(n_slots, 1)));
@@ -852,7 +859,7 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream
                        slot_row);
     hipLaunchKernelGGL(k_ema_records, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.eptr, E.n_tiles, E.elems,
                        E.joff, ds.rs_ptr, slot_row, ds.pat.colpos, ds.pat.cp_stride, ds.nloc, E.R,
-                       E.ent, E.rec, overflow);
+                       m->elems, m->dim + 1, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, overflow);
     FEM_HIP(hipGetLastError());
     int h = 0;
     FEM_HIP(hipMemcpyAsync(&h, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -899,6 +906,7 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             }
             m->allocs.push_back(cand.eptr);
             m->allocs.push_back(cand.ent);
+            m->allocs.push_back(cand.egid);
             m->allocs.push_back(cand.rec);
             m->allocs.push_back(cand.hdr);
             cand.NT = nt;
