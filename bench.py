@@ -235,6 +235,35 @@ def cpu_baseline(p, target_seconds=12.0):
                       f"matrices + CSR accumulation, topology given), {reps} reps, 1 thread"}
 
 
+def calib_copy():
+    """A plain device copy of known size (1 GiB read + 1 GiB written), to scale the
+    HBM byte counters of a profiler run."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2 * src.numel() * 8
+
+
+def only_workload(args):
+    import meshgen as mg
+    if args.only in ("kuhn128_ned3d", "kuhn128_rt3d"):
+        p = mg.kuhn128_ned() if args.only == "kuhn128_ned3d" else mg.kuhn128_rt()
+        s = setup_mesh(p)
+        f = forward_rate(p, s, args.steps, args.warmup)
+        out = {"workload": args.only, "ms": f["ms"], "mtets": f["mtets"], "bytes_per_launch": f["bytes"],
+               "achieved_gbs": f["gbs"], "frac": f["frac"]}
+    elif args.only == "kuhn96_fwd_bwd":
+        out = fwd_bwd_rate(mg.kuhn96_ned_grad(), args.steps, args.warmup)
+    else:
+        out = batched_rate(args.steps, args.warmup, float("nan"))
+    if args.calib_copy:
+        out["calib_copy_bytes"] = calib_copy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +273,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (profiler byte-counter calibration)")
+    ap.add_argument("--only", choices=["kuhn128_ned3d", "kuhn128_rt3d", "kuhn96_fwd_bwd", "batch256"],
+                    help="time one secondary workload alone and print its JSON (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1",
@@ -254,6 +285,10 @@ def main():
     import paper_1409_4618_amd as fem  # noqa: F401  (fails loudly if libfem.so is missing)
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+
+    if args.only:
+        print(json.dumps(only_workload(args)), flush=True)
+        return
 
     log("bench: building kuhn64_ned3d")
     p64 = mg.kuhn64_ned()
@@ -282,15 +317,7 @@ def main():
                      "kernel": "fem::k_forward_ema<2, 256>", "bytes_per_launch": f64["bytes"]},
     }
     if args.calib_copy:
-        # a plain device copy of known size (1 GiB read + 1 GiB written per launch),
-        # to scale the HBM byte counters of a profiler run
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        result["calib_copy_bytes"] = 2 * src.numel() * 8
-        del src, dst
+        result["calib_copy_bytes"] = calib_copy()
     if args.quick:
         print(json.dumps(result), flush=True)
         return
