@@ -323,11 +323,21 @@ __device__ __forceinline__ double sgn_bit(uint32_t bits, int l) {
     return ((bits >> l) & 1u) ? 1.0 : -1.0;
 }
 
+// s_l * x as a flip of the sign bit (neg = 0x80000000 iff s_l = -1): bitwise
+// the product with +-1.0, without a floating-point multiply.
+__device__ __forceinline__ double with_sign(double x, uint32_t neg) {
+    return __hiloint2double(__double2hiint(x) ^ (int)neg, __double2loint(x));
+}
+__device__ __forceinline__ uint32_t neg_mask(uint32_t sbits, int l) {
+    return ((~sbits) << (31 - l)) & 0x80000000u;
+}
+
 struct Ned3Elem {
     V3 b1, b2, b3;  // x_j - x_0
     double ka, mb;  // a * 2/(3|J|), b * 1/(120|J|)
     double J;
     uint32_t sbits;  // bit l set iff s_l = +1
+    uint32_t nm[6];  // sign-bit masks of the s_l
 };
 
 // What the mass rows need: the Gram matrix of the cofactor vectors. It is
@@ -337,6 +347,7 @@ struct Ned3Mass {
     double G[10];  // G_ab = c_a . c_b, packed upper triangle
     double mb;
     uint32_t sbits;
+    uint32_t nm[6];
 };
 
 __device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4], double ca,
@@ -353,6 +364,8 @@ __device__ __forceinline__ Ned3Elem ned3_elem(const V3 x[4], const int gid[4], d
 #pragma unroll
     for (int l = 0; l < 6; ++l)
         e.sbits |= (gid[nib(NED3_START, l)] > gid[nib(NED3_END, l)] ? 1u : 0u) << l;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) e.nm[l] = neg_mask(e.sbits, l);
     return e;
 }
 
@@ -370,6 +383,8 @@ __device__ __forceinline__ Ned3Mass ned3_mass(const Ned3Elem& e) {
         for (int b = a; b < 4; ++b) m.G[tri_index(a, b)] = dot(c[a], c[b]);
     m.mb = e.mb;
     m.sbits = e.sbits;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) m.nm[l] = e.nm[l];
     return m;
 }
 
@@ -386,16 +401,16 @@ __device__ __forceinline__ V3 ned3_o_of(const Ned3Elem& e) {
 // row scale s_k * (a kf) of the stiffness pass, s_k * (b mf) of the mass pass
 template <int k>
 __device__ __forceinline__ double ned3_krow(const Ned3Elem& e) {
-    return sgn_bit(e.sbits, k) * e.ka;
+    return with_sign(e.ka, e.nm[k]);
 }
 template <int k>
 __device__ __forceinline__ double ned3_mrow(const Ned3Mass& e) {
-    return sgn_bit(e.sbits, k) * e.mb;
+    return with_sign(e.mb, e.nm[k]);
 }
 
 template <int k, int l>
 __device__ __forceinline__ double ned3_K(const Ned3Elem& e, double kr) {
-    return (sgn_bit(e.sbits, l) * kr) * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
+    return (with_sign(kr, e.nm[l])) * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
 }
 
 template <int k, int l>
@@ -406,7 +421,7 @@ __device__ __forceinline__ double ned3_M(const Ned3Mass& e, double mr) {
                                   e.G[tri_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri_index(i, n)] * (1.0 + (j == m)));
-    return (sgn_bit(e.sbits, l) * mr) * t;
+    return (with_sign(mr, e.nm[l])) * t;
 }
 
 struct Rt3Elem {
@@ -416,6 +431,7 @@ struct Rt3Elem {
     double ka, mb;  // a * 3/(2|J|), b * 1/(120|J|)
     double J;
     uint32_t sbits;
+    uint32_t nm[4];
 };
 
 __device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4], double ca,
@@ -438,6 +454,8 @@ __device__ __forceinline__ Rt3Elem rt3_elem(const V3 x[4], const int gid[4], dou
     e.sbits = 0;
 #pragma unroll
     for (int l = 0; l < 4; ++l) e.sbits |= (s[l] > 0.0 ? 1u : 0u) << l;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) e.nm[l] = neg_mask(e.sbits, l);
     return e;
 }
 
@@ -458,23 +476,23 @@ __device__ __forceinline__ double rt3_u(const Rt3Elem& e) {
 
 template <int k>
 __device__ __forceinline__ double rt3_krow(const Rt3Elem& e) {
-    return sgn_bit(e.sbits, k) * e.ka;
+    return with_sign(e.ka, e.nm[k]);
 }
 template <int k>
 __device__ __forceinline__ double rt3_mrow(const Rt3Elem& e) {
-    return sgn_bit(e.sbits, k) * e.mb;
+    return with_sign(e.mb, e.nm[k]);
 }
 
 template <int k, int l>
 __device__ __forceinline__ double rt3_K(const Rt3Elem& e, double kr) {
-    return sgn_bit(e.sbits, l) * kr;
+    return with_sign(kr, e.nm[l]);
 }
 
 template <int k, int l>
 __device__ __forceinline__ double rt3_M(const Rt3Elem& e, double mr) {
     constexpr int pk = 3 - k, pl = 3 - l;
     const double t = e.base - 5.0 * (rt3_u<pk>(e) + rt3_u<pl>(e)) + 20.0 * dot(rt3_y<pk>(e), rt3_y<pl>(e));
-    return (sgn_bit(e.sbits, l) * mr) * t;
+    return (with_sign(mr, e.nm[l])) * t;
 }
 
 struct TriElem {
@@ -482,6 +500,7 @@ struct TriElem {
     double ka, mb;  // a * 2/|J|, b * 1/(24|J|)
     double J;
     uint32_t sbits;
+    uint32_t nm[3];
 };
 
 __host__ __device__ constexpr int tri3_index(int a, int b) {
@@ -503,21 +522,23 @@ __device__ __forceinline__ TriElem tri_elem(const V2 x[3], const int gid[3], dou
 #pragma unroll
     for (int l = 0; l < 3; ++l)
         e.sbits |= (gid[nib(TRI_START, l)] > gid[nib(TRI_END, l)] ? 1u : 0u) << l;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) e.nm[l] = neg_mask(e.sbits, l);
     return e;
 }
 
 template <int k>
 __device__ __forceinline__ double tri_krow(const TriElem& e) {
-    return sgn_bit(e.sbits, k) * e.ka;
+    return with_sign(e.ka, e.nm[k]);
 }
 template <int k>
 __device__ __forceinline__ double tri_mrow(const TriElem& e) {
-    return sgn_bit(e.sbits, k) * e.mb;
+    return with_sign(e.mb, e.nm[k]);
 }
 
 template <int k, int l>
 __device__ __forceinline__ double tri_K(const TriElem& e, double kr) {
-    return sgn_bit(e.sbits, l) * kr;
+    return with_sign(kr, e.nm[l]);
 }
 
 template <int k, int l>
@@ -528,7 +549,7 @@ __device__ __forceinline__ double tri_M(const TriElem& e, double mr) {
                                   e.G[tri3_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri3_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri3_index(i, n)] * (1.0 + (j == m)));
-    return (sgn_bit(e.sbits, l) * mr) * t;
+    return (with_sign(mr, e.nm[l])) * t;
 }
 
 }  // namespace fem
