@@ -171,6 +171,24 @@ def fwd_bwd_rate(p, steps, warmup):
     return out
 
 
+def small_mesh_latency(steps, warmup):
+    """The 2D 32x32 unit square (2,048 triangles, unit coefficients): launch-bound,
+    so reported as microseconds per assembly, direct launch and HIP-graph replay
+    (a one-mesh batch)."""
+    import meshgen as mg
+    import paper_1409_4618_amd as fem
+    p = mg.square_ned32()
+    s = setup_mesh(p)
+    run = lambda: fem.assemble_into(s["mesh"], p.kind, s["nodes"], None, None, s["K"], s["M"])
+    us_direct = timed(run, steps, warmup) * 1e3
+    B = fem.Batch([s["mesh"]], [p.kind])
+    B.bind([s["nodes"]], [None], [None], [s["K"]], [s["M"]])
+    us_graph = timed(B.graph_launch, steps, warmup) * 1e3
+    s["mesh"].status()
+    return {"workload": "square32_ned2d: 2D Nedelec K+M, unit square 32x32 (2,048 triangles), unit coefficients",
+            "us_direct": us_direct, "us_graph": us_graph, "nnz": s["nnz"]}
+
+
 def batched_rate(steps, warmup, ref_mtets, scale=1.0):
     import torch
     import meshgen as mg
@@ -351,6 +369,10 @@ def main():
     result["fwd_bwd"] = {k: (round(v, 6) if isinstance(v, float) else v)
                          for k, v in fwd_bwd_rate(mg.kuhn96_ned_grad(), args.steps, args.warmup).items()}
     torch.cuda.empty_cache()
+
+    log("bench: square32 latency")
+    result["small_2d"] = {k: (round(v, 3) if isinstance(v, float) else v)
+                          for k, v in small_mesh_latency(args.steps, args.warmup).items()}
 
     log("bench: batched 256 meshes")
     result["batched"] = {k: (round(v, 6) if isinstance(v, float) else v)
