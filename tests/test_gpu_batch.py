@@ -69,14 +69,15 @@ def test_batch_equals_single_launches(batch_setup, rows, schedule):
     assert cfg["rows_per_tile"] == rows and cfg["schedule"] == schedule and cfg["grid"] >= 1
 
 
-def test_graph_replay_equals_direct(batch_setup):
+@pytest.mark.parametrize("rows", [0, 128])
+def test_graph_replay_equals_direct(batch_setup, rows):
     import torch
     import paper_1409_4618_amd as fem
     probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
-    say("[gpu] batch graph replays")
+    say(f"[gpu] batch graph replays, rows={rows}")
     B = fem.Batch(meshes, kinds)
     B.bind(nodes, a, b, Ks, Ms)
-    B.set_config(128, 1)
+    B.set_config(rows, 1)
     for rep in range(3):
         for K, M in zip(Ks, Ms):
             K.zero_()
@@ -115,3 +116,43 @@ def test_autotuner_and_cache(batch_setup, tmp_path):
     torch.cuda.synchronize()
     for (K, M), (Kr, Mr) in zip(zip(Ks, Ms), refs):
         assert torch.equal(K, Kr) and torch.equal(M, Mr)
+
+
+def test_full_size_batch_as_benchmarked():
+    """The batched workload at its full size (256 meshes, 16.8 M elements) in the
+    configuration the benchmark times (autotuned, graph replay): bitwise equal to
+    single-mesh launches for every mesh, and the four smallest meshes equal to
+    the oracle."""
+    import torch
+    import paper_1409_4618_amd as fem
+    probs = mg.batch_problems(seed=4, count=256, scale=1.0)
+    say(f"[gpu] full-size batch: {len(probs)} meshes, {sum(p.T for p in probs)} elements")
+    meshes, kinds, nodes, a, b, Ks, Ms, refs = [], [], [], [], [], [], [], []
+    for p in probs:
+        tn, te, ta, tb = dev_tensors(p.nodes, p.elems, p.a, p.b)
+        m = fem.Mesh(tn, te)
+        K, M = fem.assemble(m, p.kind, tn, ta, tb)
+        meshes.append(m)
+        kinds.append(p.kind)
+        nodes.append(tn)
+        a.append(ta)
+        b.append(tb)
+        refs.append((K, M))
+        Ks.append(torch.full_like(K, float("nan")))
+        Ms.append(torch.full_like(M, float("nan")))
+    B = fem.Batch(meshes, kinds)
+    B.bind(nodes, a, b, Ks, Ms)
+    B.tune(None)
+    say(f"    tuned: {B.config()}")
+    for _ in range(2):
+        B.graph_launch()
+    torch.cuda.synchronize()
+    for i, ((K, M), (Kr, Mr)) in enumerate(zip(zip(Ks, Ms), refs)):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr), i
+    for m in meshes:
+        m.status()
+    for i in np.argsort([p.T for p in probs])[:4]:
+        p = probs[i]
+        csr, _ = oracle.assemble(p.nodes, p.elems, p.kind, a=p.a, b=p.b)
+        K, M = refs[i]
+        assert rel_fro(K.cpu().numpy(), csr.Kv) <= TOL and rel_fro(M.cpu().numpy(), csr.Mv) <= TOL
