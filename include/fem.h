@@ -139,6 +139,18 @@ fem_status fem_assemble_backward(fem_mesh mesh, fem_kind kind, const double* nod
                                  const double* gK, const double* gM,
                                  double* ga, double* gb, double* gnodes, void* stream);
 
+/* Adjoint of the quadratic form L = u^T (K(a) + M(b)) u (the energy of a dof
+ * vector u): the same outputs as fem_assemble_backward with
+ * gK[p] = gM[p] = u_row(p) u_col(p), bitwise, but the weights are formed per
+ * element from u at its dofs instead of being read from nnz-sized arrays.
+ * Not part of the paper. Asynchronous.
+ *   u       dev f64 [n_rows of fem_pattern(kind)] (edge or face values)
+ *   ga, gb, gnodes as in fem_assemble_backward (NULL to skip)
+ * FEM_EINVAL if u is NULL.                                                  */
+fem_status fem_assemble_backward_quadratic(fem_mesh mesh, fem_kind kind, const double* nodes,
+                                           const double* a, const double* b, const double* u,
+                                           double* ga, double* gb, double* gnodes, void* stream);
+
 /* Synchronises the last stream used with `mesh`, returns and clears the
  * asynchronous device error word (FEM_OK, FEM_EDEGENERATE or FEM_ENONFINITE). */
 fem_status fem_status_query(fem_mesh mesh);

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 
 from ._lib import (FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
-__all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "FemAssemble", "FemError",
+__all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
            "kind_code", "NED", "RT"]
 
 NED = "ned"
@@ -186,6 +186,24 @@ def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b
     check(lib().fem_assemble_backward(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b),
                                       _ptr(gK), _ptr(gM), _ptr(ga), _ptr(gb), _ptr(gn),
                                       _stream_ptr()), "fem_assemble_backward")
+    return gn, ga, gb
+
+
+def assemble_backward_quadratic(mesh: Mesh, kind, nodes, a, b, u, need_a=True, need_b=True,
+                                need_nodes=True):
+    """Adjoint of L = u^T (K(a) + M(b)) u: (dL/dnodes, dL/da, dL/db), the same as
+    assemble_backward with gK = gM = u_row u_col, without materialising them."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(kind)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(u, torch.float64, "u", (n_rows,))
+    dev = nodes.device
+    ga = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_a else None
+    gb = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_b else None
+    gn = torch.empty_like(nodes) if need_nodes else None
+    check(lib().fem_assemble_backward_quadratic(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b),
+                                                _ptr(u), _ptr(ga), _ptr(gb), _ptr(gn), _stream_ptr()),
+          "fem_assemble_backward_quadratic")
     return gn, ga, gb
 
 

@@ -32,6 +32,7 @@ SIGNATURES = [
                                    c_void_pp, c_void_pp]),
     ("fem_assemble", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6),
     ("fem_assemble_backward", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 9),
+    ("fem_assemble_backward_quadratic", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 8),
     ("fem_status_query", ctypes.c_int, [ctypes.c_void_p]),
     ("fem_mesh_destroy", None, [ctypes.c_void_p]),
     ("fem_batch_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, c_void_pp]),

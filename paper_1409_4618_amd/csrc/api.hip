@@ -224,7 +224,22 @@ fem_status fem_assemble_backward(fem_mesh m, fem_kind kind, const double* nodes,
     if (!ga && !gb && !gnodes) return FEM_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
-    return launch_backward(m, ds, kind, nodes, a, b, gK, gM, ga, gb, gnodes, s);
+    return launch_backward(m, ds, kind, nodes, a, b, gK, gM, nullptr, ga, gb, gnodes, s);
+}
+
+fem_status fem_assemble_backward_quadratic(fem_mesh m, fem_kind kind, const double* nodes,
+                                           const double* a, const double* b, const double* u,
+                                           double* ga, double* gb, double* gnodes, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_assemble_backward_quadratic: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS)
+        return fail(FEM_EINVAL, "fem_assemble_backward_quadratic: bad kind");
+    if (!nodes || !u) return fail(FEM_EINVAL, "fem_assemble_backward_quadratic: nodes or u is NULL");
+    DofSet& ds = dofset(m, kind);
+    if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+    if (!ga && !gb && !gnodes) return FEM_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    return launch_backward(m, ds, kind, nodes, a, b, nullptr, nullptr, u, ga, gb, gnodes, s);
 }
 
 fem_status fem_status_query(fem_mesh m) {

@@ -766,6 +766,8 @@ struct BwdArgs {
     const double* gM;
     const int64_t* slot_base;  // [T*nloc] row start of each slot's dof
     const uint64_t* slot_cp;   // [T*nloc] column offsets of each slot's row
+    const double* u;           // quadratic form: [n_dofs] vector, weights u_I u_J
+    const int32_t* elems2dofs; // quadratic form: [T*nloc] global dof of each slot
     double* ga;
     double* gb;
     double* partials;          // [T*(dim+1)][dim] vertex derivatives, node order
@@ -776,26 +778,51 @@ struct BwdArgs {
 
 // Upstream weights of row k of an element (the slot's row start and column
 // offsets give the positions of its n_local entries).
-// A missing weight array reads the other one and is zeroed by a select (not a
-// branch, which would split the gathers into separate blocks); the launcher
-// handles both missing. SAME: gK and gM are the same array (L = u^T (K + M) u
-// has equal weights), gathered once.
-template <int NLOC, bool SAME>
-__device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t base, uint64_t cp,
+// Weight modes of the adjoint: separate gK and gM arrays, one array for both
+// (L = u^T (K + M) u with its weights materialised), or the quadratic form
+// itself, whose weight at (I, J) is u_I u_J and is formed from u without
+// reading an nnz-sized array.
+enum BwdMode { BWD_SEPARATE = 0, BWD_SAME = 1, BWD_QUADRATIC = 2 };
+
+// Upstream weights of row k of element e. A missing weight array reads the
+// other one and is zeroed by a select (not a branch, which would split the
+// gathers into separate blocks); the launcher handles both missing. In the
+// quadratic mode, uk = u[dof k] and ue[] = u[dofs of the element]: u_I u_J is
+// the same product, bitwise, that the materialised weights hold.
+template <int NLOC, int MODE>
+__device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t e, int k, const double ue[NLOC],
                                            double wk[NLOC], double wm[NLOC]) {
-    const double* pK = A.gK ? A.gK : A.gM;
-    const double* pM = A.gM ? A.gM : A.gK;
+    if constexpr (MODE == BWD_QUADRATIC) {
 #pragma unroll
-    for (int l = 0; l < NLOC; ++l) {
-        const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
-        if constexpr (SAME) {
-            wk[l] = wm[l] = pK[pos];
-        } else {
-            const double vk = pK[pos];
-            const double vm = pM[pos];
-            wk[l] = A.gK ? vk : 0.0;
-            wm[l] = A.gM ? vm : 0.0;
+        for (int l = 0; l < NLOC; ++l) wk[l] = wm[l] = ue[k] * ue[l];
+    } else {
+        const int64_t base = A.slot_base[e * NLOC + k];
+        const uint64_t cp = A.slot_cp[e * NLOC + k];
+        const double* pK = A.gK ? A.gK : A.gM;
+        const double* pM = A.gM ? A.gM : A.gK;
+#pragma unroll
+        for (int l = 0; l < NLOC; ++l) {
+            const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
+            if constexpr (MODE == BWD_SAME) {
+                wk[l] = wm[l] = pK[pos];
+            } else {
+                const double vk = pK[pos];
+                const double vm = pM[pos];
+                wk[l] = A.gK ? vk : 0.0;
+                wm[l] = A.gM ? vm : 0.0;
+            }
         }
+    }
+}
+
+// u at the element's dofs (quadratic mode only)
+template <int NLOC, int MODE>
+__device__ __forceinline__ void load_u(const BwdArgs& A, int64_t e, double ue[NLOC]) {
+#pragma unroll
+    for (int l = 0; l < NLOC; ++l) ue[l] = 0.0;
+    if constexpr (MODE == BWD_QUADRATIC) {
+#pragma unroll
+        for (int l = 0; l < NLOC; ++l) ue[l] = A.u[A.elems2dofs[e * NLOC + l]];
     }
 }
 
@@ -818,7 +845,7 @@ __device__ __forceinline__ void store_vertex2(const BwdArgs& A, int64_t inc, dou
 //   the Gram entries, symmetric part accumulated once per pair),
 // and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
-template <bool SAME>
+template <int MODE>
 __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
     int gid[4];
     V3 x[4];
@@ -830,6 +857,8 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
     const V3 b1 = sub(x[1], x[0]), b2 = sub(x[2], x[0]), b3 = sub(x[3], x[0]);
     double s[6];
     ned3_signs(gid, s);
+    double ue[6];
+    load_u<6, MODE>(A, e, ue);
     // dPhi_j (derivative of Phi with respect to b_j) is accumulated directly:
     // with q_k = sum_l (w_kl + w_lk) o_l,
     //   dPhi_1 = q_1 - q_2 + q_4, dPhi_2 = q_2 - q_0 + q_5, dPhi_3 = q_0 - q_1 + q_3
@@ -850,7 +879,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
         // 72 gathers up front and hold them, at one wavefront per SIMD
         __builtin_amdgcn_sched_barrier(0);
         double gk[6], gm[6];
-        gather_row<6, SAME>(A, A.slot_base[e * 6 + k], A.slot_cp[e * 6 + k], gk, gm);
+        gather_row<6, MODE>(A, e, k, ue, gk, gm);
         const int i = nib(NED3_START, k), j = nib(NED3_END, k);
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
@@ -932,7 +961,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
 }
 
 // 3D Raviart-Thomas
-template <bool SAME>
+template <int MODE>
 __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
     int gid[4];
     V3 x[4];
@@ -942,8 +971,10 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
     double GK[4][4], GM[4][4];
+double ue[4];
+    load_u<4, MODE>(A, e, ue);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gather_row<4, SAME>(A, A.slot_base[e * 4 + k], A.slot_cp[e * 4 + k], GK[k], GM[k]);
+    for (int k = 0; k < 4; ++k) gather_row<4, MODE>(A, e, k, ue, GK[k], GM[k]);
     const GeoRT3 g = geo_rt3(x);
     double s[4];
     rt3_signs(gid, s);
@@ -1003,7 +1034,7 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
 }
 
 // 2D (both kinds)
-template <bool SAME>
+template <int MODE>
 __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
     int gid[3];
     V2 x[3];
@@ -1013,8 +1044,10 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
         x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
     }
     double GK[3][3], GM[3][3];
+double ue[3];
+    load_u<3, MODE>(A, e, ue);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gather_row<3, SAME>(A, A.slot_base[e * 3 + k], A.slot_cp[e * 3 + k], GK[k], GM[k]);
+    for (int k = 0; k < 3; ++k) gather_row<3, MODE>(A, e, k, ue, GK[k], GM[k]);
     const Geo2 g = geo2(x);
     double s[3];
     tri_signs(gid, s);
@@ -1077,7 +1110,7 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e) {
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
-template <int KC, bool SAME>
+template <int KC, int MODE>
 __global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the
@@ -1086,9 +1119,9 @@ __global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
     const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     const int64_t e = blk * blockDim.x + threadIdx.x;
     if (e >= A.T) return;
-    if constexpr (KC == 2) bwd_ned3<SAME>(A, e);
-    else if constexpr (KC == 1) bwd_rt3<SAME>(A, e);
-    else bwd_tri<SAME>(A, e);
+    if constexpr (KC == 2) bwd_ned3<MODE>(A, e);
+    else if constexpr (KC == 1) bwd_rt3<MODE>(A, e);
+    else bwd_tri<MODE>(A, e);
 }
 
 // gnodes[v] = sum of the vertex derivatives of the node's incidences, which
@@ -1123,12 +1156,24 @@ static fem_status zero_f64(double* p, int64_t n, hipStream_t s) {
     return FEM_OK;
 }
 
+template <int KC, int MODE>
+static void launch_bwd_t(const BwdArgs& A, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_backward<KC, MODE>), dim3(grid), dim3(256), 0, s, A);
+}
+
+template <int MODE>
+static void launch_bwd_mode(int kc, const BwdArgs& A, unsigned grid, hipStream_t s) {
+    if (kc == 2) launch_bwd_t<2, MODE>(A, grid, s);
+    else if (kc == 1) launch_bwd_t<1, MODE>(A, grid, s);
+    else launch_bwd_t<0, MODE>(A, grid, s);
+}
+
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                            const double* a, const double* b, const double* gK, const double* gM,
-                           double* ga, double* gb, double* gnodes, hipStream_t s) {
+                           const double* u, double* ga, double* gb, double* gnodes, hipStream_t s) {
     const int kc = kind_code(m->dim, kind);
     const int nv = m->dim + 1;
-    if (!gK && !gM) {  // L = 0: every derivative is zero
+    if (!u && !gK && !gM) {  // L = 0: every derivative is zero
         if (fem_status st = zero_f64(ga, m->T, s)) return st;
         if (fem_status st = zero_f64(gb, m->T, s)) return st;
         return zero_f64(gnodes, m->V * m->dim, s);
@@ -1137,8 +1182,11 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
         if (fem_status st = build_node_map(m, s)) return st;
         if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, m->T * nv * m->dim));
     }
-    if (fem_status st = build_slot_map(m, ds, s)) return st;
+    if (!u)
+        if (fem_status st = build_slot_map(m, ds, s)) return st;
     BwdArgs A;
+    A.u = u;
+    A.elems2dofs = ds.elems2dofs;
     A.elems = m->elems;
     A.nodes = nodes;
     A.a = a;
@@ -1155,15 +1203,9 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.err_word = m->err_word;
     const unsigned grid = (unsigned)(((m->T + 255) / 256 + 7) / 8 * 8);
     if (m->T > 0) {
-        if (gK == gM) {
-            if (kc == 2) hipLaunchKernelGGL((k_backward<2, true>), dim3(grid), dim3(256), 0, s, A);
-            else if (kc == 1) hipLaunchKernelGGL((k_backward<1, true>), dim3(grid), dim3(256), 0, s, A);
-            else hipLaunchKernelGGL((k_backward<0, true>), dim3(grid), dim3(256), 0, s, A);
-        } else {
-            if (kc == 2) hipLaunchKernelGGL((k_backward<2, false>), dim3(grid), dim3(256), 0, s, A);
-            else if (kc == 1) hipLaunchKernelGGL((k_backward<1, false>), dim3(grid), dim3(256), 0, s, A);
-            else hipLaunchKernelGGL((k_backward<0, false>), dim3(grid), dim3(256), 0, s, A);
-        }
+        if (u) launch_bwd_mode<BWD_QUADRATIC>(kc, A, grid, s);
+        else if (gK == gM) launch_bwd_mode<BWD_SAME>(kc, A, grid, s);
+        else launch_bwd_mode<BWD_SEPARATE>(kc, A, grid, s);
         FEM_HIP(hipGetLastError());
     }
     if (gnodes && m->V > 0) {

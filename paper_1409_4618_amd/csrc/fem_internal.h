@@ -179,10 +179,12 @@ struct MeshDev {
 int kind_code(int dim, fem_kind kind);
 int rows_index(int rows_per_tile);  // 32 -> 0, 64 -> 1, 128 -> 2, 256 -> 3
 fem_status launch_forward(const MeshDev& md, int rows_per_tile, int pmax, hipStream_t s);
+// Adjoint. Weights: gK, gM (either may be NULL = 0), or, when u is not NULL,
+// the quadratic form L = u^T (K(a) + M(b)) u (weights u_I u_J, gK/gM unused).
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                            const double* a, const double* b, const double* gK,
-                           const double* gM, double* ga, double* gb, double* gnodes,
-                           hipStream_t s);
+                           const double* gM, const double* u, double* ga, double* gb,
+                           double* gnodes, hipStream_t s);
 fem_status launch_batch(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
                         int rows_per_tile, int schedule, int grid, int pmax,
                         unsigned* counters, hipStream_t s);

@@ -60,6 +60,10 @@ def test_adjoint_matches_oracle(case):
     tw = weights_on_device(rowptr, colind, tu)
     gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, tw, tw)
     mesh.status()
+    # the quadratic-form entry point forms the same weights u_I u_J per element
+    qn, qa, qb = fem.assemble_backward_quadratic(mesh, kind, tn, ta, tb, tu)
+    mesh.status()
+    assert torch.equal(qn, gn) and torch.equal(qa, ga) and torch.equal(qb, gb)
     for got, ref, nm in ((ga, ga_o, "a"), (gb, gb_o, "b"), (gn, gn_o, "x")):
         got = got.cpu().numpy()
         err = np.abs(got - ref).max() / np.abs(ref).max()

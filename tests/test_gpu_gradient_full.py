@@ -2,6 +2,8 @@
 5,308,416 tets; L = u^T (K(a) + M(b)) u, u ~ N(0, 1) per edge), in the launch
 configuration bench.py times:
 
+* the quadratic-form entry point bitwise equal to the general one with the
+  materialised weights u_row u_col;
 * sampled elements and vertices against the oracle: dL/da, dL/db of 256
   random elements and dL/dx of 64 random vertices, computed by the oracle on
   the sub-mesh of those elements and of every element around those vertices,
@@ -46,6 +48,10 @@ def test_full_size_adjoint():
     K, M = fem.assemble(mesh, p.kind, tn, ta, tb)
     gn, ga, gb = fem.assemble_backward(mesh, p.kind, tn, ta, tb, w, w)
     mesh.status()
+    qn, qa, qb = fem.assemble_backward_quadratic(mesh, p.kind, tn, ta, tb, tu)
+    mesh.status()
+    assert torch.equal(qn, gn) and torch.equal(qa, ga) and torch.equal(qb, gb)
+    del qn, qa, qb
     LK = float((w * K).sum())
     LM = float((w * M).sum())
     del K, M, w
