@@ -770,8 +770,11 @@ struct BwdArgs {
     const int32_t* elems2dofs; // quadratic form: [T*nloc] global dof of each slot
     double* ga;
     double* gb;
-    double* partials;          // [T*(dim+1)][dim] vertex derivatives, node order
-    const int32_t* node_rank;  // [T*(dim+1)] position of incidence (e, v) in node order
+    double* partials;          // [pairs][dim] vertex-derivative partial per (node, workgroup)
+    const int32_t* bptr;       // [workgroups+1] pairs of each workgroup
+    const int32_t* bpair;      // pair indices by workgroup
+    const int32_t* pinc;       // [pairs+1] incidences of each pair
+    const int32_t* sinc;       // incidences sorted by (node, workgroup, element)
     int64_t T;
     int* err_word;
 };
@@ -826,15 +829,16 @@ __device__ __forceinline__ void load_u(const BwdArgs& A, int64_t e, double ue[NL
     }
 }
 
-// Vertex derivative of incidence (e, v), written at its node-order position.
-__device__ __forceinline__ void store_vertex3(const BwdArgs& A, int64_t inc, V3 d) {
-    double* p = A.partials + (int64_t)A.node_rank[inc] * 3;
+// Vertex derivative of local vertex v of the lane's element, into the
+// workgroup's LDS slot of that incidence (summed per vertex afterwards).
+__device__ __forceinline__ void store_vertex3(double* sh, int v, V3 d) {
+    double* p = sh + ((int)threadIdx.x * 4 + v) * 3;
     p[0] = d.x;
     p[1] = d.y;
     p[2] = d.z;
 }
-__device__ __forceinline__ void store_vertex2(const BwdArgs& A, int64_t inc, double dx, double dy) {
-    double* p = A.partials + (int64_t)A.node_rank[inc] * 2;
+__device__ __forceinline__ void store_vertex2(double* sh, int v, double dx, double dy) {
+    double* p = sh + ((int)threadIdx.x * 3 + v) * 2;
     p[0] = dx;
     p[1] = dy;
 }
@@ -846,7 +850,7 @@ __device__ __forceinline__ void store_vertex2(const BwdArgs& A, int64_t inc, dou
 // and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
 template <int MODE>
-__device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
+__device__ void bwd_ned3(const BwdArgs& A, int64_t e, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -952,17 +956,17 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e) {
             const V3 cj = c[jj + 1];
             const V3 dj = add(scale(sub(dPhi[jj], scale(cj, Phi / J)), fk),
                               scale(sub(dPsi[jj], scale(cj, Psi / J)), fm));
-            store_vertex3(A, e * 4 + jj + 1, dj);
+            store_vertex3(sh, jj + 1, dj);
             d0 = sub(d0, dj);
         }
-        store_vertex3(A, e * 4, d0);
+        store_vertex3(sh, 0, d0);
     }
     if (!(aJ > 0.0) || !isfinite(J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
 // 3D Raviart-Thomas
 template <int MODE>
-__device__ void bwd_rt3(const BwdArgs& A, int64_t e) {
+__device__ void bwd_rt3(const BwdArgs& A, int64_t e, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -1025,17 +1029,17 @@ double ue[4];
             const V3 dK = scale(ck, -ca * 1.5 * hK / (aJ * g.J));
             const V3 dM = scale(sub(dOm, scale(ck, Omega / g.J)), cb / (120.0 * aJ));
             const V3 da = add(dK, dM);
-            store_vertex3(A, e * 4 + a, da);
+            store_vertex3(sh, a, da);
             d0 = sub(d0, da);
         }
-        store_vertex3(A, e * 4, d0);
+        store_vertex3(sh, 0, d0);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
 // 2D (both kinds)
 template <int MODE>
-__device__ void bwd_tri(const BwdArgs& A, int64_t e) {
+__device__ void bwd_tri(const BwdArgs& A, int64_t e, double* sh) {
     int gid[3];
     V2 x[3];
 #pragma unroll
@@ -1101,31 +1105,56 @@ double ue[3];
             const V2 cj = g.c[jj + 1];
             const double dx = fk * cj.x + fm * (dPsi[jj].x - cj.x * Psi / g.J);
             const double dy = fk * cj.y + fm * (dPsi[jj].y - cj.y * Psi / g.J);
-            store_vertex2(A, e * 3 + jj + 1, dx, dy);
+            store_vertex2(sh, jj + 1, dx, dy);
             d0x -= dx;
             d0y -= dy;
         }
-        store_vertex2(A, e * 3, d0x, d0y);
+        store_vertex2(sh, 0, d0x, d0y);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
 }
 
 template <int KC, int MODE>
-__global__ __launch_bounds__(256) void k_backward(const BwdArgs A) {
+__global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
+    constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM;
+    __shared__ double sh[BWD_BLOCK * NV * DIM];
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the
     // upstream weights, and that reuse then stays in one L2.
     const int64_t per = gridDim.x / 8;
     const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    const int64_t e = blk * blockDim.x + threadIdx.x;
-    if (e >= A.T) return;
-    if constexpr (KC == 2) bwd_ned3<MODE>(A, e);
-    else if constexpr (KC == 1) bwd_rt3<MODE>(A, e);
-    else bwd_tri<MODE>(A, e);
+    const int64_t e0 = blk * BWD_BLOCK;
+    if (e0 >= A.T) return;  // whole workgroup
+    const int64_t e = e0 + threadIdx.x;
+    if (e < A.T) {
+        if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sh);
+        else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sh);
+        else bwd_tri<MODE>(A, e, sh);
+    }
+    if (!A.partials) return;  // uniform
+    __syncthreads();
+    // one partial per (vertex, workgroup): the workgroup's incidences of that
+    // vertex, in ascending element order
+    const int j0 = A.bptr[blk], j1 = A.bptr[blk + 1];
+    const int64_t i_base = e0 * NV;
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += BWD_BLOCK) {
+        const int q = A.bpair[j];
+        double acc[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+        const int i1 = A.pinc[q + 1];
+        for (int i = A.pinc[q]; i < i1; ++i) {
+            const int slot = (int)((int64_t)A.sinc[i] - i_base);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[c] += sh[slot * DIM + c];
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) A.partials[(int64_t)q * DIM + c] = acc[c];
+    }
 }
 
-// gnodes[v] = sum of the vertex derivatives of the node's incidences, which
-// are stored contiguously in node order (ascending element within a node).
+// gnodes[v] = sum of the node's (node, workgroup) partials, which are stored
+// contiguously in node order (ascending workgroup within a node).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const double* partials,
                                                       int64_t V, double* gnodes) {
@@ -1158,7 +1187,7 @@ static fem_status zero_f64(double* p, int64_t n, hipStream_t s) {
 
 template <int KC, int MODE>
 static void launch_bwd_t(const BwdArgs& A, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_backward<KC, MODE>), dim3(grid), dim3(256), 0, s, A);
+    hipLaunchKernelGGL((k_backward<KC, MODE>), dim3(grid), dim3(BWD_BLOCK), 0, s, A);
 }
 
 template <int MODE>
@@ -1172,7 +1201,6 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
                            const double* a, const double* b, const double* gK, const double* gM,
                            const double* u, double* ga, double* gb, double* gnodes, hipStream_t s) {
     const int kc = kind_code(m->dim, kind);
-    const int nv = m->dim + 1;
     if (!u && !gK && !gM) {  // L = 0: every derivative is zero
         if (fem_status st = zero_f64(ga, m->T, s)) return st;
         if (fem_status st = zero_f64(gb, m->T, s)) return st;
@@ -1180,7 +1208,7 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     }
     if (gnodes) {
         if (fem_status st = build_node_map(m, s)) return st;
-        if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, m->T * nv * m->dim));
+        if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, std::max<int64_t>(m->bwd_pairs, 1) * m->dim));
     }
     if (!u)
         if (fem_status st = build_slot_map(m, ds, s)) return st;
@@ -1198,10 +1226,13 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.ga = ga;
     A.gb = gb;
     A.partials = gnodes ? m->elem_partials : nullptr;
-    A.node_rank = m->node_rank;
+    A.bptr = m->bwd_bptr;
+    A.bpair = m->bwd_bpair;
+    A.pinc = m->bwd_pinc;
+    A.sinc = m->bwd_sinc;
     A.T = m->T;
     A.err_word = m->err_word;
-    const unsigned grid = (unsigned)(((m->T + 255) / 256 + 7) / 8 * 8);
+    const unsigned grid = (unsigned)(((m->T + BWD_BLOCK - 1) / BWD_BLOCK + 7) / 8 * 8);
     if (m->T > 0) {
         if (u) launch_bwd_mode<BWD_QUADRATIC>(kc, A, grid, s);
         else if (gK == gM) launch_bwd_mode<BWD_SAME>(kc, A, grid, s);

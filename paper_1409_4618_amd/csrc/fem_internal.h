@@ -105,15 +105,24 @@ struct fem_mesh_s {
     fem::DofSet edges;
     fem::DofSet faces;
     // backward scratch
-    double* elem_partials = nullptr; // [T*(dim+1)][dim], incidences in node order
-    int32_t* node_ptr = nullptr;     // [V+1]
-    int32_t* node_rank = nullptr;    // [T*(dim+1)] position of incidence e*(dim+1)+v in node order
+    // adjoint node map (built on first use): (node, workgroup) pairs in node-major
+    // order; see build_node_map
+    double* elem_partials = nullptr; // [pairs][dim] vertex-derivative partial of each pair
+    int32_t* node_ptr = nullptr;     // [V+1] pairs of each node
+    int32_t* bwd_pinc = nullptr;     // [pairs+1] incidences of each pair (into bwd_sinc)
+    int32_t* bwd_sinc = nullptr;     // [T*(dim+1)] incidences e*(dim+1)+v sorted by (node, workgroup, e)
+    int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (into bwd_bpair)
+    int32_t* bwd_bpair = nullptr;    // [pairs] pair indices, by workgroup
+    int64_t bwd_pairs = 0;
     int* err_word = nullptr;         // device error word
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;       // everything to free
 };
 
 namespace fem {
+
+// elements per adjoint workgroup (one per lane)
+constexpr int BWD_BLOCK = 256;
 
 // memory helpers (record the allocation in the mesh)
 hipError_t dmalloc(fem_mesh m, void** p, size_t bytes);

@@ -501,17 +501,6 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     return FEM_OK;
 }
 
-// ---------------------------------------------------------------- node map (backward)
-__global__ void k_node_keys(const int32_t* elems, int64_t n, uint64_t* keys, uint32_t* vals,
-                            int32_t* counts) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const int32_t v = elems[q];
-    keys[q] = (uint32_t)v;
-    vals[q] = (uint32_t)q;
-    atomicAdd(&counts[v], 1);
-}
-
 // Adjoint gather map: per slot (element-major order) the row start of the
 // slot's dof and the slot's column-offset record, so the adjoint reaches the
 // n_local^2 positions of an element with one level of indirection.
@@ -540,32 +529,96 @@ fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
     return FEM_OK;
 }
 
-// rank[perm[i]] = i
-__global__ void k_invert_perm(const uint32_t* perm, int64_t n, int32_t* rank) {
+// ---------------------------------------------------------------- adjoint node map
+// The adjoint runs one element per lane in workgroups of BWD_BLOCK consecutive
+// elements. A workgroup first sums, per vertex it touches, the vertex
+// derivatives of its own elements (in ascending element order, in LDS), and
+// writes one partial per (vertex, workgroup) pair; the node sum then adds the
+// pairs of a node in ascending workgroup order. Both orders are fixed, so the
+// result is deterministic, and the partials are far fewer than the incidences.
+//   pairs: the distinct (node, workgroup) keys in node-major order; pair q
+//          covers the incidences sinc[pinc[q] .. pinc[q+1]) (incidence
+//          e*(dim+1)+v, ascending);
+//   node_ptr[v] .. node_ptr[v+1]: the pairs of node v;
+//   bptr[b] .. bptr[b+1]: the pairs of workgroup b (bpair, ascending q).
+__global__ void k_inc_pair_keys(const int32_t* elems, int64_t n, int nv, int64_t n_blocks, uint64_t* keys,
+                            uint32_t* vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) rank[perm[i]] = (int32_t)i;
+    if (i >= n) return;
+    const int64_t blk = (i / nv) / BWD_BLOCK;
+    keys[i] = (uint64_t)elems[i] * (uint64_t)n_blocks + (uint64_t)blk;
+    vals[i] = (uint32_t)i;
 }
 
-// Node map of the adjoint: the (element, vertex) incidences sorted by node
-// (stable, so ascending element within a node); node_ptr delimits each node's
-// run and node_rank gives each incidence its position in that order, where the
-// adjoint writes the incidence's vertex derivative.
+__global__ void k_inc_pair_heads(const uint64_t* keys, int64_t n, uint32_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// After the exclusive scan of the head flags: pair q starts at incidence pinc[q];
+// count the pairs of each node and of each workgroup.
+__global__ void k_inc_pair_fill(const uint64_t* keys, const uint32_t* scan, int64_t n, int64_t n_blocks,
+                            int32_t* pinc, int32_t* node_cnt, int32_t* blk_cnt, uint64_t* bkey,
+                            uint32_t* bval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i != 0 && keys[i] == keys[i - 1]) return;
+    const int64_t q = scan[i];
+    pinc[q] = (int32_t)i;
+    const uint64_t node = keys[i] / (uint64_t)n_blocks;
+    const uint64_t blk = keys[i] - node * (uint64_t)n_blocks;
+    atomicAdd(&node_cnt[node], 1);
+    atomicAdd(&blk_cnt[blk], 1);
+    bkey[q] = blk;
+    bval[q] = (uint32_t)q;
+}
+
 fem_status build_node_map(fem_mesh m, hipStream_t s) {
     if (m->node_ptr) return FEM_OK;
-    const int64_t n = m->T * (m->dim + 1);
+    const int nv = m->dim + 1;
+    const int64_t n = m->T * nv;
+    const int64_t n_blocks = (m->T + BWD_BLOCK - 1) / BWD_BLOCK;
+    FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
+    FEM_HIP(dmalloc(m, &m->bwd_bptr, n_blocks + 1));
+    FEM_HIP(dmalloc(m, &m->bwd_sinc, n > 0 ? n : 1));
+    FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
+    FEM_HIP(hipMemsetAsync(m->bwd_bptr, 0, (n_blocks + 1) * sizeof(int32_t), s));
+    if (n == 0) {
+        FEM_HIP(dmalloc(m, &m->bwd_pinc, 1));
+        FEM_HIP(dmalloc(m, &m->bwd_bpair, 1));
+        FEM_HIP(hipMemsetAsync(m->bwd_pinc, 0, sizeof(int32_t), s));
+        m->bwd_pairs = 0;
+        return FEM_OK;
+    }
     TmpBufs tb;
     FEM_HIP(tb.alloc(n));
-    FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
-    FEM_HIP(dmalloc(m, &m->node_rank, n));
-    FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_node_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, tb.keys, tb.vals,
-                       m->node_ptr);
+    hipLaunchKernelGGL(k_inc_pair_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, nv, n_blocks, tb.keys, tb.vals);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n,
+                             bit_length((uint64_t)m->V * (uint64_t)n_blocks - 1), s));
+    FEM_HIP(hipMemcpyAsync(m->bwd_sinc, tb.vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_inc_pair_heads, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, n, tb.scan);
+    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(tb.scan, n, s));
+    int64_t P = 0;
+    if (fem_status st = read_count(tb.scan, tb.keys, n, s, &P)) return st;
+    m->bwd_pairs = P;
+    FEM_HIP(dmalloc(m, &m->bwd_pinc, P + 1));
+    FEM_HIP(dmalloc(m, &m->bwd_bpair, P));
+    // pair keys by workgroup, reusing the (now free) tmp key/value space after
+    // the incidence keys: bkey/bval need P entries each, P <= n
+    uint64_t* bkey = tb.keys_tmp;
+    uint32_t* bval = tb.vals_tmp;
+    hipLaunchKernelGGL(k_inc_pair_fill, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, tb.scan, n, n_blocks, m->bwd_pinc,
+                       m->node_ptr, m->bwd_bptr, bkey, bval);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, m->bwd_pinc + P, (int32_t)n);
     FEM_HIP(hipGetLastError());
     FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->node_ptr), m->V + 1, s));
-    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n,
-                             bit_length((uint64_t)m->V - 1), s));
-    hipLaunchKernelGGL(k_invert_perm, dim3(nblk(n)), dim3(TB), 0, s, tb.vals, n, m->node_rank);
-    FEM_HIP(hipGetLastError());
+    FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->bwd_bptr), n_blocks + 1, s));
+    // pairs of each workgroup, ascending pair index (stable sort by workgroup)
+    FEM_HIP(radix_sort_pairs(bkey, bval, tb.keys, tb.vals, P, bit_length((uint64_t)n_blocks - 1), s));
+    FEM_HIP(hipMemcpyAsync(m->bwd_bpair, bval, P * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     FEM_HIP(hipStreamSynchronize(s));
     return FEM_OK;
 }
