@@ -48,7 +48,10 @@ struct V3 {
 __device__ __forceinline__ V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
-__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// Dot products with fused multiply-adds: one rounding less per term than
+// separate products and sums, and fma(a, b, c) == fma(b, a, c) exactly, so
+// dot(a, b) == dot(b, a) bitwise (symmetric Gram entries and local matrices).
+__device__ __forceinline__ double dot(V3 a, V3 b) { return fma(a.x, b.x, fma(a.y, b.y, a.z * b.z)); }
 __device__ __forceinline__ V3 cross(V3 a, V3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
@@ -263,7 +266,7 @@ __device__ __forceinline__ void tri_signs(const int gid[3], double s[3]) {
     for (int l = 0; l < 3; ++l) s[l] = gid[nib(TRI_START, l)] > gid[nib(TRI_END, l)] ? 1.0 : -1.0;
 }
 
-__device__ __forceinline__ double dot2(V2 a, V2 b) { return a.x * b.x + a.y * b.y; }
+__device__ __forceinline__ double dot2(V2 a, V2 b) { return fma(a.x, b.x, a.y * b.y); }
 
 __device__ __forceinline__ void tri_row(const Geo2& g, const double s[3], int k, double ca,
                                         double cb, double Kr[3], double Mr[3]) {
