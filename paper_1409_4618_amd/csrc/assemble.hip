@@ -863,83 +863,140 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e, double* sh) {
     ned3_signs(gid, s);
     double ue[6];
     load_u<6, MODE>(A, e, ue);
-    // dPhi_j (derivative of Phi with respect to b_j) is accumulated directly:
-    // with q_k = sum_l (w_kl + w_lk) o_l,
-    //   dPhi_1 = q_1 - q_2 + q_4, dPhi_2 = q_2 - q_0 + q_5, dPhi_3 = q_0 - q_1 + q_3
-    // (o_0 = b3 - b2, o_1 = b1 - b3, o_2 = b2 - b1, o_3 = b3, o_4 = b1, o_5 = b2).
-    double Phi = 0.0;
-    V3 dPhi[3];
-    double P[10];
+    double Phi = 0.0, Psi = 0.0;
+    V3 dPhi[3], c[4], w[4];  // w_a = dPsi/dc_a
+    if constexpr (MODE == BWD_QUADRATIC) {
+        // Weights w_kl = v_k v_l with v_k = s_k u_k: both contractions are sums
+        // of squares.
+        //   Phi = |z|^2, z = sum_k v_k o_k = beta_1 b1 + beta_2 b2 + beta_3 b3,
+        //     so dPhi/db_t = 2 beta_t z;
+        //   with alpha the antisymmetric vertex matrix of v (alpha_ij = v_k for
+        //   edge k = i -> j), the Whitney field is sum_a lambda_a sum_b alpha_ab
+        //   grad lambda_b, and the mass contraction is
+        //     Psi = sum_bd G_bd sum_ac (1 + delta_ac) alpha_ab alpha_cd
+        //         = |S|^2 + sum_a |R_a|^2,
+        //     sigma_b = sum_a alpha_ab, S = sum_b sigma_b c_b, R_a = sum_b alpha_ab c_b,
+        //     dPsi/dc_b = 2 (sigma_b S + sum_a alpha_ab R_a).
+        double v[6];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) dPhi[t] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 6; ++k) v[k] = s[k] * ue[k];
+        const double beta[3] = {(v[1] - v[2]) + v[4], (v[2] - v[0]) + v[5], (v[0] - v[1]) + v[3]};
+        const V3 z = add(add(scale(b1, beta[0]), scale(b2, beta[1])), scale(b3, beta[2]));
+        Phi = dot(z, z);
 #pragma unroll
-    for (int t = 0; t < 10; ++t) P[t] = 0.0;
-    const V3 o[6] = {sub(b3, b2), sub(b1, b3), sub(b2, b1), b3, b1, b2};
-    // sign pattern of q_k in dPhi_1..3
-    constexpr int QSGN[6][3] = {{0, -1, 1}, {1, 0, -1}, {-1, 1, 0}, {0, 0, 1}, {1, 0, 0}, {0, 1, 0}};
+        for (int t = 0; t < 3; ++t) dPhi[t] = scale(z, 2.0 * beta[t]);
+        c[1] = cross(b2, b3);
+        c[2] = cross(b3, b1);
+        c[3] = cross(b1, b2);
+        c[0] = neg(add(add(c[1], c[2]), c[3]));
+        double al[4][4];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        // one row of weights at a time: the scheduler would otherwise issue all
-        // 72 gathers up front and hold them, at one wavefront per SIMD
-        __builtin_amdgcn_sched_barrier(0);
-        double gk[6], gm[6];
-        gather_row<6, MODE>(A, e, k, ue, gk, gm);
-        const int i = nib(NED3_START, k), j = nib(NED3_END, k);
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int l = 0; l < 6; ++l) {
-            const int m = nib(NED3_START, l), n = nib(NED3_END, l);
-            const double ss = s[k] * s[l];
-            const double wk = gk[l] * ss;
-            const double wm = gm[l] * ss;
-            Phi += wk * dot(o[k], o[l]);
-            // q_k += wk o_l and q_l += wk o_k, folded into dPhi
-            const V3 ol = scale(o[l], wk), ok = scale(o[k], wk);
+            for (int bb = 0; bb < 4; ++bb) al[a][bb] = 0.0;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                if (QSGN[k][t] > 0) dPhi[t] = add(dPhi[t], ol);
-                if (QSGN[k][t] < 0) dPhi[t] = sub(dPhi[t], ol);
-                if (QSGN[l][t] > 0) dPhi[t] = add(dPhi[t], ok);
-                if (QSGN[l][t] < 0) dPhi[t] = sub(dPhi[t], ok);
-            }
-            P[tri_index(j, n)] += wm * (1.0 + (i == m));
-            P[tri_index(j, m)] -= wm * (1.0 + (i == n));
-            P[tri_index(i, n)] -= wm * (1.0 + (j == m));
-            P[tri_index(i, m)] += wm * (1.0 + (j == n));
+        for (int k = 0; k < 6; ++k) {
+            al[nib(NED3_START, k)][nib(NED3_END, k)] = v[k];
+            al[nib(NED3_END, k)][nib(NED3_START, k)] = -v[k];
         }
-        // fold this row in now (the sums would otherwise be sunk into the
-        // conditional output blocks with all 72 weights live until there)
-        pin(Phi);
+        double sig[4];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) pin(dPhi[t]);
+        for (int bb = 0; bb < 4; ++bb) sig[bb] = (al[0][bb] + al[1][bb]) + (al[2][bb] + al[3][bb]);
+        V3 S = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < 10; ++t) pin(P[t]);
+        for (int bb = 0; bb < 4; ++bb) S = add(S, scale(c[bb], sig[bb]));
+        Psi = dot(S, S);
+        V3 Ra[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            Ra[a] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+                if (bb != a) Ra[a] = add(Ra[a], scale(c[bb], al[a][bb]));
+            Psi += dot(Ra[a], Ra[a]);
+        }
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            V3 t = scale(S, sig[bb]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (a != bb) t = add(t, scale(Ra[a], al[a][bb]));
+            w[bb] = scale(t, 2.0);
+        }
+    } else {
+        // dPhi_j (derivative of Phi with respect to b_j) is accumulated directly:
+        // with q_k = sum_l (w_kl + w_lk) o_l,
+        //   dPhi_1 = q_1 - q_2 + q_4, dPhi_2 = q_2 - q_0 + q_5, dPhi_3 = q_0 - q_1 + q_3
+        // (o_0 = b3 - b2, o_1 = b1 - b3, o_2 = b2 - b1, o_3 = b3, o_4 = b1, o_5 = b2).
+        double P[10];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) dPhi[t] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 10; ++t) P[t] = 0.0;
+        const V3 o[6] = {sub(b3, b2), sub(b1, b3), sub(b2, b1), b3, b1, b2};
+        // sign pattern of q_k in dPhi_1..3
+        constexpr int QSGN[6][3] = {{0, -1, 1}, {1, 0, -1}, {-1, 1, 0}, {0, 0, 1}, {1, 0, 0}, {0, 1, 0}};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            // one row of weights at a time: the scheduler would otherwise issue all
+            // 72 gathers up front and hold them, at one wavefront per SIMD
+            __builtin_amdgcn_sched_barrier(0);
+            double gk[6], gm[6];
+            gather_row<6, MODE>(A, e, k, ue, gk, gm);
+            const int i = nib(NED3_START, k), j = nib(NED3_END, k);
+#pragma unroll
+            for (int l = 0; l < 6; ++l) {
+                const int m = nib(NED3_START, l), n = nib(NED3_END, l);
+                const double ss = s[k] * s[l];
+                const double wk = gk[l] * ss;
+                const double wm = gm[l] * ss;
+                Phi += wk * dot(o[k], o[l]);
+                // q_k += wk o_l and q_l += wk o_k, folded into dPhi
+                const V3 ol = scale(o[l], wk), ok = scale(o[k], wk);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    if (QSGN[k][t] > 0) dPhi[t] = add(dPhi[t], ol);
+                    if (QSGN[k][t] < 0) dPhi[t] = sub(dPhi[t], ol);
+                    if (QSGN[l][t] > 0) dPhi[t] = add(dPhi[t], ok);
+                    if (QSGN[l][t] < 0) dPhi[t] = sub(dPhi[t], ok);
+                }
+                P[tri_index(j, n)] += wm * (1.0 + (i == m));
+                P[tri_index(j, m)] -= wm * (1.0 + (i == n));
+                P[tri_index(i, n)] -= wm * (1.0 + (j == m));
+                P[tri_index(i, m)] += wm * (1.0 + (j == n));
+            }
+            // fold this row in now (the sums would otherwise be sunk into the
+            // conditional output blocks with all 72 weights live until there)
+            pin(Phi);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) pin(dPhi[t]);
+#pragma unroll
+            for (int t = 0; t < 10; ++t) pin(P[t]);
+        }
+        // cofactor vectors after the weight loop (not live during it)
+        c[1] = cross(b2, b3);
+        c[2] = cross(b3, b1);
+        c[3] = cross(b1, b2);
+        c[0] = neg(add(add(c[1], c[2]), c[3]));
+#pragma unroll
+        for (int a = 0; a < 4; ++a) w[a] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int bb = a; bb < 4; ++bb) {
+                const double p = P[tri_index(a, bb)];
+                Psi += p * dot(c[a], c[bb]);
+                if (a == bb) {
+                    w[a] = add(w[a], scale(c[a], 2.0 * p));
+                } else {
+                    w[a] = add(w[a], scale(c[bb], p));
+                    w[bb] = add(w[bb], scale(c[a], p));
+                }
+            }
+        }
     }
-    // cofactor vectors after the weight loop (not live during it)
-    V3 c[4];
-    c[1] = cross(b2, b3);
-    c[2] = cross(b3, b1);
-    c[3] = cross(b1, b2);
-    c[0] = neg(add(add(c[1], c[2]), c[3]));
     const double J = dot(b1, c[1]);
     const double aJ = fabs(J);
-    double Psi = 0.0;
-    V3 w[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) w[a] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int bb = a; bb < 4; ++bb) {
-            const double p = P[tri_index(a, bb)];
-            Psi += p * dot(c[a], c[bb]);
-            if (a == bb) {
-                w[a] = add(w[a], scale(c[a], 2.0 * p));
-            } else {
-                w[a] = add(w[a], scale(c[bb], p));
-                w[bb] = add(w[bb], scale(c[a], p));
-            }
-        }
-    }
     const double ca = A.a ? A.a[e] : 1.0;
     const double cb = A.b ? A.b[e] : 1.0;
     if (A.ga) A.ga[e] = (2.0 / 3.0) * Phi / aJ;

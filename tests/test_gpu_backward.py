@@ -5,6 +5,10 @@ Tolerance: the adjoint and the complex-step oracle are both exact up to
 rounding; they differ by the conditioning of the per-element formulas
 (a few hundred ulps of the largest term), so the check is
 max |g_gpu - g_oracle| <= 1e-11 max |g_oracle| for each of dL/da, dL/db, dL/dx.
+The quadratic-form entry point evaluates the same contraction with weights
+formed from u (3D Nedelec: as sums of squares, a different rounding), so it
+is held to max |g_quad - g_general| <= 1e-12 max |g_general| as well as to
+the oracle.
 """
 import numpy as np
 import pytest
@@ -17,6 +21,7 @@ from oracle.gradient import grad_coefficients, grad_nodes, positions, quadratic_
 pytestmark = pytest.mark.gpu
 
 GTOL = 1e-11
+QTOL = 1e-12
 
 
 def weights_on_device(rowptr, colind, u):
@@ -60,11 +65,16 @@ def test_adjoint_matches_oracle(case):
     tw = weights_on_device(rowptr, colind, tu)
     gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, tw, tw)
     mesh.status()
-    # the quadratic-form entry point forms the same weights u_I u_J per element
+    # the quadratic-form entry point: the same contraction from u at each
+    # element's dofs
     qn, qa, qb = fem.assemble_backward_quadratic(mesh, kind, tn, ta, tb, tu)
     mesh.status()
-    assert torch.equal(qn, gn) and torch.equal(qa, ga) and torch.equal(qb, gb)
-    for got, ref, nm in ((ga, ga_o, "a"), (gb, gb_o, "b"), (gn, gn_o, "x")):
+    for q, g, nm in ((qa, ga, "a"), (qb, gb, "b"), (qn, gn, "x")):
+        err = float((q - g).abs().max()) / float(g.abs().max())
+        say(f"    quadratic vs general dL/d{nm}: {err:.2e}")
+        assert err <= QTOL, (nm, err)
+    for got, ref, nm in ((ga, ga_o, "a"), (gb, gb_o, "b"), (gn, gn_o, "x"),
+                         (qa, ga_o, "a (quadratic)"), (qb, gb_o, "b (quadratic)"), (qn, gn_o, "x (quadratic)")):
         got = got.cpu().numpy()
         err = np.abs(got - ref).max() / np.abs(ref).max()
         say(f"    dL/d{nm}: max rel err {err:.2e}")

@@ -2,8 +2,8 @@
 5,308,416 tets; L = u^T (K(a) + M(b)) u, u ~ N(0, 1) per edge), in the launch
 configuration bench.py times:
 
-* the quadratic-form entry point bitwise equal to the general one with the
-  materialised weights u_row u_col;
+* the quadratic-form entry point equal, up to rounding (1e-12 of the largest
+  value), to the general one with the materialised weights u_row u_col;
 * sampled elements and vertices against the oracle: dL/da, dL/db of 256
   random elements and dL/dx of 64 random vertices, computed by the oracle on
   the sub-mesh of those elements and of every element around those vertices,
@@ -50,7 +50,10 @@ def test_full_size_adjoint():
     mesh.status()
     qn, qa, qb = fem.assemble_backward_quadratic(mesh, p.kind, tn, ta, tb, tu)
     mesh.status()
-    assert torch.equal(qn, gn) and torch.equal(qa, ga) and torch.equal(qb, gb)
+    for q, g, nm in ((qa, ga, "a"), (qb, gb, "b"), (qn, gn, "x")):
+        err = float((q - g).abs().max()) / float(g.abs().max())
+        say(f"    quadratic vs general dL/d{nm}: {err:.2e}")
+        assert err <= 1e-12, (nm, err)
     del qn, qa, qb
     LK = float((w * K).sum())
     LM = float((w * M).sum())
