@@ -328,6 +328,10 @@ __device__ __forceinline__ double sgn_bit(uint32_t bits, int l) {
 
 // s_l * x as a flip of the sign bit (neg = 0x80000000 iff s_l = -1): bitwise
 // the product with +-1.0, without a floating-point multiply.
+// x with its sign flipped where neg has the sign bit set. Round-to-nearest is
+// symmetric under negation, so with_sign(r * t, neg) == with_sign(r, neg) * t
+// bitwise; entries flip the sign of the product, which leaves the low word in
+// place.
 __device__ __forceinline__ double with_sign(double x, uint32_t neg) {
     return __hiloint2double(__double2hiint(x) ^ (int)neg, __double2loint(x));
 }
@@ -413,7 +417,7 @@ __device__ __forceinline__ double ned3_mrow(const Ned3Mass& e) {
 
 template <int k, int l>
 __device__ __forceinline__ double ned3_K(const Ned3Elem& e, double kr) {
-    return (with_sign(kr, e.nm[l])) * dot(ned3_o_of<k>(e), ned3_o_of<l>(e));
+    return with_sign(kr * dot(ned3_o_of<k>(e), ned3_o_of<l>(e)), e.nm[l]);
 }
 
 template <int k, int l>
@@ -424,7 +428,7 @@ __device__ __forceinline__ double ned3_M(const Ned3Mass& e, double mr) {
                                   e.G[tri_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri_index(i, n)] * (1.0 + (j == m)));
-    return (with_sign(mr, e.nm[l])) * t;
+    return with_sign(mr * t, e.nm[l]);
 }
 
 struct Rt3Elem {
@@ -495,7 +499,7 @@ template <int k, int l>
 __device__ __forceinline__ double rt3_M(const Rt3Elem& e, double mr) {
     constexpr int pk = 3 - k, pl = 3 - l;
     const double t = e.base - 5.0 * (rt3_u<pk>(e) + rt3_u<pl>(e)) + 20.0 * dot(rt3_y<pk>(e), rt3_y<pl>(e));
-    return (with_sign(mr, e.nm[l])) * t;
+    return with_sign(mr * t, e.nm[l]);
 }
 
 struct TriElem {
@@ -552,7 +556,7 @@ __device__ __forceinline__ double tri_M(const TriElem& e, double mr) {
                                   e.G[tri3_index(i, m)] * (1.0 + (j == n)),
                                   e.G[tri3_index(j, m)] * (1.0 + (i == n)),
                                   e.G[tri3_index(i, n)] * (1.0 + (j == m)));
-    return (with_sign(mr, e.nm[l])) * t;
+    return with_sign(mr * t, e.nm[l]);
 }
 
 }  // namespace fem
