@@ -62,6 +62,7 @@ static void fill_ema(const DofSet& ds, int nt, MeshDev* md) {
     md->ema_ent = E.ent;
     md->ema_gid = reinterpret_cast<const int4*>(E.egid);
     md->ema_rec = E.rec;
+    md->ema_rtab = E.rtab;
     md->ema_R = E.R;
     md->ema_pmax = E.pmax;
     md->ema_max_slots = E.max_slots;

@@ -540,9 +540,9 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     // header of the tile
     const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile];
     const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile + 1];
-    const int64_t r0 = h0.x;
+    const int64_t r0 = tile * R;
+    const int nslots = h0.x;
     const int nrows = h0.y;
-    const int64_t r1 = r0 + nrows;
     const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)h0.w << 32) | (uint64_t)(uint32_t)h0.z);
     const int nt = h1.x;
     const int js0 = h1.y;
@@ -583,10 +583,11 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;
     for (int lr = tid; lr < nrows; lr += NT) {
-        rowbase[lr] = (int)(md.rowptr[r0 + lr] - p0);
-        if constexpr (KC == 2) rowslot[lr] = md.rs_ptr[r0 + lr] - js0;
+        const uint32_t rt = md.ema_rtab[r0 + lr];
+        rowbase[lr] = (int)(rt & 0xFFFFu);
+        if constexpr (KC == 2) rowslot[lr] = (int)(rt >> 16);
     }
-    if (KC == 2 && tid == 0) rowslot[nrows] = md.rs_ptr[r1] - js0;
+    if (KC == 2 && tid == 0) rowslot[nrows] = nslots;
     __syncthreads();
 
     // gather (coordinates, coefficients), then the element state

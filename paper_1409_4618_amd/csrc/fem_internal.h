@@ -68,9 +68,12 @@ struct Pattern {
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)
         uint64_t* rec = nullptr;    // [n_slots]
-        // per-tile header, 8 ints: r0, rows, p0 (lo, hi), values, first
-        // slot, first entry, entries
+        // per-tile header, 8 ints: slots, rows, p0 (lo, hi), values, first
+        // slot, first entry, entries (the first row is tile * R)
         int32_t* hdr = nullptr;     // [n_tiles][8]
+        // per row: its value offset in its tile (bits 0..15) and its first
+        // slot in the tile's slot list (16..31)
+        uint32_t* rtab = nullptr;   // [n_rows]
         int max_elems = 0;          // largest tile element list
         int max_slots = 0;          // most slots of one tile
         int pmax = 0;               // most matrix entries of one tile
@@ -179,6 +182,7 @@ struct MeshDev {
     const int2* ema_ent;
     const int4* ema_gid;
     const uint64_t* ema_rec;
+    const uint32_t* ema_rtab;
     int32_t ema_R;
     int32_t ema_pmax;
     int32_t ema_max_slots;

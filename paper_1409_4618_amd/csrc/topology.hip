@@ -813,7 +813,9 @@ static void ema_free(Pattern::Ema& e) {
     e.egid = nullptr;
     if (e.rec) (void)hipFree(e.rec);
     if (e.hdr) (void)hipFree(e.hdr);
+    if (e.rtab) (void)hipFree(e.rtab);
     e.hdr = nullptr;
+    e.rtab = nullptr;
     e.eptr = nullptr;
     e.elems = nullptr;
     e.joff = nullptr;
@@ -874,7 +876,7 @@ __global__ void k_tile_headers(int64_t n_tiles, int R, int64_t n_rows, const int
     const int64_t r1 = (r0 + R < n_rows) ? r0 + R : n_rows;
     const int64_t p0 = rowptr[r0];
     int32_t* h = hdr + t * 8;
-    h[0] = (int32_t)r0;
+    h[0] = rs_ptr[r1] - rs_ptr[r0];
     h[1] = (int32_t)(r1 - r0);
     h[2] = (int32_t)(uint32_t)(uint64_t)p0;
     h[3] = (int32_t)((uint64_t)p0 >> 32);
@@ -884,13 +886,30 @@ __global__ void k_tile_headers(int64_t n_tiles, int R, int64_t n_rows, const int
     h[7] = eptr[t + 1] - eptr[t];
 }
 
-static fem_status ema_headers(DofSet& ds, Pattern::Ema& E, hipStream_t s) {
+// Row table: each row's value offset and first slot within its tile. Both fit
+// 16 bits because a tile's values and diagonal slots fit in LDS (checked when
+// the tiles are built); the kernel raises the overflow flag otherwise.
+__global__ void k_tile_rows(int64_t n_rows, int R, const int64_t* rowptr, const int32_t* rs_ptr,
+                            uint32_t* rtab, int* overflow) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t r0 = (r / R) * R;
+    const int64_t pv = rowptr[r] - rowptr[r0];
+    const int64_t ps = (int64_t)rs_ptr[r] - rs_ptr[r0];
+    if (pv > 0xFFFF || ps > 0xFFFF) atomicOr(overflow, 1);
+    rtab[r] = (uint32_t)(pv & 0xFFFF) | ((uint32_t)(ps & 0xFFFF) << 16);
+}
+
+static fem_status ema_headers(DofSet& ds, Pattern::Ema& E, int* overflow, hipStream_t s) {
     if (ds.pat.n_rows >= (int64_t(1) << 31))
         return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 rows");
     FEM_HIP(hipMalloc((void**)&E.hdr, (size_t)std::max<int64_t>(E.n_tiles, 1) * 8 * sizeof(int32_t)));
+    FEM_HIP(hipMalloc((void**)&E.rtab, (size_t)std::max<int64_t>(ds.pat.n_rows, 1) * sizeof(uint32_t)));
     if (E.n_tiles == 0) return FEM_OK;
     hipLaunchKernelGGL(k_tile_headers, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.n_tiles, E.R,
                        ds.pat.n_rows, ds.pat.rowptr, ds.rs_ptr, E.eptr, E.hdr);
+    hipLaunchKernelGGL(k_tile_rows, dim3(nblk(ds.pat.n_rows)), dim3(TB), 0, s, ds.pat.n_rows, E.R,
+                       ds.pat.rowptr, ds.rs_ptr, E.rtab, overflow);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
@@ -914,11 +933,11 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream
                        E.joff, ds.rs_ptr, slot_row, ds.pat.colpos, ds.pat.cp_stride, ds.nloc, E.R,
                        m->elems, m->dim + 1, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, overflow);
     FEM_HIP(hipGetLastError());
+    if (fem_status st = ema_headers(ds, E, overflow, s)) return st;
     int h = 0;
     FEM_HIP(hipMemcpyAsync(&h, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
     if (h) return fail(FEM_EOVERFLOW, "fem_pattern: a tile row or slot index exceeds its record field");
-    if (fem_status st = ema_headers(ds, E, s)) return st;
     // the build-only arrays
     (void)hipFree(E.elems);
     (void)hipFree(E.joff);
@@ -962,6 +981,7 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             m->allocs.push_back(cand.egid);
             m->allocs.push_back(cand.rec);
             m->allocs.push_back(cand.hdr);
+            m->allocs.push_back(cand.rtab);
             cand.NT = nt;
             cand.built = true;
             cand.usable = cand.max_elems <= nt;
