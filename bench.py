@@ -273,6 +273,43 @@ def calib_copy():
     return 2 * src.numel() * 8
 
 
+def stream_ceiling(kernel_ms, traffic):
+    """Practical HBM rates of plain streaming kernels (torch's fill, copy and a
+    broadcast copy that reads N and writes 2N doubles, about the forward kernel's
+    read:write mix), with N = 28 Mi doubles. The forward kernel's measured
+    traffic rate is reported beside them when its profile is current."""
+    import torch
+    n = 28 << 20
+    x = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty(2 * n, dtype=torch.float64, device="cuda:0")
+    z = torch.empty(n, dtype=torch.float64, device="cuda:0")
+
+    def best_ms(fn, reps=30):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = float("inf")
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    fill = 2 * n * 8 / best_ms(lambda: y.fill_(1.0)) / 1e6
+    copy = 2 * n * 8 / best_ms(lambda: z.copy_(x)) / 1e6
+    mix = 3 * n * 8 / best_ms(lambda: y.view(n, 2).copy_(x.unsqueeze(1).expand(n, 2))) / 1e6
+    del x, y, z
+    out = {"unit": "GB/s", "fill": round(fill, 1), "copy": round(copy, 1), "read1_write2": round(mix, 1)}
+    if traffic:
+        rate = traffic / (kernel_ms * 1e-3) / 1e9
+        out["forward_traffic_rate"] = round(rate, 1)
+        out["forward_over_read1_write2"] = round(rate / mix, 4)
+    return out
+
+
 def only_workload(args):
     import meshgen as mg
     if args.only in ("kuhn128_ned3d", "kuhn128_rt3d"):
@@ -347,6 +384,8 @@ def main():
     if args.quick:
         print(json.dumps(result), flush=True)
         return
+    log("bench: streaming ceilings")
+    result["stream_ceiling"] = stream_ceiling(f64["ms"], result["roofline"]["traffic"])
     result["cold_ms"] = round(cold_rate(p64, s64), 6)
     result["cold_end_to_end_s"] = {"topology": round(s64["t_topology"], 4), "pattern": round(s64["t_pattern"], 4)}
     del s64
