@@ -73,6 +73,13 @@ def algorithmic_bytes(T, V, dim, nnz, with_coeffs=True):
     return T * (dim + 1) * 4 + V * dim * 8 + (16 * T if with_coeffs else 0) + 16 * nnz
 
 
+def adjoint_bytes(T, V, dim, n_dofs):
+    """Compulsory bytes of the quadratic-form adjoint: read elems, coordinates
+    (each node once), a, b and u (each dof once); write dL/da and dL/db. The
+    vertex derivatives are written by the node sum, not counted here."""
+    return T * (dim + 1) * 4 + V * dim * 8 + 16 * T + 8 * n_dofs + 16 * T
+
+
 def timed(fn, steps, warmup, sync_each=False):
     """Average ms per call of fn() on the current stream, HIP events around the
     timed region, synchronised on both sides."""
@@ -176,6 +183,10 @@ def fwd_bwd_rate(p, steps, warmup):
                fwd_ms=fwd["ms"], bwd_ms=ms_b, bwd_general_ms=ms_bg, fwd_mtets=fwd["mtets"],
                fwd_bwd_mtets=p.T / ((fwd["ms"] + ms_b) * 1e-3) / 1e6)
     out["fwd_bwd_over_fwd"] = out["fwd_bwd_mtets"] / out["fwd_mtets"]
+    nb = adjoint_bytes(p.T, int(p.nodes.shape[0]), p.dim, int(rowptr.numel() - 1))
+    out["bwd_bytes"] = nb
+    out["bwd_achieved_gbs"] = nb / (ms_b * 1e-3) / 1e9
+    out["bwd_frac"] = out["bwd_achieved_gbs"] / PEAK_HBM_GBS
     return out
 
 
@@ -216,6 +227,8 @@ def batched_rate(steps, warmup, ref_mtets, scale=1.0):
         Ks.append(torch.empty(nnz, dtype=torch.float64, device=d))
         Ms.append(torch.empty(nnz, dtype=torch.float64, device=d))
     T_total = sum(p.T for p in probs)
+    bytes_total = sum(algorithmic_bytes(p.T, int(p.nodes.shape[0]), p.dim, int(K.numel()), p.a is not None)
+                      for p, K in zip(probs, Ks))
     B = fem.Batch(meshes, kinds)
     B.bind(nodes, a, b, Ks, Ms)
     cache = os.path.join(ROOT, "gpurun_out", "fem_batch_tune.jsonl")
@@ -236,7 +249,10 @@ def batched_rate(steps, warmup, ref_mtets, scale=1.0):
     return dict(workload=f"256 meshes (2D/3D, Nedelec/RT), {T_total} elements",
                 elements=T_total, ms_graph=ms_graph, ms_direct=ms_direct, ms_sequential=ms_seq,
                 mtets=mt, sequential_mtets=T_total / (ms_seq * 1e-3) / 1e6,
-                over_plain_forward=mt / ref_mtets, over_sequential=ms_seq / ms_graph, tuned=cfg)
+                over_plain_forward=mt / ref_mtets if ref_mtets else None, over_sequential=ms_seq / ms_graph,
+                tuned=cfg,
+                bytes=bytes_total, achieved_gbs=bytes_total / (ms_graph * 1e-3) / 1e9,
+                frac=bytes_total / (ms_graph * 1e-3) / 1e9 / PEAK_HBM_GBS)
 
 
 def cpu_baseline(p, target_seconds=12.0):
@@ -321,7 +337,7 @@ def only_workload(args):
     elif args.only == "kuhn96_fwd_bwd":
         out = fwd_bwd_rate(mg.kuhn96_ned_grad(), args.steps, args.warmup)
     else:
-        out = batched_rate(args.steps, args.warmup, float("nan"))
+        out = batched_rate(args.steps, args.warmup, None)
     if args.calib_copy:
         out["calib_copy_bytes"] = calib_copy()
     return out
