@@ -988,9 +988,11 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             E = cand;
             return FEM_OK;
         }
-        // shrink the tile in proportion to the overshoot
+        // shrink the tile in proportion to the overshoot: exactly at first (the
+        // largest tile that fits keeps the grid's last round of workgroups as
+        // full as possible), with a margin once that has not converged
         const double f = cand.max_elems > nt ? (double)nt / cand.max_elems : 0.5;
-        int R2 = (int)(R * f * 0.97);
+        int R2 = (int)(R * f * (attempt < 2 ? 1.0 : 0.97));
         if (R2 >= R) R2 = R - 1;
         R = R2 < 4 ? 4 : R2;
         ema_free(cand);
