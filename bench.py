@@ -31,10 +31,11 @@ PEAK_HBM_GBS = 8000.0
 
 # rocprofv3 summary of the headline kernel (FETCH_SIZE / WRITE_SIZE passes,
 # calibrated with a 1 GiB device copy); its traffic figure is reported only
-# while the kernel sources still hash to the value it was measured with.
+# while the kernel sources, and the tile builder that sizes the tiles, still
+# hash to the value it was measured with.
 PROFILE = os.path.join(ROOT, "profiles", "fem_forward_ema_ned3d_kuhn64.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4618_amd", "csrc", f)
-                  for f in ("assemble.hip", "element.h", "fem_internal.h")]
+                  for f in ("assemble.hip", "element.h", "fem_internal.h", "topology.hip")]
 
 
 def log(*a):
