@@ -772,10 +772,9 @@ struct BwdArgs {
     double* ga;
     double* gb;
     double* partials;          // [pairs][dim] vertex-derivative partial per (node, workgroup)
-    const int32_t* bptr;       // [workgroups+1] pairs of each workgroup
-    const int32_t* bpair;      // pair indices by workgroup
-    const int32_t* pinc;       // [pairs+1] incidences of each pair
-    const int32_t* sinc;       // incidences sorted by (node, workgroup, element)
+    const int32_t* bptr;       // [workgroups+1] pairs of each workgroup (workgroup-major)
+    const uint16_t* pst;       // [pairs] first incidence of each pair, workgroup-local
+    const uint16_t* inc;       // workgroup-local incidences by workgroup, node, element
     int64_t T;
     int* err_word;
 };
@@ -1175,7 +1174,10 @@ double ue[3];
 template <int KC, int MODE>
 __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM;
-    __shared__ double sh[BWD_BLOCK * NV * DIM];
+    constexpr int NINC = BWD_BLOCK * NV;
+    __shared__ double sh[NINC * DIM];
+    __shared__ uint16_t s_inc[NINC];
+    __shared__ uint16_t s_pst[NINC];
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the
     // upstream weights, and that reuse then stays in one L2.
@@ -1184,6 +1186,18 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     const int64_t e0 = blk * BWD_BLOCK;
     if (e0 >= A.T) return;  // whole workgroup
     const int64_t e = e0 + threadIdx.x;
+    const int n_inc = (int)((A.T - e0 < BWD_BLOCK ? A.T - e0 : BWD_BLOCK) * NV);
+    int pb0 = 0, np = 0;
+    if (A.partials) {
+        // the workgroup's part of the node map, into LDS first: its loads are
+        // in flight while the elements are computed
+        pb0 = A.bptr[blk];
+        np = A.bptr[blk + 1] - pb0;
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(A.inc + e0 * NV);  // 4-byte aligned: e0 * NV is even
+        for (int i = (int)threadIdx.x; 2 * i < n_inc; i += BWD_BLOCK)
+            reinterpret_cast<uint32_t*>(s_inc)[i] = w[i];
+        for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) s_pst[j] = A.pst[pb0 + j];
+    }
     if (e < A.T) {
         if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sh);
         else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sh);
@@ -1193,29 +1207,27 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     __syncthreads();
     // one partial per (vertex, workgroup): the workgroup's incidences of that
     // vertex, in ascending element order
-    const int j0 = A.bptr[blk], j1 = A.bptr[blk + 1];
-    const int64_t i_base = e0 * NV;
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += BWD_BLOCK) {
-        const int q = A.bpair[j];
+    for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) {
+        const int i0 = s_pst[j];
+        const int i1 = j + 1 < np ? s_pst[j + 1] : n_inc;
         double acc[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
-        const int i1 = A.pinc[q + 1];
-        for (int i = A.pinc[q]; i < i1; ++i) {
-            const int slot = (int)((int64_t)A.sinc[i] - i_base);
+        for (int i = i0; i < i1; ++i) {
+            const int slot = s_inc[i];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) acc[c] += sh[slot * DIM + c];
         }
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) A.partials[(int64_t)q * DIM + c] = acc[c];
+        for (int c = 0; c < DIM; ++c) A.partials[(int64_t)(pb0 + j) * DIM + c] = acc[c];
     }
 }
 
-// gnodes[v] = sum of the node's (node, workgroup) partials, which are stored
-// contiguously in node order (ascending workgroup within a node).
+// gnodes[v] = sum of the node's (node, workgroup) partials, in ascending
+// workgroup order (npair lists them by node).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const double* partials,
-                                                      int64_t V, double* gnodes) {
+__global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const int32_t* npair,
+                                                      const double* partials, int64_t V, double* gnodes) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     double acc[DIM];
@@ -1224,8 +1236,9 @@ __global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, co
     const int64_t j1 = node_ptr[v + 1];
 #pragma unroll 4
     for (int64_t j = node_ptr[v]; j < j1; ++j) {
+        const int64_t q = npair[j];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] += partials[j * DIM + c];
+        for (int c = 0; c < DIM; ++c) acc[c] += partials[q * DIM + c];
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) gnodes[v * DIM + c] = acc[c];
@@ -1285,9 +1298,8 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.gb = gb;
     A.partials = gnodes ? m->elem_partials : nullptr;
     A.bptr = m->bwd_bptr;
-    A.bpair = m->bwd_bpair;
-    A.pinc = m->bwd_pinc;
-    A.sinc = m->bwd_sinc;
+    A.pst = m->bwd_pst;
+    A.inc = m->bwd_inc;
     A.T = m->T;
     A.err_word = m->err_word;
     const unsigned grid = (unsigned)(((m->T + BWD_BLOCK - 1) / BWD_BLOCK + 7) / 8 * 8);
@@ -1300,10 +1312,10 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     if (gnodes && m->V > 0) {
         const unsigned gv = (unsigned)((m->V + 255) / 256);
         if (m->dim == 3)
-            hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr,
+            hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->bwd_npair,
                                m->elem_partials, m->V, gnodes);
         else
-            hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr,
+            hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->bwd_npair,
                                m->elem_partials, m->V, gnodes);
         FEM_HIP(hipGetLastError());
     }

@@ -111,11 +111,11 @@ struct fem_mesh_s {
     // adjoint node map (built on first use): (node, workgroup) pairs in node-major
     // order; see build_node_map
     double* elem_partials = nullptr; // [pairs][dim] vertex-derivative partial of each pair
-    int32_t* node_ptr = nullptr;     // [V+1] pairs of each node
-    int32_t* bwd_pinc = nullptr;     // [pairs+1] incidences of each pair (into bwd_sinc)
-    int32_t* bwd_sinc = nullptr;     // [T*(dim+1)] incidences e*(dim+1)+v sorted by (node, workgroup, e)
-    int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (into bwd_bpair)
-    int32_t* bwd_bpair = nullptr;    // [pairs] pair indices, by workgroup
+    int32_t* node_ptr = nullptr;     // [V+1] pairs of each node (into bwd_npair)
+    int32_t* bwd_npair = nullptr;    // [pairs] pair indices by node, ascending workgroup
+    int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (pairs are workgroup-major)
+    uint16_t* bwd_pst = nullptr;     // [pairs] first incidence of each pair, workgroup-local
+    uint16_t* bwd_inc = nullptr;     // [T*(dim+1)+1] workgroup-local incidences, by workgroup, node, element
     int64_t bwd_pairs = 0;
     int* err_word = nullptr;         // device error word
     hipStream_t last_stream = nullptr;

@@ -536,42 +536,53 @@ fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
 // writes one partial per (vertex, workgroup) pair; the node sum then adds the
 // pairs of a node in ascending workgroup order. Both orders are fixed, so the
 // result is deterministic, and the partials are far fewer than the incidences.
-//   pairs: the distinct (node, workgroup) keys in node-major order; pair q
-//          covers the incidences sinc[pinc[q] .. pinc[q+1]) (incidence
-//          e*(dim+1)+v, ascending);
-//   node_ptr[v] .. node_ptr[v+1]: the pairs of node v;
-//   bptr[b] .. bptr[b+1]: the pairs of workgroup b (bpair, ascending q).
-__global__ void k_inc_pair_keys(const int32_t* elems, int64_t n, int nv, int64_t n_blocks, uint64_t* keys,
-                            uint32_t* vals) {
+// Layout, workgroup-major so a workgroup reads its part contiguously:
+//   bwd_inc [T*(dim+1)] u16: workgroup b's incidences occupy positions
+//       b*BWD_BLOCK*(dim+1) onwards, each as its workgroup-local index
+//       (e - b*BWD_BLOCK)*(dim+1) + v, sorted by (node, element);
+//   bwd_bptr [workgroups+1]: the pairs of workgroup b are bptr[b] .. bptr[b+1],
+//       in ascending node order; pair q's partial is partials[q];
+//   bwd_pst [pairs] u16: the workgroup-local position in bwd_inc of the first
+//       incidence of each pair (the pair ends where the next one starts, or at
+//       the end of the workgroup's incidences);
+//   node_ptr [V+1], bwd_npair [pairs]: the pairs of each node, ascending
+//       workgroup.
+__global__ void k_inc_wg_keys(const int32_t* elems, int64_t n, int nv, int64_t V, uint64_t* keys,
+                              uint32_t* vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t blk = (i / nv) / BWD_BLOCK;
-    keys[i] = (uint64_t)elems[i] * (uint64_t)n_blocks + (uint64_t)blk;
+    keys[i] = (uint64_t)blk * (uint64_t)V + (uint64_t)elems[i];
     vals[i] = (uint32_t)i;
 }
 
-__global__ void k_inc_pair_heads(const uint64_t* keys, int64_t n, uint32_t* flag) {
+// After the stable sort by (workgroup, node): local incidence index and pair
+// head flags.
+__global__ void k_inc_wg_local(const uint64_t* keys, const uint32_t* vals, int64_t n, int nv,
+                               uint16_t* inc, uint32_t* flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t wg_first = ((int64_t)vals[i] / (nv * BWD_BLOCK)) * (nv * BWD_BLOCK);
+    inc[i] = (uint16_t)((int64_t)vals[i] - wg_first);
     flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
 }
 
-// After the exclusive scan of the head flags: pair q starts at incidence pinc[q];
-// count the pairs of each node and of each workgroup.
-__global__ void k_inc_pair_fill(const uint64_t* keys, const uint32_t* scan, int64_t n, int64_t n_blocks,
-                            int32_t* pinc, int32_t* node_cnt, int32_t* blk_cnt, uint64_t* bkey,
-                            uint32_t* bval) {
+// After the exclusive scan of the head flags: pair starts, and the pair counts
+// of each node and of each workgroup; node keys for the node-major pair list.
+__global__ void k_inc_wg_pairs(const uint64_t* keys, const uint32_t* scan, int64_t n, int nv, int64_t V,
+                               uint16_t* pst, int32_t* node_cnt, int32_t* blk_cnt, uint64_t* nkey,
+                               uint32_t* nval) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (i != 0 && keys[i] == keys[i - 1]) return;
     const int64_t q = scan[i];
-    pinc[q] = (int32_t)i;
-    const uint64_t node = keys[i] / (uint64_t)n_blocks;
-    const uint64_t blk = keys[i] - node * (uint64_t)n_blocks;
+    const uint64_t blk = keys[i] / (uint64_t)V;
+    const uint64_t node = keys[i] - blk * (uint64_t)V;
+    pst[q] = (uint16_t)(i - (int64_t)blk * nv * BWD_BLOCK);
     atomicAdd(&node_cnt[node], 1);
     atomicAdd(&blk_cnt[blk], 1);
-    bkey[q] = blk;
-    bval[q] = (uint32_t)q;
+    nkey[q] = node;
+    nval[q] = (uint32_t)q;
 }
 
 fem_status build_node_map(fem_mesh m, hipStream_t s) {
@@ -579,46 +590,47 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
     const int nv = m->dim + 1;
     const int64_t n = m->T * nv;
     const int64_t n_blocks = (m->T + BWD_BLOCK - 1) / BWD_BLOCK;
+    static_assert(BWD_BLOCK * 4 <= 65536, "workgroup-local incidence indices are 16-bit");
     FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
     FEM_HIP(dmalloc(m, &m->bwd_bptr, n_blocks + 1));
-    FEM_HIP(dmalloc(m, &m->bwd_sinc, n > 0 ? n : 1));
+    FEM_HIP(dmalloc(m, &m->bwd_inc, (n > 0 ? n : 1) + 1));   // +1: read as 32-bit words
     FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
     FEM_HIP(hipMemsetAsync(m->bwd_bptr, 0, (n_blocks + 1) * sizeof(int32_t), s));
+    FEM_HIP(hipMemsetAsync(m->bwd_inc, 0, ((n > 0 ? n : 1) + 1) * sizeof(uint16_t), s));
     if (n == 0) {
-        FEM_HIP(dmalloc(m, &m->bwd_pinc, 1));
-        FEM_HIP(dmalloc(m, &m->bwd_bpair, 1));
-        FEM_HIP(hipMemsetAsync(m->bwd_pinc, 0, sizeof(int32_t), s));
+        FEM_HIP(dmalloc(m, &m->bwd_pst, 1));
+        FEM_HIP(dmalloc(m, &m->bwd_npair, 1));
         m->bwd_pairs = 0;
         return FEM_OK;
     }
     TmpBufs tb;
     FEM_HIP(tb.alloc(n));
-    hipLaunchKernelGGL(k_inc_pair_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, nv, n_blocks, tb.keys, tb.vals);
+    hipLaunchKernelGGL(k_inc_wg_keys, dim3(nblk(n)), dim3(TB), 0, s, m->elems, n, nv, m->V, tb.keys, tb.vals);
     FEM_HIP(hipGetLastError());
     FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n,
                              bit_length((uint64_t)m->V * (uint64_t)n_blocks - 1), s));
-    FEM_HIP(hipMemcpyAsync(m->bwd_sinc, tb.vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_inc_pair_heads, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, n, tb.scan);
+    hipLaunchKernelGGL(k_inc_wg_local, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, tb.vals, n, nv, m->bwd_inc,
+                       tb.scan);
     FEM_HIP(hipGetLastError());
     FEM_HIP(scan_exclusive_u32(tb.scan, n, s));
     int64_t P = 0;
     if (fem_status st = read_count(tb.scan, tb.keys, n, s, &P)) return st;
     m->bwd_pairs = P;
-    FEM_HIP(dmalloc(m, &m->bwd_pinc, P + 1));
-    FEM_HIP(dmalloc(m, &m->bwd_bpair, P));
-    // pair keys by workgroup, reusing the (now free) tmp key/value space after
-    // the incidence keys: bkey/bval need P entries each, P <= n
-    uint64_t* bkey = tb.keys_tmp;
-    uint32_t* bval = tb.vals_tmp;
-    hipLaunchKernelGGL(k_inc_pair_fill, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, tb.scan, n, n_blocks, m->bwd_pinc,
-                       m->node_ptr, m->bwd_bptr, bkey, bval);
-    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, m->bwd_pinc + P, (int32_t)n);
+    FEM_HIP(dmalloc(m, &m->bwd_pst, P));
+    FEM_HIP(dmalloc(m, &m->bwd_npair, P));
+    // node keys of the pairs, in the (now free) tmp key/value space after the
+    // incidence keys: P <= n entries each
+    uint64_t* nkey = tb.keys_tmp;
+    uint32_t* nval = tb.vals_tmp;
+    hipLaunchKernelGGL(k_inc_wg_pairs, dim3(nblk(n)), dim3(TB), 0, s, tb.keys, tb.scan, n, nv, m->V, m->bwd_pst,
+                       m->node_ptr, m->bwd_bptr, nkey, nval);
     FEM_HIP(hipGetLastError());
     FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->node_ptr), m->V + 1, s));
     FEM_HIP(scan_exclusive_u32(reinterpret_cast<uint32_t*>(m->bwd_bptr), n_blocks + 1, s));
-    // pairs of each workgroup, ascending pair index (stable sort by workgroup)
-    FEM_HIP(radix_sort_pairs(bkey, bval, tb.keys, tb.vals, P, bit_length((uint64_t)n_blocks - 1), s));
-    FEM_HIP(hipMemcpyAsync(m->bwd_bpair, bval, P * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    // pairs of each node, ascending workgroup (stable sort of the workgroup-major
+    // pair list by node)
+    FEM_HIP(radix_sort_pairs(nkey, nval, tb.keys, tb.vals, P, bit_length((uint64_t)m->V - 1), s));
+    FEM_HIP(hipMemcpyAsync(m->bwd_npair, nval, P * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     FEM_HIP(hipStreamSynchronize(s));
     return FEM_OK;
 }
