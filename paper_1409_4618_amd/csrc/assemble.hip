@@ -546,7 +546,6 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)h0.w << 32) | (uint64_t)(uint32_t)h0.z);
     const int nt = h1.x;
     const int js0 = h1.y;
-    const int e_beg = h1.z;
     const int ne = h1.w;  // <= NT (checked when the tiles are built)
     // LDS layout
     double* out = reinterpret_cast<double*>(smem);
@@ -556,7 +555,10 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     int* rowdiag = rowslot + R + 1;
 
     // this lane's element: entry, node ids and slot records first, so their
-    // latency overlaps the LDS set-up below
+    // latency overlaps the LDS set-up below. A tile's entries sit at a fixed
+    // stride, so they load together with the header.
+    const int2 en = md.ema_ent[tile * NT + tid];
+    const int4 q = md.ema_gid[tile * NT + tid];  // the element's node ids, streamed with the entry
     const bool have = tid < ne;
     int64_t e = 0;
     uint32_t mask = 0;
@@ -567,14 +569,12 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
 #pragma unroll
     for (int k = 0; k < NLOC; ++k) cp[k] = 0;
     if (have) {
-        const int2 en = md.ema_ent[e_beg + tid];
         e = en.x;
         mask = (uint32_t)en.y & 0x3Fu;
         const int64_t roff = (int64_t)js0 + ((uint32_t)en.y >> 8);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k)
             if ((mask >> k) & 1u) cp[k] = md.ema_rec[roff + __popc(mask & ((1u << k) - 1u))];
-        const int4 q = md.ema_gid[e_beg + tid];  // the element's node ids, streamed with the entry
         gid[0] = q.x;
         gid[1] = q.y;
         gid[2] = q.z;

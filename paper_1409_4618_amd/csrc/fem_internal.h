@@ -60,10 +60,10 @@ struct Pattern {
         int32_t* eptr = nullptr;    // [n_tiles+1]
         int32_t* elems = nullptr;   // [n_entries] (build only)
         uint16_t* joff = nullptr;   // [n_entries][8] (build only)
-        // entry i of a tile: (element, in-tile local dofs (6 bits) | offset of
-        // its first record in the tile << 8)
-        int2* ent = nullptr;        // [n_entries]
-        int32_t* egid = nullptr;    // [n_entries][4] node ids of the entry's element (zero-padded in 2D)
+        // entry i of tile t, at t * NT + i: (element, in-tile local dofs (6
+        // bits) | offset of its first record in the tile << 8)
+        int2* ent = nullptr;        // [n_tiles * NT]
+        int32_t* egid = nullptr;    // [n_tiles * NT][4] node ids of the entry's element (zero-padded in 2D)
         // record of an in-tile slot, grouped by entry, ascending local dof:
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)

@@ -847,7 +847,7 @@ __global__ void k_slot_rows(const int32_t* rs_ptr, int64_t n_rows, int32_t* slot
 __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_t* elems,
                               const uint16_t* joff, const int32_t* rs_ptr, const int32_t* slot_row,
                               const uint8_t* colpos, int cp_stride, int nloc, int R,
-                              const int32_t* elem_nodes, int nv, int2* ent, int4* egid,
+                              const int32_t* elem_nodes, int nv, int stride, int2* ent, int4* egid,
                               uint64_t* rec, int* overflow) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
@@ -871,9 +871,10 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
         }
         if (off > 0xFFFFFFu) atomicOr(overflow, 1);
         const int64_t e = elems[i];
-        ent[i] = make_int2((int)e, (int)(mask | (off << 8)));
+        const int64_t pi = t * stride + (i - eptr[t]);  // fixed stride per tile
+        ent[pi] = make_int2((int)e, (int)(mask | (off << 8)));
         const int32_t* q = elem_nodes + e * nv;
-        egid[i] = make_int4(q[0], q[1], q[2], nv == 4 ? q[3] : 0);
+        egid[pi] = make_int4(q[0], q[1], q[2], nv == 4 ? q[3] : 0);
         off += cnt;
     }
 }
@@ -894,7 +895,7 @@ __global__ void k_tile_headers(int64_t n_tiles, int R, int64_t n_rows, const int
     h[3] = (int32_t)((uint64_t)p0 >> 32);
     h[4] = (int32_t)(rowptr[r1] - p0);
     h[5] = rs_ptr[r0];
-    h[6] = eptr[t];
+    h[6] = eptr[t];  // first entry in the compact order (the entry arrays are strided)
     h[7] = eptr[t + 1] - eptr[t];
 }
 
@@ -926,13 +927,20 @@ static fem_status ema_headers(DofSet& ds, Pattern::Ema& E, int* overflow, hipStr
     return FEM_OK;
 }
 
-static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream_t s) {
+// Tile t's entries sit at t * stride onwards (stride = nt whenever the tiles
+// fit their workgroup, the only case in which a kernel reads them), so a
+// workgroup can load its entries together with its header. Unused positions
+// are zero.
+static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, int nt, hipStream_t s) {
     const int64_t n_slots = m->T * ds.nloc;
-    int32_t n_ent = 0;
-    FEM_HIP(hipMemcpyAsync(&n_ent, E.eptr + E.n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    FEM_HIP(hipStreamSynchronize(s));
-    FEM_HIP(hipMalloc((void**)&E.ent, (size_t)std::max<int32_t>(n_ent, 1) * sizeof(int2)));
-    FEM_HIP(hipMalloc((void**)&E.egid, (size_t)std::max<int32_t>(n_ent, 1) * sizeof(int4)));
+    const int stride = std::max(nt, E.max_elems);
+    const int64_t n_pad = std::max<int64_t>(E.n_tiles * stride, 1);
+    if (E.n_tiles * stride >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 tile entries");
+    FEM_HIP(hipMalloc((void**)&E.ent, (size_t)n_pad * sizeof(int2)));
+    FEM_HIP(hipMalloc((void**)&E.egid, (size_t)n_pad * sizeof(int4)));
+    FEM_HIP(hipMemsetAsync(E.ent, 0, (size_t)n_pad * sizeof(int2), s));
+    FEM_HIP(hipMemsetAsync(E.egid, 0, (size_t)n_pad * sizeof(int4), s));
     FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * sizeof(uint64_t)));
     TmpBufs tb;
     FEM_HIP(tb.alloc(std::max<int64_t>(n_slots, 1)));
@@ -943,7 +951,7 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, hipStream
                        slot_row);
     hipLaunchKernelGGL(k_ema_records, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.eptr, E.n_tiles, E.elems,
                        E.joff, ds.rs_ptr, slot_row, ds.pat.colpos, ds.pat.cp_stride, ds.nloc, E.R,
-                       m->elems, m->dim + 1, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, overflow);
+                       m->elems, m->dim + 1, stride, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, overflow);
     FEM_HIP(hipGetLastError());
     if (fem_status st = ema_headers(ds, E, overflow, s)) return st;
     int h = 0;
@@ -983,7 +991,7 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
                 return fail(FEM_EOVERFLOW, "fem_pattern: a row tile needs more LDS than the device has");
             }
             fem_status so = ema_order(cand, ds.nloc, s);
-            if (so == FEM_OK) so = ema_records(m, ds, cand, s);
+            if (so == FEM_OK) so = ema_records(m, ds, cand, nt, s);
             if (so != FEM_OK) {
                 ema_free(cand);
                 return so;
