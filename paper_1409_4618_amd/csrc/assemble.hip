@@ -792,15 +792,22 @@ enum BwdMode { BWD_SEPARATE = 0, BWD_SAME = 1, BWD_QUADRATIC = 2 };
 // gathers into separate blocks); the launcher handles both missing. In the
 // quadratic mode, uk = u[dof k] and ue[] = u[dofs of the element]: u_I u_J is
 // the same product, bitwise, that the materialised weights hold.
+// This lane's slot records (row start, column offsets): staged in LDS by the
+// workgroup at kernel start (3D Nedelec), or read in place.
+struct SlotView {
+    const int64_t* base;
+    const uint64_t* cp;
+};
+
 template <int NLOC, int MODE>
-__device__ __forceinline__ void gather_row(const BwdArgs& A, int64_t e, int k, const double ue[NLOC],
+__device__ __forceinline__ void gather_row(const BwdArgs& A, const SlotView& sv, int k, const double ue[NLOC],
                                            double wk[NLOC], double wm[NLOC]) {
     if constexpr (MODE == BWD_QUADRATIC) {
 #pragma unroll
         for (int l = 0; l < NLOC; ++l) wk[l] = wm[l] = ue[k] * ue[l];
     } else {
-        const int64_t base = A.slot_base[e * NLOC + k];
-        const uint64_t cp = A.slot_cp[e * NLOC + k];
+        const int64_t base = sv.base[k];
+        const uint64_t cp = sv.cp[k];
         const double* pK = A.gK ? A.gK : A.gM;
         const double* pM = A.gM ? A.gM : A.gK;
 #pragma unroll
@@ -850,7 +857,7 @@ __device__ __forceinline__ void store_vertex2(double* sh, int v, double dx, doub
 // and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
 template <int MODE>
-__device__ void bwd_ned3(const BwdArgs& A, int64_t e, double* sh) {
+__device__ void bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -942,7 +949,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e, double* sh) {
             // 72 gathers up front and hold them, at one wavefront per SIMD
             __builtin_amdgcn_sched_barrier(0);
             double gk[6], gm[6];
-            gather_row<6, MODE>(A, e, k, ue, gk, gm);
+            gather_row<6, MODE>(A, sv, k, ue, gk, gm);
             const int i = nib(NED3_START, k), j = nib(NED3_END, k);
 #pragma unroll
             for (int l = 0; l < 6; ++l) {
@@ -1023,7 +1030,7 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e, double* sh) {
 
 // 3D Raviart-Thomas
 template <int MODE>
-__device__ void bwd_rt3(const BwdArgs& A, int64_t e, double* sh) {
+__device__ void bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -1035,7 +1042,7 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e, double* sh) {
 double ue[4];
     load_u<4, MODE>(A, e, ue);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gather_row<4, MODE>(A, e, k, ue, GK[k], GM[k]);
+    for (int k = 0; k < 4; ++k) gather_row<4, MODE>(A, sv, k, ue, GK[k], GM[k]);
     const GeoRT3 g = geo_rt3(x);
     double s[4];
     rt3_signs(gid, s);
@@ -1096,7 +1103,7 @@ double ue[4];
 
 // 2D (both kinds)
 template <int MODE>
-__device__ void bwd_tri(const BwdArgs& A, int64_t e, double* sh) {
+__device__ void bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[3];
     V2 x[3];
 #pragma unroll
@@ -1108,7 +1115,7 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e, double* sh) {
 double ue[3];
     load_u<3, MODE>(A, e, ue);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gather_row<3, MODE>(A, e, k, ue, GK[k], GM[k]);
+    for (int k = 0; k < 3; ++k) gather_row<3, MODE>(A, sv, k, ue, GK[k], GM[k]);
     const Geo2 g = geo2(x);
     double s[3];
     tri_signs(gid, s);
@@ -1173,11 +1180,17 @@ double ue[3];
 
 template <int KC, int MODE>
 __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
-    constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM;
+    constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM, NLOC = KT<KC>::NLOC;
     constexpr int NINC = BWD_BLOCK * NV;
+    // 3D Nedelec with weights read through the slot map: the slot records are
+    // staged in LDS (24 KB; the workgroups per CU are bounded by registers
+    // anyway). For the other kinds the extra LDS would cost occupancy.
+    constexpr bool SLOTS = MODE != BWD_QUADRATIC && KC == 2;
     __shared__ double sh[NINC * DIM];
     __shared__ uint16_t s_inc[NINC];
     __shared__ uint16_t s_pst[NINC];
+    __shared__ int64_t s_base[SLOTS ? BWD_BLOCK * NLOC : 1];
+    __shared__ uint64_t s_cp[SLOTS ? BWD_BLOCK * NLOC : 1];
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the
     // upstream weights, and that reuse then stays in one L2.
@@ -1198,10 +1211,22 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
             reinterpret_cast<uint32_t*>(s_inc)[i] = w[i];
         for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) s_pst[j] = A.pst[pb0 + j];
     }
+    if constexpr (SLOTS) {
+        // the workgroup's slot records are contiguous (element-major): one
+        // coalesced pass into LDS instead of a dependent load per row
+        const int n_sl = n_inc / NV * NLOC;
+        for (int i = (int)threadIdx.x; i < n_sl; i += BWD_BLOCK) {
+            s_base[i] = A.slot_base[e0 * NLOC + i];
+            s_cp[i] = A.slot_cp[e0 * NLOC + i];
+        }
+        __syncthreads();
+    }
+    const SlotView sv = SLOTS ? SlotView{s_base + (int)threadIdx.x * NLOC, s_cp + (int)threadIdx.x * NLOC}
+                              : SlotView{A.slot_base + e * NLOC, A.slot_cp + e * NLOC};
     if (e < A.T) {
-        if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sh);
-        else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sh);
-        else bwd_tri<MODE>(A, e, sh);
+        if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sv, sh);
+        else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sv, sh);
+        else bwd_tri<MODE>(A, e, sv, sh);
     }
     if (!A.partials) return;  // uniform
     __syncthreads();
