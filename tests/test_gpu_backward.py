@@ -163,3 +163,54 @@ def test_adjoint_separate_and_missing_weights(case):
     gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, None, None)
     mesh.status()
     assert not bool(gn.abs().max() > 0) and not bool(ga.abs().max() > 0) and not bool(gb.abs().max() > 0)
+
+
+def multi_wg_case(case):
+    """Meshes larger than one 256-element adjoint workgroup, with a partial last
+    workgroup: Kuhn 5x4x3 (360 tets = 256 + 104), relabelled; a 12x11 square
+    with one interior triangle removed (263 triangles = 256 + 7, so the last
+    workgroup has an odd number of vertex incidences, 21)."""
+    rng = np.random.default_rng(41)
+    if case in ("ned3", "rt3"):
+        nodes, elems = relabel(*mg.kuhn_box(5, 4, 3), 9)
+        nodes = mg.perturb_interior(nodes, 0.2, 0.2, rng)
+    else:
+        nodes, elems = relabel(*mg.unit_square(12, 11), 9)
+        nodes = mg.perturb_interior(nodes, 1 / 12, 0.2, rng)
+        elems = np.delete(elems, elems.shape[0] // 2, axis=0)
+    kind = case[:-1]
+    a = rng.lognormal(0, 0.5, elems.shape[0])
+    b = rng.uniform(0.5, 2, elems.shape[0])
+    return nodes, elems, kind, a, b, rng
+
+
+@pytest.mark.parametrize("case", ["ned3", "rt3", "ned2"])
+def test_adjoint_several_workgroups(case):
+    import torch
+    import paper_1409_4618_amd as fem
+    nodes, elems, kind, a, b, rng = multi_wg_case(case)
+    say(f"[gpu] adjoint over several workgroups: {case} T={elems.shape[0]}")
+    csr, topo = oracle.assemble(nodes, elems, kind, a=a, b=b)
+    u = rng.normal(size=csr.n_rows)
+    w = quadratic_weights(csr, u)
+    pos = positions(csr, oracle.element_dofs(topo, kind))
+    ga_o, gb_o = grad_coefficients(nodes, elems, kind, topo, pos, w, w)
+    gn_o = grad_nodes(nodes, elems, kind, topo, pos, w, w, a, b)
+    tn, te, ta, tb = dev_tensors(nodes, elems, a, b)
+    mesh = fem.Mesh(tn, te)
+    rowptr, colind = mesh.pattern(kind)
+    tu = torch.tensor(u, device=tn.device)
+    tw = weights_on_device(rowptr, colind, tu)
+    gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, tw, tw)
+    qn, qa, qb = fem.assemble_backward_quadratic(mesh, kind, tn, ta, tb, tu)
+    mesh.status()
+    for got, ref, nm in ((ga, ga_o, "a"), (gb, gb_o, "b"), (gn, gn_o, "x"),
+                         (qa, ga_o, "a (quadratic)"), (qb, gb_o, "b (quadratic)"), (qn, gn_o, "x (quadratic)")):
+        got = got.cpu().numpy()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say(f"    dL/d{nm}: max rel err {err:.2e}")
+        assert err <= GTOL, (nm, err)
+    # deterministic: a second call is bitwise identical
+    gn2, ga2, gb2 = fem.assemble_backward(mesh, kind, tn, ta, tb, tw, tw)
+    mesh.status()
+    assert torch.equal(gn, gn2) and torch.equal(ga, ga2) and torch.equal(gb, gb2)
