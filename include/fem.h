@@ -142,11 +142,12 @@ fem_status fem_assemble_backward(fem_mesh mesh, fem_kind kind, const double* nod
 /* Adjoint of the quadratic form L = u^T (K(a) + M(b)) u (the energy of a dof
  * vector u): the outputs of fem_assemble_backward with
  * gK[p] = gM[p] = u_row(p) u_col(p), up to rounding, but formed per element
- * from u at its dofs instead of from nnz-sized arrays. For 3D Nedelec the
- * element's contractions are evaluated as sums of squares (|sum_k s_k u_k o_k|^2
- * for K, the squared Whitney field for M), so the results differ from the
- * general entry point by a few ulps of the element sums. Deterministic.
- * Not part of the paper. Asynchronous.
+ * from u at its dofs instead of from nnz-sized arrays. The element's
+ * contractions are evaluated as sums of squares (for 3D Nedelec
+ * |sum_k s_k u_k o_k|^2 for K and the squared Whitney field for M; for
+ * Raviart-Thomas and 2D the squared divergence and field likewise), so the
+ * results differ from the general entry point by a few ulps of the element
+ * sums. Deterministic. Not part of the paper. Asynchronous.
  *   u       dev f64 [n_rows of fem_pattern(kind)] (edge or face values)
  *   ga, gb, gnodes as in fem_assemble_backward (NULL to skip)
  * FEM_EINVAL if u is NULL.                                                  */

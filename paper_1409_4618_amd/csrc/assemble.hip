@@ -1038,11 +1038,8 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double*
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
-    double GK[4][4], GM[4][4];
-double ue[4];
+    double ue[4];
     load_u<4, MODE>(A, e, ue);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gather_row<4, MODE>(A, sv, k, ue, GK[k], GM[k]);
     const GeoRT3 g = geo_rt3(x);
     double s[4];
     rt3_signs(gid, s);
@@ -1052,22 +1049,44 @@ double ue[4];
     V3 z[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) z[p] = {0.0, 0.0, 0.0};
+    if constexpr (MODE == BWD_QUADRATIC) {
+        // Weights v_k v_l with v_k = s_k u_k (face k opposite vertex 3 - k): the
+        // sums below are squares, with Vs = sum_k v_k and Y = sum_k v_k y_(3-k):
+        //   hK = hM = Vs^2, rho_p = 2 v_(3-p) Vs, cross = |Y|^2, z_p = 2 v_(3-p) Y.
+        double v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int pk = 3 - k;
+        for (int k = 0; k < 4; ++k) v[k] = s[k] * ue[k];
+        const double Vs = (v[0] + v[1]) + (v[2] + v[3]);
+        const V3 Y = add(add(scale(g.y[3], v[0]), scale(g.y[2], v[1])), scale(g.y[1], v[2]));
+        hK = Vs * Vs;
+        hM = hK;
+        cross_term = dot(Y, Y);
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            const int pl = 3 - l;
-            const double ss = s[k] * s[l];
-            const double hk = GK[k][l] * ss;
-            const double hm = GM[k][l] * ss;
-            hK += hk;
-            hM += hm;
-            rho[pk] += hm;
-            rho[pl] += hm;
-            cross_term += hm * dot(g.y[pk], g.y[pl]);
-            z[pk] = add(z[pk], scale(g.y[pl], hm));
-            z[pl] = add(z[pl], scale(g.y[pk], hm));
+        for (int p = 1; p < 4; ++p) {
+            rho[p] = 2.0 * v[3 - p] * Vs;
+            z[p] = scale(Y, 2.0 * v[3 - p]);
+        }
+    } else {
+        double GK[4][4], GM[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gather_row<4, MODE>(A, sv, k, ue, GK[k], GM[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int pk = 3 - k;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int pl = 3 - l;
+                const double ss = s[k] * s[l];
+                const double hk = GK[k][l] * ss;
+                const double hm = GM[k][l] * ss;
+                hK += hk;
+                hM += hm;
+                rho[pk] += hm;
+                rho[pl] += hm;
+                cross_term += hm * dot(g.y[pk], g.y[pl]);
+                z[pk] = add(z[pk], scale(g.y[pl], hm));
+                z[pl] = add(z[pl], scale(g.y[pk], hm));
+            }
         }
     }
     double ru = 0.0;
@@ -1111,46 +1130,92 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double*
         gid[v] = A.elems[e * 3 + v];
         x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
     }
-    double GK[3][3], GM[3][3];
-double ue[3];
+    double ue[3];
     load_u<3, MODE>(A, e, ue);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gather_row<3, MODE>(A, sv, k, ue, GK[k], GM[k]);
     const Geo2 g = geo2(x);
     double s[3];
     tri_signs(gid, s);
     const double aJ = fabs(g.J);
     double hK = 0.0;
-    double Q[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Q[i][j] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int i = nib(TRI_START, k), j = nib(TRI_END, k);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int m = nib(TRI_START, l), n = nib(TRI_END, l);
-            const double ss = s[k] * s[l];
-            hK += GK[k][l] * ss;
-            const double gm = GM[k][l] * ss;
-            Q[j][n] += gm * (1.0 + (i == m));
-            Q[j][m] -= gm * (1.0 + (i == n));
-            Q[i][n] -= gm * (1.0 + (j == m));
-            Q[i][m] += gm * (1.0 + (j == n));
-        }
-    }
     double Psi = 0.0;
     V2 w[3];
+    if constexpr (MODE == BWD_QUADRATIC) {
+        // Weights v_k v_l with v_k = s_k u_k: hK = (sum_k v_k)^2, and with alpha
+        // the antisymmetric vertex matrix of v, sigma_b = sum_a alpha_ab,
+        // S = sum_b sigma_b c_b, R_a = sum_b alpha_ab c_b:
+        //   Psi = |S|^2 + sum_a |R_a|^2, dPsi/dc_b = 2 (sigma_b S + sum_a alpha_ab R_a).
+        double v[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        w[a] = {0.0, 0.0};
+        for (int k = 0; k < 3; ++k) v[k] = s[k] * ue[k];
+        const double Vs = (v[0] + v[1]) + v[2];
+        hK = Vs * Vs;
+        double al[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) al[a][bb] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            al[nib(TRI_START, k)][nib(TRI_END, k)] = v[k];
+            al[nib(TRI_END, k)][nib(TRI_START, k)] = -v[k];
+        }
+        double sig[3];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) sig[bb] = (al[0][bb] + al[1][bb]) + al[2][bb];
+        V2 S = {0.0, 0.0};
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) S = {S.x + sig[bb] * g.c[bb].x, S.y + sig[bb] * g.c[bb].y};
+        Psi = dot2(S, S);
+        V2 Ra[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Ra[a] = {0.0, 0.0};
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+                if (bb != a) Ra[a] = {Ra[a].x + al[a][bb] * g.c[bb].x, Ra[a].y + al[a][bb] * g.c[bb].y};
+            Psi += dot2(Ra[a], Ra[a]);
+        }
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) {
-            Psi += Q[a][bb] * dot2(g.c[a], g.c[bb]);
-            const double f = Q[a][bb] + Q[bb][a];
-            w[a] = {w[a].x + f * g.c[bb].x, w[a].y + f * g.c[bb].y};
+            V2 t = {sig[bb] * S.x, sig[bb] * S.y};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a != bb) t = {t.x + al[a][bb] * Ra[a].x, t.y + al[a][bb] * Ra[a].y};
+            w[bb] = {2.0 * t.x, 2.0 * t.y};
+        }
+    } else {
+        double GK[3][3], GM[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gather_row<3, MODE>(A, sv, k, ue, GK[k], GM[k]);
+        double Q[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Q[i][j] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int i = nib(TRI_START, k), j = nib(TRI_END, k);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int m = nib(TRI_START, l), n = nib(TRI_END, l);
+                const double ss = s[k] * s[l];
+                hK += GK[k][l] * ss;
+                const double gm = GM[k][l] * ss;
+                Q[j][n] += gm * (1.0 + (i == m));
+                Q[j][m] -= gm * (1.0 + (i == n));
+                Q[i][n] -= gm * (1.0 + (j == m));
+                Q[i][m] += gm * (1.0 + (j == n));
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[a] = {0.0, 0.0};
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                Psi += Q[a][bb] * dot2(g.c[a], g.c[bb]);
+                const double f = Q[a][bb] + Q[bb][a];
+                w[a] = {w[a].x + f * g.c[bb].x, w[a].y + f * g.c[bb].y};
+            }
         }
     }
     const double ca = A.a ? A.a[e] : 1.0;
