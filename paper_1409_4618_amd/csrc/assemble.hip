@@ -1,16 +1,19 @@
 // Numeric assembly of K(a), M(b) (forward), its adjoint (backward) and the
 // batched persistent launch.
 //
-// Forward ("row tiles"): the CSR rows are cut into tiles of R consecutive rows;
-// a tile owns the contiguous value range rowptr[r0] .. rowptr[r0+R]. One
-// workgroup of R threads takes a tile, one thread per row. The thread walks the
-// row's slots (element, local dof) in ascending element order, recomputes that
-// element's geometry in registers, forms row k of the element's K and M
-// (Section 2.4; closed forms in element.h) and adds it into the row's segment of
-// an LDS copy of the tile's values, at the byte offsets of the scatter map. The
-// sum over the elements sharing a matrix entry is therefore a segmented
-// reduction in a fixed order (deterministic, no atomics), and the tile is
-// written to HBM once with coalesced stores.
+// Both forward kernels cut the CSR rows into tiles of R consecutive rows; a
+// tile owns the contiguous value range rowptr[r0] .. rowptr[r0+R], accumulates
+// it in LDS and writes it to HBM once with coalesced stores.
+//   * Element-major tiles (k_forward_ema, the production path, further below):
+//     one lane per element that has a dof among the tile's rows.
+//   * Row tiles (k_forward, the fallback when a tile's element list does not
+//     fit a workgroup, and a batch tiling): R*G threads, G lanes per row. A lane
+//     walks its row's slots (element, local dof) in ascending element order,
+//     recomputes that element's geometry in registers, forms row k of the
+//     element's K and M (Section 2.4; closed forms in element.h) and adds it
+//     into the row's segment of the LDS copy, at the byte offsets of the
+//     scatter map: a segmented reduction in a fixed order (deterministic, no
+//     atomics).
 //
 // Workgroups are mapped to tiles XCD by XCD (workgroup b runs on XCD b mod 8),
 // so each XCD walks a contiguous range of rows and its L2 sees the reuse of
