@@ -43,7 +43,10 @@
  *     present even when its value is zero. K and M share the pattern. Values are
  *     bitwise symmetric and deterministic: an entry with more than two element
  *     contributions is summed in ascending element order, and one with two is
- *     the same either way round (x + y == y + x in IEEE arithmetic).
+ *     the same either way round (x + y == y + x in IEEE arithmetic). A mesh in
+ *     which some facet (3D face, 2D edge) has more than two elements, or which
+ *     repeats an element, is assembled by the row kernels, which sum every
+ *     entry in ascending element order.
  */
 #ifndef FEM_H
 #define FEM_H

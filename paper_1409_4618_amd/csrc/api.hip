@@ -198,7 +198,7 @@ fem_status fem_assemble(fem_mesh m, fem_kind kind, const double* nodes, const do
         const int nt = default_ema_threads();
         const Pattern::Ema& E = dofset(m, kind).pat.ema[ema_index(nt)];
         if (!E.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
-        if (E.usable) {
+        if (E.usable && !m->nonconforming) {
             MeshDev md;
             if (fem_status st = fill_meshdev(m, kind, nodes, a, b, K_vals, M_vals, 128, &md))
                 return st;
@@ -456,7 +456,7 @@ fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n
             delete B;
             return st;
         }
-        B->ema_ok = B->ema_ok && ds.pat.ema[ema_index(256)].usable;
+        B->ema_ok = B->ema_ok && ds.pat.ema[ema_index(256)].usable && !meshes[i]->nonconforming;
     }
     B->host_table.resize(n);
     hipError_t e = hipMalloc((void**)&B->table_dev, n * sizeof(MeshDev));

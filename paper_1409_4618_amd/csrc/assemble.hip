@@ -500,6 +500,12 @@ __device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T&
     }
 }
 
+// Local edges k and l of a tetrahedron share no vertex (3D Nedelec numbering).
+__host__ __device__ constexpr bool ned3_opposite(int k, int l) {
+    return nib(NED3_START, k) != nib(NED3_START, l) && nib(NED3_START, k) != nib(NED3_END, l) &&
+           nib(NED3_END, k) != nib(NED3_START, l) && nib(NED3_END, k) != nib(NED3_END, l);
+}
+
 // One pass (K or M) of a lane's element: rows k that belong to the tile
 // (bit k of mask). The slot record cp[k] gives the row's column offsets, its
 // tile-local row (LDS base of the row's values) and, for the 3D Nedelec
@@ -526,9 +532,17 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, u
             }
             static_for<0, NLOC>([&](auto ll) {
                 constexpr int l = decltype(ll)::value;
-                if constexpr (l != k)
-                    atomicAdd(&out[base + (int)((c >> (8 * l)) & 0xFFu)],
-                              ema_entry<KC, MASS, k, l>(sk, r));
+                if constexpr (l != k) {
+                    double* o = &out[base + (int)((c >> (8 * l)) & 0xFFu)];
+                    const double v = ema_entry<KC, MASS, k, l>(sk, r);
+                    // 3D Nedelec, opposite edges k and l: they span all four
+                    // vertices, so in a conforming mesh (the only kind these
+                    // tiles are used for) their entry has this element as its
+                    // only contribution, and a store onto the zeroed copy
+                    // equals the atomic add bitwise.
+                    if constexpr (KC == 2 && ned3_opposite(k, l)) *o = v;
+                    else atomicAdd(o, v);
+                }
             });
         }
     });

@@ -118,6 +118,11 @@ struct fem_mesh_s {
     uint16_t* bwd_inc = nullptr;     // [T*(dim+1)+1] workgroup-local incidences, by workgroup, node, element
     int64_t bwd_pairs = 0;
     int* err_word = nullptr;         // device error word
+    // Some facet (3D face, 2D edge) has more than two elements, or two elements
+    // with the same vertices. Such meshes take the row kernels, which sum every
+    // entry in element order; the element-major tiles assume at most two
+    // contributions per atomically summed entry.
+    bool nonconforming = false;
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;       // everything to free
 };

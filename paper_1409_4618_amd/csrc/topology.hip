@@ -200,6 +200,46 @@ __global__ void k_face_signs(const int32_t* elems, int64_t T, int8_t* signs) {
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+// Conformity, for the element-major assembly (whose entries with one or two
+// contributions are summed without a fixed order): a facet (3D face, 2D edge)
+// with more than two elements, or with two elements whose vertices opposite it
+// coincide (a duplicated element), makes the mesh non-conforming.
+// 3D: face slot s = element * 4 + k, face k opposite local vertex 3 - k.
+__global__ void k_face_conformity(const int32_t* rs_ptr, const int32_t* rs_slot, const int32_t* elems,
+                                  int64_t F, int* flag) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t j0 = rs_ptr[f];
+    const int32_t n = rs_ptr[f + 1] - j0;
+    if (n > 2) {
+        atomicOr(flag, 1);
+    } else if (n == 2) {
+        const int64_t s1 = rs_slot[j0], s2 = rs_slot[j0 + 1];
+        const int32_t o1 = elems[(s1 / 4) * 4 + 3 - s1 % 4];
+        const int32_t o2 = elems[(s2 / 4) * 4 + 3 - s2 % 4];
+        if (o1 == o2) atomicOr(flag, 1);
+    }
+}
+
+// 2D: edge slot s = element * 3 + k, edge k = (start, end) opposite the third
+// local vertex 3 - start - end.
+__global__ void k_edge_conformity_2d(const int32_t* rs_ptr, const int32_t* rs_slot, const int32_t* elems,
+                                     int64_t E, int* flag) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= E) return;
+    const int32_t j0 = rs_ptr[q];
+    const int32_t n = rs_ptr[q + 1] - j0;
+    if (n > 2) {
+        atomicOr(flag, 1);
+    } else if (n == 2) {
+        const int64_t s1 = rs_slot[j0], s2 = rs_slot[j0 + 1];
+        const int k1 = (int)(s1 % 3), k2 = (int)(s2 % 3);
+        const int32_t o1 = elems[(s1 / 3) * 3 + 3 - nib(TRI_START, k1) - nib(TRI_END, k1)];
+        const int32_t o2 = elems[(s2 / 3) * 3 + 3 - nib(TRI_START, k2) - nib(TRI_END, k2)];
+        if (o1 == o2) atomicOr(flag, 1);
+    }
+}
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
 // ---------------------------------------------------------------- helpers
@@ -312,6 +352,18 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems_
     else
         hipLaunchKernelGGL(k_edge_signs<2>, dim3(nblk(ns)), dim3(TB), 0, s, m->elems, T, m->signs_e);
     FEM_HIP(hipGetLastError());
+    if (dim == 2) {
+        int* flag = reinterpret_cast<int*>(tb.scan);   // free again after the edge numbering
+        FEM_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+        if (E > 0)
+            hipLaunchKernelGGL(k_edge_conformity_2d, dim3(nblk(E)), dim3(TB), 0, s, ed.rs_ptr, ed.rs_slot, m->elems,
+                               E, flag);
+        FEM_HIP(hipGetLastError());
+        int h = 0;
+        FEM_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FEM_HIP(hipStreamSynchronize(s));
+        m->nonconforming = h != 0;
+    }
 
     // 4. faces (3D)
     if (dim == 3) {
@@ -341,6 +393,16 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems_
         FEM_HIP(dmalloc(m, &m->signs_f, nf));
         hipLaunchKernelGGL(k_face_signs, dim3(nblk(T)), dim3(TB), 0, s, m->elems, T, m->signs_f);
         FEM_HIP(hipGetLastError());
+        int* flag = reinterpret_cast<int*>(tb.scan);   // the scan space is free again
+        FEM_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+        if (F > 0)
+            hipLaunchKernelGGL(k_face_conformity, dim3(nblk(F)), dim3(TB), 0, s, fd.rs_ptr, fd.rs_slot, m->elems, F,
+                               flag);
+        FEM_HIP(hipGetLastError());
+        int h = 0;
+        FEM_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FEM_HIP(hipStreamSynchronize(s));
+        m->nonconforming = h != 0;
     }
     FEM_HIP(hipStreamSynchronize(s));
     return FEM_OK;

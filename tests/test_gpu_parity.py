@@ -203,3 +203,59 @@ def test_row_longer_than_255_is_rejected():
     with pytest.raises(FemError) as ei:
         mesh.pattern("ned")
     assert ei.value.status == 5
+
+
+def nonconforming_cases():
+    """Meshes outside the element-major tiles' assumption (at most two elements
+    per facet, no duplicated element): a Kuhn 2^3 box with one tetrahedron
+    duplicated (its opposite-edge entries then have two contributions), a 3x3
+    square with one triangle duplicated, and three triangles on one edge."""
+    n3, e3 = mg.kuhn_box(2)
+    n2, e2 = mg.unit_square(3, 3)
+    nb = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [0.5, -1.0], [1.2, 1.1]])
+    eb = np.array([[0, 1, 2], [0, 1, 3], [1, 0, 4]], np.int32)
+    return [("kuhn 2^3 + duplicated tet", n3, np.concatenate([e3, e3[5:6]]).astype(np.int32), "ned"),
+            ("kuhn 2^3 + duplicated tet", n3, np.concatenate([e3, e3[5:6]]).astype(np.int32), "rt"),
+            ("square 3x3 + duplicated triangle", n2, np.concatenate([e2, e2[4:5]]).astype(np.int32), "ned"),
+            ("three triangles on one edge", nb, eb, "rt")]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_nonconforming_meshes_take_the_row_kernel(idx):
+    name, nodes, elems, kind = nonconforming_cases()[idx]
+    rng = np.random.default_rng(61 + idx)
+    a = rng.uniform(0.5, 2.0, elems.shape[0])
+    b = rng.uniform(0.5, 2.0, elems.shape[0])
+    g = run_case(name, nodes, elems, kind, a, b)
+    check_against_oracle(g, nodes, elems, kind, a, b)
+
+
+def test_batch_with_a_nonconforming_mesh():
+    """Element-major tiling is refused for a batch holding a non-conforming
+    mesh; the row tiling gives the single launches' values."""
+    import torch
+    import paper_1409_4618_amd as fem
+    from paper_1409_4618_amd import FemError
+    name, nodes, elems, kind = nonconforming_cases()[0]
+    ok_nodes, ok_elems = mg.kuhn_box(3)
+    meshes, kinds, tn_l, K_l, M_l, ref = [], [], [], [], [], []
+    for nd, el in ((nodes, elems), (ok_nodes, ok_elems)):
+        tn, te, _, _ = dev_tensors(nd, el)
+        m = fem.Mesh(tn, te)
+        K, M = fem.assemble(m, kind, tn)
+        ref.append((K.clone(), M.clone()))
+        meshes.append(m)
+        kinds.append(kind)
+        tn_l.append(tn)
+        K_l.append(torch.zeros_like(K))
+        M_l.append(torch.zeros_like(M))
+    B = fem.Batch(meshes, kinds)
+    B.bind(tn_l, [None, None], [None, None], K_l, M_l)
+    with pytest.raises(FemError):
+        B.set_config(0, 0)
+    B.set_config(128, 0)
+    B.assemble()
+    for m in meshes:
+        m.status()
+    for (K, M), K2, M2 in zip(ref, K_l, M_l):
+        assert torch.equal(K, K2) and torch.equal(M, M2)
