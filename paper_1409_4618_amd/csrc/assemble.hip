@@ -535,12 +535,14 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, u
                 if constexpr (l != k) {
                     double* o = &out[base + (int)((c >> (8 * l)) & 0xFFu)];
                     const double v = ema_entry<KC, MASS, k, l>(sk, r);
-                    // 3D Nedelec, opposite edges k and l: they span all four
-                    // vertices, so in a conforming mesh (the only kind these
-                    // tiles are used for) their entry has this element as its
-                    // only contribution, and a store onto the zeroed copy
-                    // equals the atomic add bitwise.
-                    if constexpr (KC == 2 && ned3_opposite(k, l)) *o = v;
+                    // Entries whose two dofs determine the element (3D
+                    // Nedelec opposite edges span all four vertices; two faces
+                    // of a tetrahedron or two edges of a triangle span all its
+                    // vertices) have this element as their only contribution
+                    // in a conforming mesh, the only kind these tiles are used
+                    // for: a store onto the zeroed copy equals the atomic add
+                    // bitwise.
+                    if constexpr (KC != 2 || ned3_opposite(k, l)) *o = v;
                     else atomicAdd(o, v);
                 }
             });
