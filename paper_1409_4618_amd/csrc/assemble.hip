@@ -784,7 +784,7 @@ struct BwdArgs {
     const double* b;
     const double* gK;
     const double* gM;
-    const int64_t* slot_base;  // [T*nloc] row start of each slot's dof
+    const int32_t* slot_base;  // [T*nloc] row start of each slot's dof
     const uint64_t* slot_cp;   // [T*nloc] column offsets of each slot's row
     const double* u;           // quadratic form: [n_dofs] vector, weights u_I u_J
     const int32_t* elems2dofs; // quadratic form: [T*nloc] global dof of each slot
@@ -814,7 +814,7 @@ enum BwdMode { BWD_SEPARATE = 0, BWD_SAME = 1, BWD_QUADRATIC = 2 };
 // This lane's slot records (row start, column offsets): staged in LDS by the
 // workgroup at kernel start (3D Nedelec), or read in place.
 struct SlotView {
-    const int64_t* base;
+    const int32_t* base;
     const uint64_t* cp;
 };
 
@@ -1273,7 +1273,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     __shared__ double sh[NINC * DIM];
     __shared__ uint16_t s_inc[NINC];
     __shared__ uint16_t s_pst[NINC];
-    __shared__ int64_t s_base[SLOTS ? BWD_BLOCK * NLOC : 1];
+    __shared__ int32_t s_base[SLOTS ? BWD_BLOCK * NLOC : 1];
     __shared__ uint64_t s_cp[SLOTS ? BWD_BLOCK * NLOC : 1];
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
     // a contiguous range of elements; neighbouring elements share rows of the

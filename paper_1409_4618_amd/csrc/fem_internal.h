@@ -90,7 +90,7 @@ struct DofSet {
     Pattern pat;
     // adjoint gather map, element-major: for slot e*nloc + k, the CSR position
     // of its row's first entry and its column-offset record (built on first use)
-    int64_t* slot_base = nullptr;  // [T*nloc]
+    int32_t* slot_base = nullptr;  // [T*nloc] (< 2^31: nnz < 2^31 is checked when the pattern is built)
     uint64_t* slot_cp = nullptr;   // [T*nloc]
 };
 

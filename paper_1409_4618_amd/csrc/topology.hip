@@ -567,11 +567,11 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
 // slot's dof and the slot's column-offset record, so the adjoint reaches the
 // n_local^2 positions of an element with one level of indirection.
 __global__ void k_slot_map(const int32_t* elems2dofs, const int64_t* rowptr, const int32_t* slot_rank,
-                           const uint8_t* colpos, int cp_stride, int64_t n, int64_t* base,
+                           const uint8_t* colpos, int cp_stride, int64_t n, int32_t* base,
                            uint64_t* cp) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    base[s] = rowptr[elems2dofs[s]];
+    base[s] = (int32_t)rowptr[elems2dofs[s]];
     const int64_t j = slot_rank[s];
     cp[s] = cp_stride == 8 ? reinterpret_cast<const uint64_t*>(colpos)[j]
                            : (uint64_t)reinterpret_cast<const uint32_t*>(colpos)[j];
