@@ -407,6 +407,8 @@ int batch_blocks_per_cu(int R, int bytes) {
 // matrices keeps the register count low: both set how many workgroups share a
 // compute unit, which is what hides the gather latency.
 // ===========================================================================
+// LDS of a tile: values (and 3D Nedelec diagonal slots), row bases, row slot
+// starts (R + 1), row diagonal offsets.
 int ema_lds_bytes(int kc, int R, int pmax, int max_slots) {
     const int sd = kc == 2 ? max_slots : 0;
     return 8 * (pmax + sd) + 4 * (3 * R + 1) + 16;
@@ -557,8 +559,9 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     const int tid = threadIdx.x;
     const int R = md.ema_R;
     // header of the tile
-    const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile];
-    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[2 * tile + 1];
+    const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile];
+    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 1];
+    const int4 h2 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 2];  // record bases of wavefronts 1-3
     const int64_t r0 = tile * R;
     const int nslots = h0.x;
     const int nrows = h0.y;
@@ -573,10 +576,12 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     int* rowslot = rowbase + R;
     int* rowdiag = rowslot + R + 1;
 
-    // this lane's element: entry, node ids and slot records first, so their
-    // latency overlaps the LDS set-up below. A tile's entries sit at a fixed
-    // stride, so they load together with the header.
-    const int2 en = md.ema_ent[tile * NT + tid];
+    // this lane's element: entry and node ids first, so their latency
+    // overlaps the LDS set-up below. A tile's entries sit at a fixed stride,
+    // so they load together with the header. The entry's in-tile dofs (mask)
+    // ride in spare bits of the node ids; its records start at the sum of the
+    // preceding entries' dof counts (padding entries have none).
+    const int en = md.ema_ent[tile * NT + tid];
     const int4 q = md.ema_gid[tile * NT + tid];  // the element's node ids, streamed with the entry
     const bool have = tid < ne;
     int64_t e = 0;
@@ -587,17 +592,33 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     for (int v = 0; v < NV; ++v) gid[v] = 0;
 #pragma unroll
     for (int k = 0; k < NLOC; ++k) cp[k] = 0;
+    if constexpr (NV == 4) {
+        mask = (((uint32_t)q.x >> 30) & 3u) | ((((uint32_t)q.y >> 30) & 3u) << 2) |
+               ((((uint32_t)q.z >> 30) & 3u) << 4);
+    } else {
+        mask = (uint32_t)q.w;
+    }
     if (have) {
-        e = en.x;
-        mask = (uint32_t)en.y & 0x3Fu;
-        const int64_t roff = (int64_t)js0 + ((uint32_t)en.y >> 8);
+        e = en;
+        gid[0] = q.x & 0x3FFFFFFF;
+        gid[1] = q.y & 0x3FFFFFFF;
+        gid[2] = q.z & 0x3FFFFFFF;
+        if constexpr (NV == 4) gid[3] = q.w;
+    }
+    // record offset: the wavefront's base (tile header) plus the exclusive
+    // prefix of the dof counts within the wavefront (three ballots over the
+    // bits of a count <= 6)
+    const uint32_t cnt = __popc(mask);
+    const uint64_t below = __lanemask_lt();
+    const uint64_t b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
+    const int in_wave = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
+    const int wave = tid / 64;
+    const int wbase = wave == 0 ? 0 : wave == 1 ? h2.x : wave == 2 ? h2.y : h2.z;
+    if (have) {
+        const int64_t roff = (int64_t)js0 + wbase + in_wave;
 #pragma unroll
         for (int k = 0; k < NLOC; ++k)
             if ((mask >> k) & 1u) cp[k] = md.ema_rec[roff + __popc(mask & ((1u << k) - 1u))];
-        gid[0] = q.x;
-        gid[1] = q.y;
-        gid[2] = q.z;
-        if constexpr (NV == 4) gid[3] = q.w;
     }
     // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;

@@ -60,17 +60,20 @@ struct Pattern {
         int32_t* eptr = nullptr;    // [n_tiles+1]
         int32_t* elems = nullptr;   // [n_entries] (build only)
         uint16_t* joff = nullptr;   // [n_entries][8] (build only)
-        // entry i of tile t, at t * NT + i: (element, in-tile local dofs (6
-        // bits) | offset of its first record in the tile << 8)
-        int2* ent = nullptr;        // [n_tiles * NT]
-        int32_t* egid = nullptr;    // [n_tiles * NT][4] node ids of the entry's element (zero-padded in 2D)
+        // entry i of tile t, at t * NT + i: the element, and its node ids with
+        // the entry's in-tile local dofs (6 bits) in spare bits: 3D, bits 30-31
+        // of the first three ids (2 bits each); 2D, the fourth word. Records
+        // of an entry start at the sum of the preceding entries' dof counts.
+        int32_t* ent = nullptr;     // [n_tiles * NT]
+        int32_t* egid = nullptr;    // [n_tiles * NT][4]
         // record of an in-tile slot, grouped by entry, ascending local dof:
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)
         uint64_t* rec = nullptr;    // [n_slots]
-        // per-tile header, 8 ints: slots, rows, p0 (lo, hi), values, first
-        // slot, first entry, entries (the first row is tile * R)
-        int32_t* hdr = nullptr;     // [n_tiles][8]
+        // per-tile header, 12 ints: slots, rows, p0 (lo, hi), values, first
+        // slot, first entry, entries, the record bases of wavefronts 1-3, 0
+        // (the first row is tile * R)
+        int32_t* hdr = nullptr;     // [n_tiles][12]
         // per row: its value offset in its tile (bits 0..15) and its first
         // slot in the tile's slot list (16..31)
         uint32_t* rtab = nullptr;   // [n_rows]
@@ -184,7 +187,7 @@ struct MeshDev {
     int* err_word;
     // element-major tiles: headers, entries, slot records
     const int32_t* ema_hdr;
-    const int2* ema_ent;
+    const int32_t* ema_ent;
     const int4* ema_gid;
     const uint64_t* ema_rec;
     const uint32_t* ema_rtab;

@@ -909,8 +909,8 @@ __global__ void k_slot_rows(const int32_t* rs_ptr, int64_t n_rows, int32_t* slot
 __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_t* elems,
                               const uint16_t* joff, const int32_t* rs_ptr, const int32_t* slot_row,
                               const uint8_t* colpos, int cp_stride, int nloc, int R,
-                              const int32_t* elem_nodes, int nv, int stride, int2* ent, int4* egid,
-                              uint64_t* rec, int* overflow) {
+                              const int32_t* elem_nodes, int nv, int stride, int32_t* ent, int4* egid,
+                              uint64_t* rec, int32_t* hdr, int* overflow) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const int32_t js0 = rs_ptr[t * R];
@@ -931,12 +931,19 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
             mask |= 1u << k;
             ++cnt;
         }
-        if (off > 0xFFFFFFu) atomicOr(overflow, 1);
         const int64_t e = elems[i];
-        const int64_t pi = t * stride + (i - eptr[t]);  // fixed stride per tile
-        ent[pi] = make_int2((int)e, (int)(mask | (off << 8)));
+        const int64_t li = i - eptr[t];
+        const int64_t pi = t * stride + li;  // fixed stride per tile
+        // record base of wavefronts 1-3 (header words 8-10)
+        if (li > 0 && li % 64 == 0 && li / 64 <= 3) hdr[t * 12 + 7 + li / 64] = (int32_t)off;
+        ent[pi] = (int32_t)e;
         const int32_t* q = elem_nodes + e * nv;
-        egid[pi] = make_int4(q[0], q[1], q[2], nv == 4 ? q[3] : 0);
+        // the dof mask in spare bits of the node ids (3D: ids < 2^30, checked
+        // when the tiles are built)
+        egid[pi] = nv == 4 ? make_int4((int)((uint32_t)q[0] | ((mask & 3u) << 30)),
+                                       (int)((uint32_t)q[1] | (((mask >> 2) & 3u) << 30)),
+                                       (int)((uint32_t)q[2] | (((mask >> 4) & 3u) << 30)), q[3])
+                           : make_int4(q[0], q[1], q[2], (int)mask);
         off += cnt;
     }
 }
@@ -950,7 +957,7 @@ __global__ void k_tile_headers(int64_t n_tiles, int R, int64_t n_rows, const int
     const int64_t r0 = t * R;
     const int64_t r1 = (r0 + R < n_rows) ? r0 + R : n_rows;
     const int64_t p0 = rowptr[r0];
-    int32_t* h = hdr + t * 8;
+    int32_t* h = hdr + t * 12;
     h[0] = rs_ptr[r1] - rs_ptr[r0];
     h[1] = (int32_t)(r1 - r0);
     h[2] = (int32_t)(uint32_t)(uint64_t)p0;
@@ -975,10 +982,11 @@ __global__ void k_tile_rows(int64_t n_rows, int R, const int64_t* rowptr, const 
     rtab[r] = (uint32_t)(pv & 0xFFFF) | ((uint32_t)(ps & 0xFFFF) << 16);
 }
 
+// Header words 0-7 here; words 8-10 (the wavefronts' record bases) come from
+// the record kernel, which runs first on the same stream.
 static fem_status ema_headers(DofSet& ds, Pattern::Ema& E, int* overflow, hipStream_t s) {
     if (ds.pat.n_rows >= (int64_t(1) << 31))
         return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 rows");
-    FEM_HIP(hipMalloc((void**)&E.hdr, (size_t)std::max<int64_t>(E.n_tiles, 1) * 8 * sizeof(int32_t)));
     FEM_HIP(hipMalloc((void**)&E.rtab, (size_t)std::max<int64_t>(ds.pat.n_rows, 1) * sizeof(uint32_t)));
     if (E.n_tiles == 0) return FEM_OK;
     hipLaunchKernelGGL(k_tile_headers, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.n_tiles, E.R,
@@ -999,9 +1007,11 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, int nt, h
     const int64_t n_pad = std::max<int64_t>(E.n_tiles * stride, 1);
     if (E.n_tiles * stride >= (int64_t(1) << 31))
         return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 tile entries");
-    FEM_HIP(hipMalloc((void**)&E.ent, (size_t)n_pad * sizeof(int2)));
+    FEM_HIP(hipMalloc((void**)&E.ent, (size_t)n_pad * sizeof(int32_t)));
     FEM_HIP(hipMalloc((void**)&E.egid, (size_t)n_pad * sizeof(int4)));
-    FEM_HIP(hipMemsetAsync(E.ent, 0, (size_t)n_pad * sizeof(int2), s));
+    FEM_HIP(hipMemsetAsync(E.ent, 0, (size_t)n_pad * sizeof(int32_t), s));
+    FEM_HIP(hipMalloc((void**)&E.hdr, (size_t)std::max<int64_t>(E.n_tiles, 1) * 12 * sizeof(int32_t)));
+    FEM_HIP(hipMemsetAsync(E.hdr, 0, (size_t)std::max<int64_t>(E.n_tiles, 1) * 12 * sizeof(int32_t), s));
     FEM_HIP(hipMemsetAsync(E.egid, 0, (size_t)n_pad * sizeof(int4), s));
     FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * sizeof(uint64_t)));
     TmpBufs tb;
@@ -1013,7 +1023,8 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, int nt, h
                        slot_row);
     hipLaunchKernelGGL(k_ema_records, dim3(nblk(E.n_tiles)), dim3(TB), 0, s, E.eptr, E.n_tiles, E.elems,
                        E.joff, ds.rs_ptr, slot_row, ds.pat.colpos, ds.pat.cp_stride, ds.nloc, E.R,
-                       m->elems, m->dim + 1, stride, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, overflow);
+                       m->elems, m->dim + 1, stride, E.ent, reinterpret_cast<int4*>(E.egid), E.rec, E.hdr,
+                       overflow);
     FEM_HIP(hipGetLastError());
     if (fem_status st = ema_headers(ds, E, overflow, s)) return st;
     int h = 0;
@@ -1066,7 +1077,8 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
             m->allocs.push_back(cand.rtab);
             cand.NT = nt;
             cand.built = true;
-            cand.usable = cand.max_elems <= nt;
+            // 3D tiles carry the dof mask in bits 30-31 of the node ids
+            cand.usable = cand.max_elems <= nt && (m->dim == 2 || m->V <= (int64_t(1) << 30));
             E = cand;
             return FEM_OK;
         }
