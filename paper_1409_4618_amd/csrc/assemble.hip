@@ -502,6 +502,19 @@ __device__ __forceinline__ double ema_entry(const typename EmaPass<KC, MASS>::T&
     }
 }
 
+// Slot record fields. 3D Nedelec (u64): column offsets 8 bits each (bits
+// 0-47), tile-local row (48-55), rank in the row's slot list (56-63). Raviart-
+// Thomas and 2D (u32; rows of a conforming mesh have at most 7 entries):
+// column offsets 6 bits each (0-23), tile-local row (24-31).
+template <int KC>
+__device__ __forceinline__ int rec_row(uint64_t c) {
+    return KC == 2 ? (int)((c >> 48) & 0xFFu) : (int)((c >> 24) & 0xFFu);
+}
+template <int KC>
+__device__ __forceinline__ int rec_col(uint64_t c, int l) {
+    return KC == 2 ? (int)((c >> (8 * l)) & 0xFFu) : (int)((c >> (6 * l)) & 0x3Fu);
+}
+
 // Local edges k and l of a tetrahedron share no vertex (3D Nedelec numbering).
 __host__ __device__ constexpr bool ned3_opposite(int k, int l) {
     return nib(NED3_START, k) != nib(NED3_START, l) && nib(NED3_START, k) != nib(NED3_END, l) &&
@@ -523,19 +536,19 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, u
             pin_state<MASS>(st);
             const typename EmaPass<KC, MASS>::T& sk = st;
             const uint64_t c = cp[k];
-            const int lr = (int)((c >> 48) & 0xFFu);
+            const int lr = rec_row<KC>(c);
             const int base = rowbase[lr];
             const double r = ema_row<KC, MASS, k>(sk);
             const double d = ema_entry<KC, MASS, k, k>(sk, r);
             if constexpr (KC == 2) {
                 sdiag[rowslot[lr] + (int)(c >> 56)] = d;
             } else {
-                atomicAdd(&out[base + (int)((c >> (8 * k)) & 0xFFu)], d);
+                atomicAdd(&out[base + rec_col<KC>(c, k)], d);
             }
             static_for<0, NLOC>([&](auto ll) {
                 constexpr int l = decltype(ll)::value;
                 if constexpr (l != k) {
-                    double* o = &out[base + (int)((c >> (8 * l)) & 0xFFu)];
+                    double* o = &out[base + rec_col<KC>(c, l)];
                     const double v = ema_entry<KC, MASS, k, l>(sk, r);
                     // Entries whose two dofs determine the element (3D
                     // Nedelec opposite edges span all four vertices; two faces
@@ -618,7 +631,11 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         const int64_t roff = (int64_t)js0 + wbase + in_wave;
 #pragma unroll
         for (int k = 0; k < NLOC; ++k)
-            if ((mask >> k) & 1u) cp[k] = md.ema_rec[roff + __popc(mask & ((1u << k) - 1u))];
+            if ((mask >> k) & 1u) {
+                const int64_t j = roff + __popc(mask & ((1u << k) - 1u));
+                if constexpr (KC == 2) cp[k] = reinterpret_cast<const uint64_t*>(md.ema_rec)[j];
+                else cp[k] = reinterpret_cast<const uint32_t*>(md.ema_rec)[j];
+            }
     }
     // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;

@@ -69,7 +69,7 @@ struct Pattern {
         // record of an in-tile slot, grouped by entry, ascending local dof:
         // column offsets (bits 0..47), tile-local row (48..55), rank of the
         // slot in its row's slot list (56..63)
-        uint64_t* rec = nullptr;    // [n_slots]
+        void* rec = nullptr;        // [n_slots] u64 (3D Nedelec) or u32 (the other kinds)
         // per-tile header, 12 ints: slots, rows, p0 (lo, hi), values, first
         // slot, first entry, entries, the record bases of wavefronts 1-3, 0
         // (the first row is tile * R)
@@ -189,7 +189,7 @@ struct MeshDev {
     const int32_t* ema_hdr;
     const int32_t* ema_ent;
     const int4* ema_gid;
-    const uint64_t* ema_rec;
+    const void* ema_rec;        // u64 records (3D Nedelec) or u32 (the other kinds)
     const uint32_t* ema_rtab;
     int32_t ema_R;
     int32_t ema_pmax;

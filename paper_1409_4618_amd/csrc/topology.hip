@@ -910,7 +910,7 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
                               const uint16_t* joff, const int32_t* rs_ptr, const int32_t* slot_row,
                               const uint8_t* colpos, int cp_stride, int nloc, int R,
                               const int32_t* elem_nodes, int nv, int stride, int32_t* ent, int4* egid,
-                              uint64_t* rec, int32_t* hdr, int* overflow) {
+                              void* rec, int32_t* hdr, int* overflow) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const int32_t js0 = rs_ptr[t * R];
@@ -927,7 +927,18 @@ __global__ void k_ema_records(const int32_t* eptr, int64_t n_tiles, const int32_
             if (lr > 255u || rank > 255u) atomicOr(overflow, 1);
             const uint64_t cp = cp_stride == 8 ? reinterpret_cast<const uint64_t*>(colpos)[j]
                                                : (uint64_t)reinterpret_cast<const uint32_t*>(colpos)[j];
-            rec[js0 + off + cnt] = (cp & 0xFFFFFFFFFFFFull) | (lr << 48) | (rank << 56);
+            if (nloc == 6) {
+                reinterpret_cast<uint64_t*>(rec)[js0 + off + cnt] = (cp & 0xFFFFFFFFFFFFull) | (lr << 48) | (rank << 56);
+            } else {
+                // four 6-bit column offsets and the 8-bit tile-local row
+                uint32_t r32 = (uint32_t)lr << 24;
+                for (int l = 0; l < nloc; ++l) {
+                    const uint32_t o = (uint32_t)(cp >> (8 * l)) & 0xFFu;
+                    if (o > 63u) atomicOr(overflow, 1);
+                    r32 |= (o & 63u) << (6 * l);
+                }
+                reinterpret_cast<uint32_t*>(rec)[js0 + off + cnt] = r32;
+            }
             mask |= 1u << k;
             ++cnt;
         }
@@ -1013,7 +1024,7 @@ static fem_status ema_records(fem_mesh m, DofSet& ds, Pattern::Ema& E, int nt, h
     FEM_HIP(hipMalloc((void**)&E.hdr, (size_t)std::max<int64_t>(E.n_tiles, 1) * 12 * sizeof(int32_t)));
     FEM_HIP(hipMemsetAsync(E.hdr, 0, (size_t)std::max<int64_t>(E.n_tiles, 1) * 12 * sizeof(int32_t), s));
     FEM_HIP(hipMemsetAsync(E.egid, 0, (size_t)n_pad * sizeof(int4), s));
-    FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * sizeof(uint64_t)));
+    FEM_HIP(hipMalloc((void**)&E.rec, (size_t)std::max<int64_t>(n_slots, 1) * (ds.nloc == 6 ? 8 : 4)));
     TmpBufs tb;
     FEM_HIP(tb.alloc(std::max<int64_t>(n_slots, 1)));
     int32_t* slot_row = reinterpret_cast<int32_t*>(tb.vals);
@@ -1046,6 +1057,15 @@ fem_status build_ema(fem_mesh m, DofSet& ds, int nt, hipStream_t s) {
     Pattern::Ema& E = ds.pat.ema[ema_index(nt)];
     if (E.built) return FEM_OK;
     const int kc = ds.nloc == 6 ? 2 : (ds.nloc == 4 ? 1 : 0);
+    // Raviart-Thomas and 2D records hold 6-bit column offsets: rows of a
+    // conforming mesh have at most 7 entries. A mesh with a longer row is not
+    // conforming and is assembled by the row kernels anyway.
+    if (kc != 2 && ds.pat.max_row_len > 64) {
+        E.NT = nt;
+        E.built = true;
+        E.usable = false;
+        return FEM_OK;
+    }
     // elements per row: about 2 (3D Nedelec), 0.9 (3D RT), 0.7 (2D)
     int R = kc == 2 ? nt / 2 : nt;
     if (R > 255) R = 255;

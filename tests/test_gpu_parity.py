@@ -214,13 +214,19 @@ def nonconforming_cases():
     n2, e2 = mg.unit_square(3, 3)
     nb = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [0.5, -1.0], [1.2, 1.1]])
     eb = np.array([[0, 1, 2], [0, 1, 3], [1, 0, 4]], np.int32)
+    # forty triangles on one edge: its row has 1 + 2 * 40 = 81 entries, beyond
+    # the 6-bit column offsets of the element-major records
+    nf = np.concatenate([[[0.0, 0.0], [1.0, 0.0]],
+                         [[0.5 + 0.4 * np.cos(t), 0.3 + 0.9 * np.sin(t)] for t in np.linspace(0.2, 6.0, 40)]])
+    ef = np.array([[0, 1, 2 + i] for i in range(40)], np.int32)
     return [("kuhn 2^3 + duplicated tet", n3, np.concatenate([e3, e3[5:6]]).astype(np.int32), "ned"),
             ("kuhn 2^3 + duplicated tet", n3, np.concatenate([e3, e3[5:6]]).astype(np.int32), "rt"),
             ("square 3x3 + duplicated triangle", n2, np.concatenate([e2, e2[4:5]]).astype(np.int32), "ned"),
-            ("three triangles on one edge", nb, eb, "rt")]
+            ("three triangles on one edge", nb, eb, "rt"),
+            ("forty triangles on one edge", nf, ef, "rt")]
 
 
-@pytest.mark.parametrize("idx", range(4))
+@pytest.mark.parametrize("idx", range(5))
 def test_nonconforming_meshes_take_the_row_kernel(idx):
     name, nodes, elems, kind = nonconforming_cases()[idx]
     rng = np.random.default_rng(61 + idx)
