@@ -573,8 +573,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     const int R = md.ema_R;
     // header of the tile
     const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile];
-    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 1];
-    const int4 h2 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 2];  // record bases of wavefronts 1-3
+    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 1];  // words 8-10: record bases of wavefronts 1-3
     const int64_t r0 = tile * R;
     const int nslots = h0.x;
     const int nrows = h0.y;
@@ -618,15 +617,19 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         gid[2] = q.z & 0x3FFFFFFF;
         if constexpr (NV == 4) gid[3] = q.w;
     }
-    // record offset: the wavefront's base (tile header) plus the exclusive
-    // prefix of the dof counts within the wavefront (three ballots over the
-    // bits of a count <= 6)
+    // record offset: the wavefront's base (tile header word 7 + wavefront)
+    // plus the exclusive prefix of the dof counts within the wavefront (one
+    // ballot per bit of a count <= 6, each counted below the lane at once)
     const uint32_t cnt = __popc(mask);
-    const uint64_t below = __lanemask_lt();
-    const uint64_t b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
-    const int in_wave = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
-    const int wave = tid / 64;
-    const int wbase = wave == 0 ? 0 : wave == 1 ? h2.x : wave == 2 ? h2.y : h2.z;
+    int in_wave = 0;
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+        const uint64_t bb = __ballot(cnt & (1u << bit));
+        in_wave += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u)) << bit;
+    }
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);  // uniform in the wavefront: a scalar load
+    const int wbase = wave == 0 ? 0 : md.ema_hdr[tile * 12 + 7 + wave];
     if (have) {
         const int64_t roff = (int64_t)js0 + wbase + in_wave;
 #pragma unroll
@@ -761,7 +764,10 @@ fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s) {
 // Each mesh keeps its own rows per tile and LDS layout; the dynamic LDS is the
 // largest over the meshes.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_batch_ema(const MeshDev* __restrict__ table,
+// Five wavefronts per SIMD: the kernel holds every kind's tile body, and the
+// register count of the widest one (3D Nedelec) otherwise lands just above
+// the five-wavefront limit.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_ema(const MeshDev* __restrict__ table,
                                                   const int2* __restrict__ work, int64_t n_work,
                                                   int schedule, unsigned* counters) {
     extern __shared__ __align__(16) char smem_raw[];
