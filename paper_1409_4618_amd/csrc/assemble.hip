@@ -571,9 +571,10 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     constexpr int NLOC = Tr::NLOC, NV = Tr::NV, DIM = Tr::DIM;
     const int tid = threadIdx.x;
     const int R = md.ema_R;
-    // header of the tile
+    // header of the tile: words 0-7 here; words 8-10, the record bases of
+    // wavefronts 1-3, are read by the wavefront that needs one (below)
     const int4 h0 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile];
-    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 1];  // words 8-10: record bases of wavefronts 1-3
+    const int4 h1 = reinterpret_cast<const int4*>(md.ema_hdr)[3 * tile + 1];
     const int64_t r0 = tile * R;
     const int nslots = h0.x;
     const int nrows = h0.y;
@@ -612,10 +613,16 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
     }
     if (have) {
         e = en;
-        gid[0] = q.x & 0x3FFFFFFF;
-        gid[1] = q.y & 0x3FFFFFFF;
-        gid[2] = q.z & 0x3FFFFFFF;
-        if constexpr (NV == 4) gid[3] = q.w;
+        if constexpr (NV == 4) {
+            gid[0] = q.x & 0x3FFFFFFF;
+            gid[1] = q.y & 0x3FFFFFFF;
+            gid[2] = q.z & 0x3FFFFFFF;
+            gid[3] = q.w;
+        } else {
+            gid[0] = q.x;
+            gid[1] = q.y;
+            gid[2] = q.z;
+        }
     }
     // record offset: the wavefront's base (tile header word 7 + wavefront)
     // plus the exclusive prefix of the dof counts within the wavefront (one
@@ -666,7 +673,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
 #pragma unroll
             for (int k = 0; k < NLOC; ++k)
                 if ((mask >> k) & 1u)
-                    rowdiag[(int)((cp[k] >> 48) & 0xFFu)] = (int)((cp[k] >> (8 * k)) & 0xFFu);
+                    rowdiag[rec_row<KC>(cp[k])] = rec_col<KC>(cp[k], k);
         }
         st = ema_elem<KC>(gid, x, ca, cb);
         bad = !(fabs(st.J) > 0.0) || !isfinite(st.J);
