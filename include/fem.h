@@ -175,8 +175,9 @@ fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n
                             fem_batch* out);
 
 /* Bind the per-mesh buffers (host arrays [n] of device pointers; a/b entries
- * may be NULL = 1, K/M entries may be NULL to skip). Copies a small table to the
- * device and synchronises. Rebinding is allowed between launches.           */
+ * may be NULL = 1, K/M entries may be NULL to skip). Waits for the device to
+ * be idle (a launch of the batch may still read the table), then copies a
+ * small table to the device. Rebinding is allowed between launches.         */
 fem_status fem_batch_bind(fem_batch batch, const double* const* nodes,
                           const double* const* a, const double* const* b,
                           double* const* K_vals, double* const* M_vals);
@@ -203,11 +204,16 @@ fem_status fem_batch_config(fem_batch batch, int* rows_per_tile, int* schedule,
 fem_status fem_batch_set_config(fem_batch batch, int rows_per_tile, int schedule);
 
 /* One persistent launch over all bound meshes. Asynchronous; contains no
- * memset or allocation, so it may be captured into a HIP graph.            */
+ * memset or allocation, so it may be captured into a HIP graph. Launches of
+ * one batch, direct or replayed, must not overlap: they share a work-queue
+ * counter that the last workgroup resets. Queue them on one stream or
+ * synchronise between them.                                                */
 fem_status fem_batch_assemble(fem_batch batch, void* stream);
 
 /* Capture one fem_batch_assemble into a HIP graph held by the batch
- * (re-captured after bind / set_config / tune), then replay it on `stream`.  */
+ * (re-captured after bind / set_config / tune), then replay it on `stream`.
+ * Before a capture, one plain launch runs on the batch's own stream, ordered
+ * after the work already queued on `stream`, and is waited for.            */
 fem_status fem_batch_graph_launch(fem_batch batch, void* stream);
 
 void fem_batch_destroy(fem_batch batch);

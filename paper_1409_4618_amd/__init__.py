@@ -46,9 +46,10 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def _check_dev(t, dtype, name, shape=None):
-    torch = _torch()
     if t is None:
         return None
+    if t.is_cuda and t.dtype == dtype and t.is_contiguous() and (shape is None or t.shape == shape):
+        return t  # the common case, in one test
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
     if t.dtype != dtype:
@@ -152,8 +153,20 @@ class Mesh:
         check(lib().fem_status_query(self._h), "fem_status_query")
 
 
+def _check_inputs(mesh: Mesh, nodes, a, b):
+    torch = _torch()
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(a, torch.float64, "a", (mesh.n_elems,))
+    _check_dev(b, torch.float64, "b", (mesh.n_elems,))
+
+
 def assemble_into(mesh: Mesh, kind, nodes, a, b, K, M):
     """fem_assemble into caller-provided outputs (no allocation)."""
+    torch = _torch()
+    _, nnz = mesh.pattern_info(kind)
+    _check_inputs(mesh, nodes, a, b)
+    _check_dev(K, torch.float64, "K", (nnz,))
+    _check_dev(M, torch.float64, "M", (nnz,))
     check(lib().fem_assemble(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b), _ptr(K),
                              _ptr(M), _stream_ptr()), "fem_assemble")
 
@@ -162,9 +175,7 @@ def assemble(mesh: Mesh, kind, nodes, a=None, b=None):
     """Values (K, M) of K(a), M(b) on ``mesh.pattern(kind)``: f64 device tensors [nnz]."""
     torch = _torch()
     _, nnz = mesh.pattern_info(kind)
-    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
-    _check_dev(a, torch.float64, "a", (mesh.n_elems,))
-    _check_dev(b, torch.float64, "b", (mesh.n_elems,))
+    _check_inputs(mesh, nodes, a, b)
     K = torch.empty(nnz, dtype=torch.float64, device=nodes.device)
     M = torch.empty(nnz, dtype=torch.float64, device=nodes.device)
     assemble_into(mesh, kind, nodes, a, b, K, M)
@@ -176,7 +187,7 @@ def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b
     """Adjoint: (dL/dnodes, dL/da, dL/db) for L = gK . K(a) + gM . M(b)."""
     torch = _torch()
     _, nnz = mesh.pattern_info(kind)
-    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_inputs(mesh, nodes, a, b)
     _check_dev(gK, torch.float64, "gK", (nnz,))
     _check_dev(gM, torch.float64, "gM", (nnz,))
     dev = nodes.device
@@ -195,7 +206,7 @@ def assemble_backward_quadratic(mesh: Mesh, kind, nodes, a, b, u, need_a=True, n
     assemble_backward with gK = gM = u_row u_col, without materialising them."""
     torch = _torch()
     n_rows, _ = mesh.pattern_info(kind)
-    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_inputs(mesh, nodes, a, b)
     _check_dev(u, torch.float64, "u", (n_rows,))
     dev = nodes.device
     ga = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_a else None
@@ -279,12 +290,24 @@ class Batch:
                 pass
 
     def bind(self, nodes, a, b, K, M):
+        """Per-mesh device tensors (sequences of length n; a, b, K, M entries may be None)."""
+        torch = _torch()
         n = len(self.meshes)
+        nodes, a, b, K, M = (list(x) for x in (nodes, a, b, K, M))
+        if any(len(x) != n for x in (nodes, a, b, K, M)):
+            raise ValueError(f"bind needs {n} entries per argument")
+        for i, (m, k) in enumerate(zip(self.meshes, self.kinds)):
+            _, nnz = m.pattern_info(k)
+            if nodes[i] is None:
+                raise ValueError(f"nodes[{i}] is None")
+            _check_inputs(m, nodes[i], a[i], b[i])
+            _check_dev(K[i], torch.float64, f"K[{i}]", (nnz,))
+            _check_dev(M[i], torch.float64, f"M[{i}]", (nnz,))
 
         def arr(ts):
             return (ctypes.c_void_p * n)(*[(0 if t is None else t.data_ptr()) for t in ts])
 
-        self._keep = (list(nodes), list(a), list(b), list(K), list(M))
+        self._keep = (nodes, a, b, K, M)
         check(lib().fem_batch_bind(self._h, arr(nodes), arr(a), arr(b), arr(K), arr(M)), "fem_batch_bind")
 
     def tune(self, cache_path: Optional[str] = None):

@@ -296,6 +296,13 @@ static void drop_graph(fem_batch B) {
 static fem_status build_work(fem_batch B) {
     const bool ema = B->R == 0;
     if (ema && !B->ema_ok) return fail(FEM_EINVAL, "fem_batch: element-major tiles unavailable for this batch");
+    // an earlier launch of this batch, on any stream, may still be reading the
+    // work list and the mesh table that are rewritten below
+    FEM_HIP(hipDeviceSynchronize());
+    // invalid until the rebuild below completes: a failed rebuild leaves no
+    // mix of old and new tiling behind (the next launch retries it)
+    B->work_valid = false;
+    drop_graph(B);
     std::vector<int2> work;
     std::vector<double> cost;
     B->pmax = 0;
@@ -358,7 +365,6 @@ static fem_status build_work(fem_batch B) {
         FEM_HIP(hipMemcpy(B->table_dev, B->host_table.data(), B->host_table.size() * sizeof(MeshDev),
                           hipMemcpyHostToDevice));
     B->work_valid = true;
-    drop_graph(B);
     return FEM_OK;
 }
 
@@ -576,10 +582,22 @@ fem_status fem_batch_graph_launch(fem_batch B, void* stream) {
         if (fem_status st = build_work(B)) return st;
     if (!B->graph_valid) {
         drop_graph(B);
-        // make sure the kernel attributes are set outside the capture
-        FEM_HIP(hipStreamSynchronize(B->cap_stream));
-        if (fem_status st = fem_batch_assemble(B, B->cap_stream)) return st;
-        FEM_HIP(hipStreamSynchronize(B->cap_stream));
+        // One plain launch first, so that the kernel attributes are set outside
+        // the capture. It runs on the capture stream after the work already
+        // queued on `stream` (which may still read K and M, or run an earlier
+        // launch of this batch that shares its work-queue counters), and has
+        // finished before the replay below is queued.
+        hipEvent_t ev = nullptr;
+        FEM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e0 = hipEventRecord(ev, reinterpret_cast<hipStream_t>(stream));
+        if (e0 == hipSuccess) e0 = hipStreamWaitEvent(B->cap_stream, ev, 0);
+        fem_status st0 = e0 == hipSuccess ? fem_batch_assemble(B, B->cap_stream) : hip_fail(e0, "fem_batch_graph_launch");
+        if (st0 == FEM_OK) {
+            e0 = hipStreamSynchronize(B->cap_stream);
+            if (e0 != hipSuccess) st0 = hip_fail(e0, "fem_batch_graph_launch");
+        }
+        (void)hipEventDestroy(ev);
+        if (st0 != FEM_OK) return st0;
         FEM_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeRelaxed));
         fem_status st = fem_batch_assemble(B, B->cap_stream);
         hipGraph_t g = nullptr;

@@ -156,3 +156,73 @@ def test_full_size_batch_as_benchmarked():
         csr, _ = oracle.assemble(p.nodes, p.elems, p.kind, a=p.a, b=p.b)
         K, M = refs[i]
         assert rel_fro(K.cpu().numpy(), csr.Kv) <= TOL and rel_fro(M.cpu().numpy(), csr.Mv) <= TOL
+
+
+def test_launches_are_ordered_with_the_callers_stream(batch_setup):
+    """The first graph launch (which runs one plain launch before capturing)
+    and a rebind both wait for work already queued by the caller: a read of K
+    queued behind a spin on the caller's stream still sees the old values, and
+    a launch queued before a rebind still writes the buffers it was bound to."""
+    import torch
+    import paper_1409_4618_amd as fem
+    probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
+    say("[gpu] batch launches ordered with the caller's stream")
+    s = torch.cuda.Stream()
+    B = fem.Batch(meshes, kinds)
+    B.bind(nodes, a, b, Ks, Ms)
+    B.set_config(0, 1)
+    for K, M in zip(Ks, Ms):
+        K.fill_(-1.0)
+        M.fill_(-1.0)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(20_000_000)
+        seen = Ks[-1].clone()
+        B.graph_launch()
+    torch.cuda.synchronize()
+    assert bool((seen == -1.0).all())
+    for (K, M), (Kr, Mr) in zip(zip(Ks, Ms), refs):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr)
+    # a launch queued behind a spin, then a rebind to fresh outputs
+    Ks2 = [torch.full_like(K, -2.0) for K in Ks]
+    Ms2 = [torch.full_like(M, -2.0) for M in Ms]
+    for K, M in zip(Ks, Ms):
+        K.fill_(-1.0)
+        M.fill_(-1.0)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(20_000_000)
+        B.assemble()
+    B.bind(nodes, a, b, Ks2, Ms2)
+    torch.cuda.synchronize()
+    for (K, M), (Kr, Mr) in zip(zip(Ks, Ms), refs):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr)
+    assert all(bool((K == -2.0).all()) for K in Ks2)
+    B.assemble()
+    torch.cuda.synchronize()
+    for (K, M), (Kr, Mr) in zip(zip(Ks2, Ms2), refs):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr)
+
+
+def test_binding_rejects_bad_buffers(batch_setup):
+    """Buffers of the wrong size, type or device are refused by the binding
+    before any kernel could write past them."""
+    import torch
+    import paper_1409_4618_amd as fem
+    probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
+    say("[gpu] binding argument checks")
+    B = fem.Batch(meshes[:2], kinds[:2])
+    short = Ks[1][:-1]
+    with pytest.raises(ValueError):
+        B.bind(nodes[:2], a[:2], b[:2], [Ks[0], short], Ms[:2])
+    with pytest.raises(ValueError):
+        B.bind(nodes[:2], a[:2], b[:2], Ks[:1], Ms[:2])
+    with pytest.raises(ValueError):
+        B.bind(nodes[:2], [a[0], a[1].float()], b[:2], Ks[:2], Ms[:2])
+    with pytest.raises(ValueError):
+        fem.assemble_into(meshes[0], kinds[0], nodes[0], a[0], b[0], Ks[0], Ms[0][:-1])
+    with pytest.raises(ValueError):
+        fem.assemble_into(meshes[0], kinds[0], nodes[0], a[0][:-1], b[0], Ks[0], Ms[0])
+    with pytest.raises(ValueError):
+        fem.assemble_into(meshes[0], kinds[0], nodes[0].cpu(), a[0], b[0], Ks[0], Ms[0])
+    torch.cuda.synchronize()
