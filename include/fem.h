@@ -20,6 +20,10 @@
  *     handle (topology, pattern, maps, scratch) and frees it in *_destroy.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
  *     enqueued on it asynchronously unless the entry point says it synchronises.
+ *   - A handle is not thread-safe, and its work on different streams must not
+ *     overlap: lazily built data (pattern, tiles, maps) and the adjoint's
+ *     per-node partial sums live in the handle. Order such calls on one stream
+ *     or synchronise between them. Distinct handles are independent.
  *   - Every entry point returns a fem_status. On an error nothing is enqueued,
  *     output buffers are left untouched, and fem_last_error() returns a message
  *     (thread-local, valid until the next call on that thread). Faults detected

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfem.so")
-SOURCES = ["radix_sort.hip", "topology.hip", "assemble.hip", "api.hip"]
+SOURCES = ["radix_sort.hip", "topology.hip", "assemble.hip", "adjoint.hip", "api.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -32,7 +32,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
 # Per-source flags. The assembly kernels are built without floating-point
 # contraction: every product is rounded on its own, so the same element entry
 # gets bitwise the same value in whichever unrolled copy of the slot loop it
-# is computed (this keeps K and M bitwise symmetric and deterministic).
+# is computed (this keeps K and M bitwise symmetric and deterministic). The
+# adjoint (adjoint.hip) has no such constraint and keeps hipcc's default
+# contraction into FMAs.
 SOURCE_FLAGS = {"assemble.hip": ["-ffp-contract=off"]}
 
 

@@ -132,6 +132,23 @@ struct fem_mesh_s {
 
 namespace fem {
 
+// Per-kind sizes: kind code 0 = 2D (Nedelec or Raviart-Thomas, the same
+// element), 1 = 3D Raviart-Thomas, 2 = 3D Nedelec.
+template <int KC>
+struct KT;
+template <>
+struct KT<0> {  // 2D (Nedelec / Raviart-Thomas)
+    static constexpr int DIM = 2, NLOC = 3, NV = 3;
+};
+template <>
+struct KT<1> {  // 3D Raviart-Thomas
+    static constexpr int DIM = 3, NLOC = 4, NV = 4;
+};
+template <>
+struct KT<2> {  // 3D Nedelec
+    static constexpr int DIM = 3, NLOC = 6, NV = 4;
+};
+
 // elements per adjoint workgroup (one per lane)
 constexpr int BWD_BLOCK = 256;
 
