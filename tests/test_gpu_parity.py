@@ -67,6 +67,10 @@ CASES = [
     ("kuhn 7x6x5 relabelled", lambda: relabel(*mg.kuhn_box(7, 6, 5), 2), "rt"),
     ("kuhn 12^3", lambda: mg.kuhn_box(12), "ned"),
     ("kuhn 12^3", lambda: mg.kuhn_box(12), "rt"),
+    # relabelled nodes spread each tile's node ids over the whole range
+    # (more than 2^16 apart), so no tile sees nearby ids
+    ("kuhn strip 16500x1x1 relabelled", lambda: relabel(*mg.kuhn_box(16500, 1, 1, lx=16500.0), 3), "ned"),
+    ("kuhn strip 16500x1x1 relabelled", lambda: relabel(*mg.kuhn_box(16500, 1, 1, lx=16500.0), 3), "rt"),
     ("kuhn 1x1x1", lambda: mg.kuhn_box(1), "ned"),
     ("single tet", lambda: (mg.kuhn_box(1)[0], mg.kuhn_box(1)[1][:1]), "rt"),
     ("single triangle", lambda: (np.array([[0., 0.], [1., 0.], [0., 1.]]), np.array([[0, 1, 2]], np.int32)), "ned"),
