@@ -357,7 +357,7 @@ def main():
                     help="time one secondary workload alone and print its JSON (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1",
+        print(json.dumps({"error": "libfem assembles on one GPU per process: --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

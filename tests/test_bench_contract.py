@@ -1,6 +1,6 @@
 """The benchmark's accounting, on the CPU (no GPU is touched).
 
-* `bench.py --gpus N` with N > 1 refuses with a message: this build runs on one
+* `bench.py --gpus N` with N > 1 refuses with a message: the library assembles on one
   GPU.
 * The algorithmic bytes behind `roofline.achieved` equal the compulsory bytes
   written out independently from the Kuhn closed forms: a tet reads its four
