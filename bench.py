@@ -17,6 +17,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -232,8 +233,8 @@ def batched_rate(steps, warmup, ref_mtets, scale=1.0):
                       for p, K in zip(probs, Ks))
     B = fem.Batch(meshes, kinds)
     B.bind(nodes, a, b, Ks, Ms)
-    cache = os.path.join(ROOT, "gpurun_out", "fem_batch_tune.jsonl")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    # the autotuner's JSON-lines cache (FEM_TUNE_CACHE overrides the location)
+    cache = os.environ.get("FEM_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "fem_batch_tune.jsonl"))
     B.tune(cache)
     cfg = B.config()
     ms_graph = timed(B.graph_launch, steps, warmup)
