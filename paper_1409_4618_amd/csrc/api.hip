@@ -538,9 +538,16 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     int R = 0, sc = 0;
     if (cache_lookup(cache_path, dev, sig, &R, &sc)) return fem_batch_set_config(B, R, sc);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipEvent_t e0, e1;
-    FEM_HIP(hipEventCreate(&e0));
-    FEM_HIP(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    FEM_HIP(hipEventCreate(&ev.e0));
+    FEM_HIP(hipEventCreate(&ev.e1));
+    const hipEvent_t e0 = ev.e0, e1 = ev.e1;
     double best = 1e30;
     int bestR = B->ema_ok ? 0 : 128, bestS = 1;
     const int Rs[4] = {0, 64, 128, 256};
@@ -568,8 +575,6 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     fem_status st = fem_batch_set_config(B, bestR, bestS);
     if (st == FEM_OK) cache_store(cache_path, dev, sig, bestR, bestS, best);
     return st;
