@@ -8,7 +8,8 @@ lengths, uneven tile element lists) and badly shaped elements (the smallest
 the same as on the structured meshes: topology and CSR pattern bit-exact
 against the oracle, values within relative Frobenius 1e-12, bitwise symmetric
 and deterministic; the adjoint of L = u^T (K(a) + M(b)) u within 1e-11 of the
-oracle's gradient (relative to its largest entry), both entry points.
+oracle's gradient (relative to its largest entry), both entry points; a
+batch of mixed Delaunay meshes bitwise equal to single-mesh launches.
 """
 import numpy as np
 import pytest
@@ -83,3 +84,44 @@ def test_adjoint_on_delaunay_meshes(dim, kind):
         err = np.abs(got - ref).max() / np.abs(ref).max()
         say(f"    dL/d{nm}: max rel err {err:.2e}")
         assert err <= GTOL, (nm, err)
+
+
+@pytest.mark.parametrize("rows", [0, 128])
+def test_batch_of_delaunay_meshes(rows):
+    """Mixed 2D/3D Delaunay meshes of both kinds in one batched launch (and its
+    graph replay): bitwise equal to single-mesh launches."""
+    import torch
+    import paper_1409_4618_amd as fem
+    specs = [(2, 500, 11, "ned"), (3, 300, 12, "rt"), (3, 700, 13, "ned"), (2, 1500, 14, "rt"),
+             (3, 150, 15, "ned"), (2, 90, 16, "ned")]
+    say(f"[gpu] batch of {len(specs)} Delaunay meshes, rows_per_tile={rows}")
+    meshes, kinds, nodes, a, b, Ks, Ms, refs = [], [], [], [], [], [], [], []
+    for dim, n, seed, kind in specs:
+        nd, el, ca, cb, _ = delaunay_mesh(dim, n, seed)
+        tn, te, ta, tb = dev_tensors(nd, el, ca, cb)
+        m = fem.Mesh(tn, te)
+        K, M = fem.assemble(m, kind, tn, ta, tb)
+        meshes.append(m)
+        kinds.append(kind)
+        nodes.append(tn)
+        a.append(ta)
+        b.append(tb)
+        refs.append((K, M))
+        Ks.append(torch.full_like(K, float("nan")))
+        Ms.append(torch.full_like(M, float("nan")))
+    B = fem.Batch(meshes, kinds)
+    B.bind(nodes, a, b, Ks, Ms)
+    B.set_config(rows, 1)
+    B.assemble()
+    torch.cuda.synchronize()
+    for i, ((K, M), (Kr, Mr)) in enumerate(zip(zip(Ks, Ms), refs)):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr), i
+    for K, M in zip(Ks, Ms):
+        K.zero_()
+        M.zero_()
+    B.graph_launch()
+    torch.cuda.synchronize()
+    for i, ((K, M), (Kr, Mr)) in enumerate(zip(zip(Ks, Ms), refs)):
+        assert torch.equal(K, Kr) and torch.equal(M, Mr), i
+    for m in meshes:
+        m.status()
