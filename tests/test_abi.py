@@ -78,3 +78,24 @@ def test_product_path_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+def test_missing_library_fails_loudly():
+    """Without libfem.so every entry point raises (no silent CPU path): checked
+    in a fresh interpreter whose loader points at a file that does not exist."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1409_4618_amd._lib as L\n"
+        "L.LIB_PATH = '/nonexistent/libfem.so'\n"
+        "import paper_1409_4618_amd as fem\n"
+        "try:\n"
+        "    fem.kind_code('ned'); fem.lib()\n"
+        "except fem.FemError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "is missing" in r.stdout
