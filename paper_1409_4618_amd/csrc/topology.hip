@@ -409,30 +409,36 @@ fem_status build_topology(fem_mesh m, const double* nodes, const int32_t* elems_
 }
 
 // ---------------------------------------------------------------- pattern
-__global__ void k_pair_keys(const int32_t* elems2dofs, int64_t T, int nloc, int64_t N,
-                            uint64_t* keys, uint32_t* vals) {
+// Pairs of the slots j0 .. j0+n of the row-sorted slot list (a range of whole
+// rows): pair q = j * nloc + l couples slot j's dof (the row) with the dof of
+// local index l of the same element (the column). Key = row * N + column; the
+// payload is the chunk-local pair index.
+__global__ void k_pair_keys(const int32_t* rs_slot, int64_t n, const int32_t* elems2dofs, int nloc,
+                            int64_t N, uint64_t* keys, uint32_t* vals) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n2 = (int64_t)nloc * nloc;
-    if (q >= T * n2) return;
-    const int64_t e = q / n2;
-    const int kl = (int)(q - e * n2);
-    const int k = kl / nloc;
-    const int l = kl - k * nloc;
-    const uint64_t I = (uint32_t)elems2dofs[e * nloc + k];
+    if (q >= n * nloc) return;
+    const int64_t j = q / nloc;
+    const int l = (int)(q - j * nloc);
+    const int64_t sl = rs_slot[j];
+    const int64_t e = sl / nloc;
+    const uint64_t I = (uint32_t)elems2dofs[sl];
     const uint64_t J = (uint32_t)elems2dofs[e * nloc + l];
     keys[q] = I * (uint64_t)N + J;
     vals[q] = (uint32_t)q;
 }
 
+// After the exclusive scan of the head flags: the CSR position of each sorted
+// pair is base + (its unique rank); heads write the column and, at a row's
+// first entry, the row start. map[pair] = CSR position (chunk-local pairs).
 __global__ void k_pair_unique(const uint64_t* keys, const uint32_t* sorted_pairs,
-                              const uint32_t* scan, int64_t n, int64_t N, int32_t* colind,
-                              int64_t* rowptr, int32_t* map) {
+                              const uint32_t* scan, int64_t n, int64_t N, int64_t base,
+                              int32_t* colind, int64_t* rowptr, int32_t* map) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
     const bool head = (i == 0 || k != keys[i - 1]);
-    const int32_t id = (int32_t)(scan[i] + (head ? 1u : 0u) - 1u);
-    map[sorted_pairs[i]] = id;
+    const int64_t id = base + (int64_t)(scan[i] + (head ? 1u : 0u) - 1u);
+    map[sorted_pairs[i]] = (int32_t)id;
     if (head) {
         const uint64_t row = k / (uint64_t)N;
         colind[id] = (int32_t)(k - row * (uint64_t)N);
@@ -446,22 +452,21 @@ __global__ void k_slot_rank(const int32_t* rs_slot, int64_t n, int32_t* rank) {
     rank[rs_slot[i]] = (int32_t)i;
 }
 
-__global__ void k_colpos(const int32_t* rs_slot, const int32_t* elems2dofs, const int32_t* map,
-                         const int64_t* rowptr, int64_t n_slots, int nloc, int cp, uint8_t* colpos,
-                         int* err) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_slots) return;
-    const int64_t s = rs_slot[i];
-    const int64_t base = rowptr[elems2dofs[s]];
-    const int64_t e = s / nloc;
-    const int k = (int)(s - e * nloc);
+// Column offsets of the slots j0 .. j0+n of the row-sorted list (the same
+// chunk as the pairs in map): byte l = CSR position of (row, dof l) minus the
+// row start.
+__global__ void k_colpos(const int32_t* rs_slot, int64_t n, const int32_t* elems2dofs, const int32_t* map,
+                         const int64_t* rowptr, int nloc, int cp, uint8_t* colpos, int* err) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t base = rowptr[elems2dofs[rs_slot[j]]];
     uint8_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int l = 0; l < nloc; ++l) {
-        const int64_t off = (int64_t)map[(e * nloc + k) * nloc + l] - base;
+        const int64_t off = (int64_t)map[j * nloc + l] - base;
         if (off < 0 || off > 255) atomicOr(err, ERR_OVERFLOW);
         out[l] = (uint8_t)off;
     }
-    for (int l = 0; l < cp; ++l) colpos[i * cp + l] = out[l];
+    for (int l = 0; l < cp; ++l) colpos[j * cp + l] = out[l];
 }
 
 // Longest row and, for R = 32, 64, 128, 256, the most values of a tile of R
@@ -508,42 +513,107 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     const int64_t N = ds.n;
     const int64_t n_slots = T * nloc;
     const int64_t n_pairs = n_slots * nloc;
-    if (n_pairs >= (int64_t(1) << 31))
-        return fail(FEM_EOVERFLOW, "fem_pattern: n_elems * n_local^2 must be below 2^31");
     p.nloc = nloc;
     p.cp_stride = nloc <= 4 ? 4 : 8;
     p.n_rows = N;
+    // The (row, column) pairs of every element are sorted and made unique in
+    // chunks of whole rows (ranges of the row-sorted slot list), each at most
+    // FEM_PAIR_CHUNK pairs (default 2^29) unless a single row is larger. The
+    // keys are unique per (row, column) and rows do not straddle chunks, so
+    // the result does not depend on the chunking.
+    int64_t chunk_max = int64_t(1) << 29;
+    if (const char* sc = std::getenv("FEM_PAIR_CHUNK")) chunk_max = std::max<int64_t>(std::atoll(sc), 1);
+    std::vector<int64_t> rb{0}, sb{0};  // row and slot boundaries of the chunks
+    if (n_pairs <= chunk_max) {
+        rb.push_back(N);
+        sb.push_back(n_slots);
+    } else {
+        std::vector<int32_t> h((size_t)N + 1);
+        FEM_HIP(hipMemcpyAsync(h.data(), ds.rs_ptr, (size_t)(N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FEM_HIP(hipStreamSynchronize(s));
+        for (int64_t r0 = 0; r0 < N;) {
+            // the last row boundary r1 with (h[r1] - h[r0]) * nloc <= chunk_max
+            const int64_t lim = (int64_t)h[r0] + chunk_max / nloc;
+            int64_t r1 = (int64_t)(std::upper_bound(h.begin() + r0 + 1, h.end(), lim) - h.begin()) - 1;
+            if (r1 <= r0) r1 = r0 + 1;  // one row larger than a chunk: alone
+            rb.push_back(r1);
+            sb.push_back(h[r1]);
+            r0 = r1;
+        }
+    }
+    const size_t n_chunks = rb.size() - 1;
+    int64_t max_pairs = 1;
+    for (size_t c = 0; c < n_chunks; ++c) max_pairs = std::max(max_pairs, (sb[c + 1] - sb[c]) * nloc);
+    if (max_pairs >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_pattern: the element pairs of one row range exceed 2^31");
+    // The pattern's arrays join the handle only when the build succeeds: a
+    // refused build (too many nonzeros, a row too long) leaves nothing behind.
+    struct Owned {
+        Pattern* p;
+        std::vector<void*> v;
+        bool keep = false;
+        ~Owned() {
+            if (keep) return;
+            for (void* q : v) (void)hipFree(q);
+            p->rowptr = nullptr;
+            p->colind = nullptr;
+            p->colpos = nullptr;
+            p->slot_rank = nullptr;
+        }
+    } own{&p, {}};
+    auto alloc = [&](auto** ptr, int64_t count) {
+        *ptr = nullptr;
+        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(**ptr);
+        hipError_t e = hipMalloc((void**)ptr, bytes);
+        if (e == hipSuccess) own.v.push_back((void*)*ptr);
+        return e;
+    };
     TmpBufs tb;
-    FEM_HIP(tb.alloc(n_pairs));
-    hipLaunchKernelGGL(k_pair_keys, dim3(nblk(n_pairs)), dim3(TB), 0, s, ds.elems2dofs, T, nloc, N,
-                       tb.keys, tb.vals);
-    FEM_HIP(hipGetLastError());
+    FEM_HIP(tb.alloc(std::max<int64_t>(max_pairs, 8)));
     const int bits = bit_length((uint64_t)N * (uint64_t)N - 1);
-    FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, n_pairs, bits, s));
-    hipLaunchKernelGGL(k_flags, dim3(nblk(n_pairs)), dim3(TB), 0, s, tb.keys, n_pairs, tb.scan);
-    FEM_HIP(hipGetLastError());
-    FEM_HIP(scan_exclusive_u32(tb.scan, n_pairs, s));
+    FEM_HIP(alloc(&p.rowptr, N + 1));
+    int32_t* map = nullptr;     // CSR position of every pair of the current chunk
+    int32_t* staged = nullptr;  // several chunks: columns until the total is known
+    struct Free {
+        int32_t** p;
+        ~Free() { (void)hipFree(*p); }
+    } free_map{&map}, free_staged{&staged};
+    FEM_HIP(hipMalloc((void**)&map, (size_t)max_pairs * sizeof(int32_t)));
+    if (n_chunks > 1) FEM_HIP(hipMalloc((void**)&staged, (size_t)n_pairs * sizeof(int32_t)));
+    FEM_HIP(alloc(&p.colpos, n_slots * p.cp_stride));
+    FEM_HIP(hipMemsetAsync(m->err_word, 0, sizeof(int), s));
     int64_t nnz = 0;
-    if (fem_status st = read_count(tb.scan, tb.keys, n_pairs, s, &nnz)) return st;
+    for (size_t c = 0; c < n_chunks; ++c) {
+        const int64_t j0 = sb[c], ns = sb[c + 1] - sb[c], np = ns * nloc;
+        if (np == 0) continue;
+        hipLaunchKernelGGL(k_pair_keys, dim3(nblk(np)), dim3(TB), 0, s, ds.rs_slot + j0, ns, ds.elems2dofs,
+                           nloc, N, tb.keys, tb.vals);
+        FEM_HIP(hipGetLastError());
+        FEM_HIP(radix_sort_pairs(tb.keys, tb.vals, tb.keys_tmp, tb.vals_tmp, np, bits, s));
+        hipLaunchKernelGGL(k_flags, dim3(nblk(np)), dim3(TB), 0, s, tb.keys, np, tb.scan);
+        FEM_HIP(hipGetLastError());
+        FEM_HIP(scan_exclusive_u32(tb.scan, np, s));
+        int64_t nc = 0;
+        if (fem_status st = read_count(tb.scan, tb.keys, np, s, &nc)) return st;
+        if (nnz + nc >= (int64_t(1) << 31))
+            return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 - 1 nonzeros");
+        if (n_chunks == 1) FEM_HIP(alloc(&p.colind, nc));
+        hipLaunchKernelGGL(k_pair_unique, dim3(nblk(np)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan, np, N,
+                           nnz, n_chunks == 1 ? p.colind : staged, p.rowptr, map);
+        hipLaunchKernelGGL(k_colpos, dim3(nblk(ns)), dim3(TB), 0, s, ds.rs_slot + j0, ns, ds.elems2dofs, map,
+                           p.rowptr, nloc, p.cp_stride, p.colpos + j0 * p.cp_stride, m->err_word);
+        FEM_HIP(hipGetLastError());
+        nnz += nc;
+    }
     p.nnz = nnz;
-    FEM_HIP(dmalloc(m, &p.rowptr, N + 1));
-    FEM_HIP(dmalloc(m, &p.colind, nnz));
-    int32_t* map = nullptr;  // CSR position of every (element, k, l), temporary
-    FEM_HIP(hipMalloc((void**)&map, n_pairs * sizeof(int32_t)));
-    struct MapFree {
-        int32_t* p;
-        ~MapFree() { (void)hipFree(p); }
-    } map_free{map};
-    hipLaunchKernelGGL(k_pair_unique, dim3(nblk(n_pairs)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan,
-                       n_pairs, N, p.colind, p.rowptr, map);
+    if (n_chunks > 1) {
+        FEM_HIP(alloc(&p.colind, nnz));
+        FEM_HIP(hipMemcpyAsync(p.colind, staged, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p.rowptr + N, nnz);
     FEM_HIP(hipGetLastError());
-    FEM_HIP(dmalloc(m, &p.slot_rank, n_slots));
+    FEM_HIP(alloc(&p.slot_rank, n_slots));
     hipLaunchKernelGGL(k_slot_rank, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, n_slots, p.slot_rank);
-    FEM_HIP(dmalloc(m, &p.colpos, n_slots * p.cp_stride));
-    FEM_HIP(hipMemsetAsync(m->err_word, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_colpos, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, ds.elems2dofs, map,
-                       p.rowptr, n_slots, nloc, p.cp_stride, p.colpos, m->err_word);
     FEM_HIP(hipGetLastError());
     // row statistics (reuse the scan buffer as 4 ints)
     int* stats = reinterpret_cast<int*>(tb.scan);
@@ -559,6 +629,8 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     for (int q = 0; q < 4; ++q) p.tile_pmax[q] = host_stats[1 + q];
     if ((err & ERR_OVERFLOW) || p.max_row_len > 255)
         return fail(FEM_EOVERFLOW, "fem_pattern: a row has more than 255 entries");
+    for (void* q : own.v) m->allocs.push_back(q);
+    own.keep = true;
     p.built = true;
     return FEM_OK;
 }

@@ -269,3 +269,21 @@ def test_batch_with_a_nonconforming_mesh():
         m.status()
     for (K, M), K2, M2 in zip(ref, K_l, M_l):
         assert torch.equal(K, K2) and torch.equal(M, M2)
+
+
+@pytest.mark.parametrize("chunk", ["1", "333"])
+@pytest.mark.parametrize("name,maker,kind", [CASES[0], CASES[1], CASES[3], CASES[4]],
+                         ids=[f"{c[0]}-{c[2]}" for c in (CASES[0], CASES[1], CASES[3], CASES[4])])
+def test_pattern_in_row_chunks_matches_oracle(monkeypatch, chunk, name, maker, kind):
+    """The pattern sorted in chunks of whole rows (at most FEM_PAIR_CHUNK pairs,
+    a single row alone when it is larger) is the same bit for bit: rowptr,
+    colind, and the assembled values that go through the column offsets."""
+    monkeypatch.setenv("FEM_PAIR_CHUNK", chunk)
+    nodes, elems = maker()
+    nodes = np.array(nodes, dtype=np.float64)
+    rng = np.random.default_rng(zlib.crc32((name + kind + chunk).encode()))
+    nodes = mg.perturb_interior(nodes, 0.05, 0.2, rng)
+    a = rng.lognormal(0, 0.5, elems.shape[0])
+    b = rng.uniform(0.5, 2.0, elems.shape[0])
+    g = run_case(f"{name}, pair chunks of {chunk}", nodes, elems, kind, a, b)
+    check_against_oracle(g, nodes, elems, kind, a, b)
