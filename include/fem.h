@@ -115,7 +115,11 @@ fem_status fem_mesh_topology(fem_mesh mesh, const int32_t** edges2nodes,
  * Builds it on first use (synchronises `stream`), then returns borrowed device
  * pointers: rowptr i64 [n_rows+1], colind i32 [nnz]. n_rows is the number of
  * edges (Nedelec, 2D RT) or faces (3D RT). Outputs may be NULL.
- * FEM_EOVERFLOW if a row has more than 255 entries or n_elems * n_local^2 >= 2^31. */
+ * The element pairs are sorted in chunks of whole rows (at most 2^29 pairs
+ * each; the environment variable FEM_PAIR_CHUNK sets another bound), so
+ * n_elems * n_local^2 may exceed 2^31 (3D Nedelec on a 60 M-tet mesh).
+ * FEM_EOVERFLOW if a row has more than 255 entries or nnz >= 2^31; a refused
+ * build keeps nothing, and the other kind's pattern can still be built.      */
 fem_status fem_pattern(fem_mesh mesh, fem_kind kind, void* stream,
                        int64_t* n_rows, int64_t* nnz,
                        const int64_t** rowptr, const int32_t** colind);
