@@ -125,3 +125,16 @@ def test_batch_of_delaunay_meshes(rows):
         assert torch.equal(K, Kr) and torch.equal(M, Mr), i
     for m in meshes:
         m.status()
+
+
+def test_sweep_of_random_delaunay_meshes():
+    """24 seeded meshes of random size (8 to 1500 points, both dimensions and
+    kinds): each against the oracle, to the same bars, in one process."""
+    rng = np.random.default_rng(2024)
+    for i in range(24):
+        dim = 2 + (i % 2)
+        kind = "ned" if (i // 2) % 2 == 0 else "rt"
+        n_points = int(rng.integers(8, 1500 if dim == 2 else 600))
+        nodes, elems, a, b, _ = delaunay_mesh(dim, n_points, 1000 + i)
+        g = run_case(f"sweep {i}: delaunay {dim}D {n_points} points", nodes, elems, kind, a, b)
+        check_against_oracle(g, nodes, elems, kind, a, b)
