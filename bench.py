@@ -6,10 +6,15 @@ Headline (``value``): M tets/s of one numeric assembly of 3D Nedelec K and M in
 CSR form (fem_assemble, one kernel launch) on the Kuhn 64^3 workload (1,572,864
 tets, interior nodes perturbed by <= 0.2h, a, b ~ lognormal(0, 0.5)), inputs
 resident in HBM, topology and pattern built beforehand (as the paper's assembly
-routines take precomputed topology). The same line reports the 128^3 target
-mesh, the forward+adjoint rate on 96^3, the batched persistent launch on 256
-uneven meshes, the cold end-to-end rate, the roofline of the forward kernel and
-the CPU oracle's rate on a bounded sample.
+routines take precomputed topology). Each timed step first reads a 1 GiB
+buffer, so the 256 MB last-level cache holds none of the step's data, then
+times one launch with HIP events; ``value`` uses the median. The warm rate
+(back-to-back launches, whose inputs partly stay in that cache) is reported
+beside it. The same line reports the 128^3 target mesh (with its own roofline
+block), the forward + adjoint rate on 96^3 through torch.autograd, the batched
+persistent launch on 256 uneven meshes, the one-time topology and pattern
+times, and the CPU oracle's rate on a bounded sample, one thread and all host
+cores.
 """
 from __future__ import annotations
 
@@ -35,6 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # while the kernel sources, and the tile builder that sizes the tiles, still
 # hash to the value it was measured with.
 PROFILE = os.path.join(ROOT, "profiles", "fem_forward_ema_ned3d_kuhn64.txt")
+PROFILE_128 = os.path.join(ROOT, "profiles", "fem_forward_ema_ned3d_kuhn128.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4618_amd", "csrc", f)
                   for f in ("assemble.hip", "element.h", "fem_internal.h", "topology.hip")]
 
@@ -52,11 +58,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per launch from the committed profile, or None if the kernel
+def profiled_traffic(path=PROFILE):
+    """HBM bytes per launch from a committed profile, or None if the kernel
     sources changed since it was taken (or there is no profile)."""
     try:
-        with open(PROFILE) as fh:
+        with open(path) as fh:
             fields = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -131,41 +137,103 @@ def forward_rate(p, s, steps, warmup):
     return dict(ms=ms, mtets=T / (ms * 1e-3) / 1e6, bytes=bytes_, gbs=gbs, frac=gbs / PEAK_HBM_GBS)
 
 
-def cold_rate(p, s):
-    """Forward time with the 256 MB last-level cache flushed before each launch."""
+class Flush:
+    """Evicts the last-level cache by reading a 1 GiB buffer (a read leaves no
+    dirty lines to be written back during the timed launch)."""
+
+    def __init__(self):
+        import torch
+        self.buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        self.out = torch.empty((), dtype=torch.float64, device="cuda:0")
+
+    def __call__(self):
+        import torch
+        torch.sum(self.buf, dim=0, out=self.out)
+
+
+def cold_times(fn, steps, warmup, flush):
+    """Per-step times (ms) of fn(), each after a cache flush: HIP events on the
+    current stream around fn() alone; the flush runs before the first event."""
     import torch
-    import paper_1409_4618_amd as fem
-    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
-    times = []
-    for _ in range(5):
-        flush.fill_(1.0)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        flush()
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        flush()
         e0.record()
-        fem.assemble_into(s["mesh"], p.kind, s["nodes"], s["a"], s["b"], s["K"], s["M"])
+        fn()
         e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    del flush
-    return float(np.median(times))
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def cold_forward(p, s, steps, warmup, flush):
+    import paper_1409_4618_amd as fem
+    run = lambda: fem.assemble_into(s["mesh"], p.kind, s["nodes"], s["a"], s["b"], s["K"], s["M"])
+    times = cold_times(run, steps, warmup, flush)
+    s["mesh"].status()
+    T, V = p.T, p.nodes.shape[0]
+    bytes_ = algorithmic_bytes(T, V, p.dim, s["nnz"], p.a is not None)
+    ms = float(np.median(times))
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    return dict(ms=ms, ms_min=float(np.min(times)), ms_max=float(np.max(times)),
+                mtets=T / (ms * 1e-3) / 1e6, bytes=bytes_, gbs=gbs, frac=gbs / PEAK_HBM_GBS)
 
 
 def fwd_bwd_rate(p, steps, warmup):
+    """Forward + backward through torch.autograd: K, M, L = assemble_quadratic
+    (fem_assemble and fem_quadratic_value) and L.backward() (the quadratic
+    adjoint, dL/da, dL/db, dL/dnodes), timed with HIP events around each half
+    of every step. Also reported: the adjoint kernels alone, and the adjoint
+    with materialised weights gK = gM = u_row u_col."""
     import torch
     import paper_1409_4618_amd as fem
     s = setup_mesh(p)
+    d = torch.device("cuda:0")
     rowptr, colind = s["mesh"].pattern(p.kind)
-    u = torch.tensor(p.u, device="cuda:0")
-    rows = torch.repeat_interleave(torch.arange(rowptr.numel() - 1, device="cuda:0"), torch.diff(rowptr))
+    u = torch.tensor(p.u, device=d)
+    x = s["nodes"].clone().requires_grad_(True)
+    a = s["a"].clone().requires_grad_(True)
+    b = s["b"].clone().requires_grad_(True)
+    fwd = forward_rate(p, s, steps, warmup)
+
+    def step(ev=None):
+        x.grad = a.grad = b.grad = None
+        if ev:
+            ev[0].record()
+        K, M, L = fem.assemble_quadratic(s["mesh"], p.kind, x, a, b, u)
+        if ev:
+            ev[1].record()
+        L.backward()
+        if ev:
+            ev[2].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    f_ms = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    b_ms = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    fb_ms = float(np.median([e[0].elapsed_time(e[2]) for e in evs]))
+    s["mesh"].status()
+
+    rows = torch.repeat_interleave(torch.arange(rowptr.numel() - 1, device=d), torch.diff(rowptr))
     w = u[rows] * u[colind.long()]
     del rows
     gn = torch.empty_like(s["nodes"])
-    ga = torch.empty(p.T, dtype=torch.float64, device="cuda:0")
+    ga = torch.empty(p.T, dtype=torch.float64, device=d)
     gb = torch.empty_like(ga)
     from paper_1409_4618_amd import _ptr, _stream_ptr, check, lib, kind_code
     kc = kind_code(p.kind)
 
-    def bwd():
+    def bwd_kernels():
         check(lib().fem_assemble_backward_quadratic(s["mesh"].handle, kc, _ptr(s["nodes"]), _ptr(s["a"]),
                                                     _ptr(s["b"]), _ptr(u), _ptr(ga), _ptr(gb), _ptr(gn),
                                                     _stream_ptr()), "fem_assemble_backward_quadratic")
@@ -175,20 +243,21 @@ def fwd_bwd_rate(p, steps, warmup):
                                           _ptr(w), _ptr(w), _ptr(ga), _ptr(gb), _ptr(gn), _stream_ptr()),
               "fem_assemble_backward")
 
-    fwd = forward_rate(p, s, steps, warmup)
-    ms_b = timed(bwd, steps, warmup)
+    ms_bk = timed(bwd_kernels, steps, warmup)
     ms_bg = timed(bwd_general, steps, warmup)
     s["mesh"].status()
-    out = dict(workload=f"kuhn96_ned3d: {p.T} tets, L = u^T(K(a)+M(b))u, grads wrt a, b, nodes "
-                        "(adjoint of the quadratic form; bwd_general_ms: the adjoint with materialised "
-                        "weights gK = gM = u_row u_col)",
-               fwd_ms=fwd["ms"], bwd_ms=ms_b, bwd_general_ms=ms_bg, fwd_mtets=fwd["mtets"],
-               fwd_bwd_mtets=p.T / ((fwd["ms"] + ms_b) * 1e-3) / 1e6)
-    out["fwd_bwd_over_fwd"] = out["fwd_bwd_mtets"] / out["fwd_mtets"]
+    out = dict(workload=f"kuhn96_ned3d: {p.T} tets, L = u^T(K(a)+M(b))u through torch.autograd: "
+                        "K, M, L = fem.assemble_quadratic(...), L.backward() (grads wrt a, b, nodes); "
+                        "bwd_kernel_ms: the adjoint kernels alone; bwd_general_ms: the adjoint with "
+                        "materialised weights gK = gM = u_row u_col",
+               fwd_ms=f_ms, bwd_ms=b_ms, fwd_bwd_ms=fb_ms, fwd_bwd_wall_ms=wall_ms,
+               plain_fwd_ms=fwd["ms"], bwd_kernel_ms=ms_bk, bwd_general_ms=ms_bg,
+               plain_fwd_mtets=fwd["mtets"], fwd_bwd_mtets=p.T / (fb_ms * 1e-3) / 1e6)
+    out["fwd_bwd_over_fwd"] = out["fwd_bwd_mtets"] / out["plain_fwd_mtets"]
     nb = adjoint_bytes(p.T, int(p.nodes.shape[0]), p.dim, int(rowptr.numel() - 1))
     out["bwd_bytes"] = nb
-    out["bwd_achieved_gbs"] = nb / (ms_b * 1e-3) / 1e9
-    out["bwd_frac"] = out["bwd_achieved_gbs"] / PEAK_HBM_GBS
+    out["bwd_kernel_gbs"] = nb / (ms_bk * 1e-3) / 1e9
+    out["bwd_kernel_frac"] = out["bwd_kernel_gbs"] / PEAK_HBM_GBS
     return out
 
 
@@ -257,9 +326,43 @@ def batched_rate(steps, warmup, ref_mtets, scale=1.0):
                 frac=bytes_total / (ms_graph * 1e-3) / 1e9 / PEAK_HBM_GBS)
 
 
-def cpu_baseline(p, target_seconds=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_chunk(args):
+    """Worker of the all-cores baseline: the oracle's numeric phase on one
+    contiguous chunk of elements, repeated for about ``seconds``; returns
+    (elements done, start, end) in wall-clock seconds."""
+    nodes, elems, kind, a, b, seconds = args
+    from threadpoolctl import threadpool_limits
+    import oracle
+    topo = oracle.build_topology(elems, nodes.shape[0])
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        done = 0
+        while True:
+            oracle.assemble(nodes, elems, kind, a=a, b=b, topo=topo)
+            done += elems.shape[0]
+            if time.time() - t0 >= seconds:
+                break
+        return done, t0, time.time()
+
+
+def cpu_baseline(p, target_seconds=12.0, workers=None):
     """The oracle (numeric phase: quadrature local matrices + CSR accumulation,
-    topology given) on the first elements of the same mesh, one thread."""
+    topology given) on a bounded sample of the same mesh: one thread on the
+    first 100k tets, and all host cores (at most 16 worker processes, each on
+    its own 100k-tet chunk) at once."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     import oracle
     from threadpoolctl import threadpool_limits
     n = 100000
@@ -274,9 +377,26 @@ def cpu_baseline(p, target_seconds=12.0):
         for _ in range(reps):
             oracle.assemble(p.nodes, elems, p.kind, a=p.a[:n], b=p.b[:n], topo=topo)
         dt = (time.perf_counter() - t0) / reps
-    return {"value": n / dt / 1e6, "unit": "M tets/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} tets of the same 64^3 mesh, numeric phase (quadrature local "
-                      f"matrices + CSR accumulation, topology given), {reps} reps, 1 thread"}
+    single = n / dt / 1e6
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nw = workers or max(1, min(16, avail))
+    jobs = []
+    for w in range(nw):
+        lo = (w * n) % max(1, p.T - n)
+        e = p.elems[lo:lo + n]
+        jobs.append((p.nodes, e, p.kind, p.a[lo:lo + n], p.b[lo:lo + n], target_seconds))
+    with cf.ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_chunk, jobs))
+    total = sum(r[0] for r in res)
+    span = max(r[2] for r in res) - min(r[1] for r in res)
+    return {"value": total / span / 1e6, "unit": "M tets/s", "cores": nw, "kind": "oracle",
+            "sample": f"{nw} worker processes (one thread each), each repeating the numeric phase "
+                      f"(quadrature local matrices + CSR accumulation, topology given) on its own "
+                      f"{n}-tet chunk of the same 64^3 mesh for about {target_seconds:.0f} s; "
+                      f"rate = all elements done / wall time from the first start to the last end",
+            "single_thread": {"value": single, "cores": 1,
+                              "sample": f"first {n} tets of the same mesh, {reps} reps, 1 thread"},
+            "cpu_count": os.cpu_count(), "cpus_available": avail, "cpu_model": cpu_model()}
 
 
 def calib_copy():
@@ -374,28 +494,36 @@ def main():
     log("bench: building kuhn64_ned3d")
     p64 = mg.kuhn64_ned()
     s64 = setup_mesh(p64)
-    log("bench: timing forward 64^3")
+    flush = Flush()
+    log("bench: timing forward 64^3 (cold: cache flushed before each step)")
+    c64 = cold_forward(p64, s64, args.steps, args.warmup, flush)
+    log("bench: timing forward 64^3 (warm: back-to-back launches)")
     f64 = forward_rate(p64, s64, args.steps, args.warmup)
     result = {
         "metric": METRIC,
-        "value": round(f64["mtets"], 3),
+        "value": round(c64["mtets"], 3),
         "unit": "M tets/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(f64["ms"], 6),
+        "ms_per_step": round(c64["ms"], 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "kuhn64_ned3d: 3D Nedelec K+M CSR assembly, Kuhn 64^3 unit cube "
-                               "(1,572,864 tets), interior nodes +-0.2h, a,b ~ lognormal(0,0.5), seed 2",
+                               "(1,572,864 tets), interior nodes +-0.2h, a,b ~ lognormal(0,0.5), seed 2; "
+                               "last-level cache flushed (1 GiB read) before each timed launch, median",
                    "elements": p64.T, "nodes": int(p64.nodes.shape[0]), "nnz": s64["nnz"],
                    "rows": s64["n_rows"]},
-        "roofline": {"bound": "hbm", "achieved": round(f64["gbs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(f64["frac"], 4), "traffic": profiled_traffic(),
-                     "kernel": "fem::k_forward_ema<2, 256>", "bytes_per_launch": f64["bytes"]},
+        "roofline": {"bound": "hbm", "achieved": round(c64["gbs"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(c64["frac"], 4), "traffic": profiled_traffic(),
+                     "kernel": "fem::k_forward_ema<2, 256>", "bytes_per_launch": c64["bytes"]},
+        "warm": {"ms": round(f64["ms"], 6), "mtets": round(f64["mtets"], 3),
+                 "achieved_gbs": round(f64["gbs"], 1), "frac": round(f64["frac"], 4),
+                 "note": "back-to-back launches (inputs partly held in the 256 MB last-level cache)"},
+        "cold_spread_ms": [round(c64["ms_min"], 6), round(c64["ms_max"], 6)],
     }
     if args.calib_copy:
         result["calib_copy_bytes"] = calib_copy()
@@ -404,8 +532,7 @@ def main():
         return
     log("bench: streaming ceilings")
     result["stream_ceiling"] = stream_ceiling(f64["ms"], result["roofline"]["traffic"])
-    result["cold_ms"] = round(cold_rate(p64, s64), 6)
-    result["cold_end_to_end_s"] = {"topology": round(s64["t_topology"], 4), "pattern": round(s64["t_pattern"], 4)}
+    result["one_time_s"] = {"topology": round(s64["t_topology"], 4), "pattern": round(s64["t_pattern"], 4)}
     del s64
     torch.cuda.empty_cache()
 
@@ -413,9 +540,15 @@ def main():
     p128 = mg.kuhn128_ned()
     s128 = setup_mesh(p128)
     f128 = forward_rate(p128, s128, args.steps, args.warmup)
+    c128 = cold_forward(p128, s128, args.steps, args.warmup, flush)
     result["target_128"] = {"workload": "kuhn128_ned3d: 12,582,912 tets, +-0.15h, lognormal a,b, seed 1",
                             "ms": round(f128["ms"], 6), "mtets": round(f128["mtets"], 3),
                             "achieved_gbs": round(f128["gbs"], 1), "frac": round(f128["frac"], 4),
+                            "cold_ms": round(c128["ms"], 6), "cold_frac": round(c128["frac"], 4),
+                            "roofline": {"bound": "hbm", "achieved": round(f128["gbs"], 1), "peak": PEAK_HBM_GBS,
+                                         "unit": "GB/s", "frac": round(f128["frac"], 4),
+                                         "traffic": profiled_traffic(PROFILE_128),
+                                         "kernel": "fem::k_forward_ema<2, 256>", "bytes_per_launch": f128["bytes"]},
                             "topology_s": round(s128["t_topology"], 4), "pattern_s": round(s128["t_pattern"], 4)}
     del s128
     torch.cuda.empty_cache()

@@ -166,6 +166,37 @@ fem_status fem_assemble_backward_quadratic(fem_mesh mesh, fem_kind kind, const d
                                            const double* a, const double* b, const double* u,
                                            double* ga, double* gb, double* gnodes, void* stream);
 
+/* Value of the quadratic form L = u^T (K(a) + M(b)) u (the energy of a dof
+ * vector u for the matrices of Section 2.4), without assembling K and M: L is
+ * linear in the coefficients, so L = sum_K (a_K dL/da_K + b_K dL/db_K), and
+ * each element's dL/da_K, dL/db_K are the sums of squares of
+ * fem_assemble_backward_quadratic. Not part of the paper (it is the forward
+ * value of that adjoint). Deterministic: one partial per workgroup of 256
+ * elements, each summed in a fixed tree order, then the partials in a fixed
+ * order. Asynchronous on `stream`.
+ *   u      dev f64 [n_rows of fem_pattern(kind)] (edge or face values)
+ *   L      dev f64 [1] output
+ * Uses library-owned scratch inside the handle (ceil(n_elems / 256) doubles,
+ * allocated on the first call). FEM_EINVAL if nodes, u or L is NULL;
+ * FEM_ENOTREADY if fem_pattern(kind) has not been called.                  */
+fem_status fem_quadratic_value(fem_mesh mesh, fem_kind kind, const double* nodes,
+                               const double* a, const double* b, const double* u,
+                               double* L, void* stream);
+
+/* Sparse product on an assembled pattern: y = alpha A x + beta B x, where A and
+ * B are value arrays on the same CSR pattern (for example K and M of
+ * fem_assemble; B may be NULL, then y = alpha A x). Not part of the paper: the
+ * operator of the linear systems its Section 4 examples solve, and the
+ * derivative 2 (K + M) u of the quadratic form with respect to u.
+ *   rowptr dev i64 [n_rows+1], colind dev i32 [nnz], A, B dev f64 [nnz]
+ *   x      dev f64 [n_cols] (n_cols = n_rows for the patterns of fem_pattern)
+ *   y      dev f64 [n_rows] output, overwritten; must not alias x
+ * Every row is summed in a fixed order (deterministic). Asynchronous.
+ * FEM_EINVAL for a NULL argument (n_rows > 0) or x == y.                    */
+fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* colind,
+                          const double* A, const double* B, double alpha, double beta,
+                          const double* x, double* y, void* stream);
+
 /* Synchronises the last stream used with `mesh`, returns and clears the
  * asynchronous device error word (FEM_OK, FEM_EDEGENERATE or FEM_ENONFINITE). */
 fem_status fem_status_query(fem_mesh mesh);

@@ -6,8 +6,10 @@ current HIP stream and the autograd hook.
 
     import paper_1409_4618_amd as fem
     mesh = fem.Mesh(nodes, elems)              # topology on the GPU
-    K, M = fem.assemble(mesh, "ned", nodes, a, b)
+    K, M = fem.assemble(mesh, "ned", nodes, a, b)   # differentiable in nodes, a, b
     rowptr, colind = mesh.pattern("ned")
+    K, M, L = fem.assemble_quadratic(mesh, "ned", nodes, a, b, u)
+    L.backward()                               # the quadratic adjoint
 """
 from __future__ import annotations
 
@@ -17,7 +19,7 @@ from typing import Optional, Sequence
 from ._lib import (FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
 __all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
-           "kind_code", "NED", "RT"]
+           "kind_code", "NED", "RT", "quadratic_value", "quadratic_form", "assemble_quadratic", "csr_matvec"]
 
 NED = "ned"
 RT = "rt"
@@ -141,6 +143,15 @@ class Mesh:
             self._patterns[kc] = (n.value, nnz.value, rp.value, ci.value)
         return self._patterns[kc][:2]
 
+    def pattern_device(self, kind):
+        """(rowptr, colind) device tensors of ``kind``'s pattern (copies, cached on
+        the mesh object)."""
+        kc = kind_code(kind)
+        cache = self.__dict__.setdefault("_pattern_dev", {})
+        if kc not in cache:
+            cache[kc] = self.pattern(kind)
+        return cache[kc]
+
     def pattern(self, kind):
         """Copies of (rowptr int64 [n_rows+1], colind int32 [nnz]) as device tensors."""
         torch = _torch()
@@ -171,8 +182,7 @@ def assemble_into(mesh: Mesh, kind, nodes, a, b, K, M):
                              _ptr(M), _stream_ptr()), "fem_assemble")
 
 
-def assemble(mesh: Mesh, kind, nodes, a=None, b=None):
-    """Values (K, M) of K(a), M(b) on ``mesh.pattern(kind)``: f64 device tensors [nnz]."""
+def _assemble_values(mesh: Mesh, kind, nodes, a=None, b=None):
     torch = _torch()
     _, nnz = mesh.pattern_info(kind)
     _check_inputs(mesh, nodes, a, b)
@@ -180,6 +190,51 @@ def assemble(mesh: Mesh, kind, nodes, a=None, b=None):
     M = torch.empty(nnz, dtype=torch.float64, device=nodes.device)
     assemble_into(mesh, kind, nodes, a, b, K, M)
     return K, M
+
+
+def _needs_grad(*ts):
+    torch = _torch()
+    return torch.is_grad_enabled() and any(t is not None and t.requires_grad for t in ts)
+
+
+def assemble(mesh: Mesh, kind, nodes, a=None, b=None):
+    """Values (K, M) of K(a), M(b) on ``mesh.pattern(kind)``: f64 device tensors [nnz].
+
+    Differentiable: when nodes, a or b require grad, the values come from the
+    autograd Function FemAssemble, whose backward is fem_assemble_backward."""
+    if _needs_grad(nodes, a, b):
+        return FemAssemble().apply(nodes, a, b, mesh, kind)
+    return _assemble_values(mesh, kind, nodes, a, b)
+
+
+def quadratic_value(mesh: Mesh, kind, nodes, a, b, u):
+    """L = u^T (K(a) + M(b)) u as a 0-dim device tensor (fem_quadratic_value; no
+    gradient)."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(kind)
+    _check_inputs(mesh, nodes, a, b)
+    _check_dev(u, torch.float64, "u", (n_rows,))
+    L = torch.empty((), dtype=torch.float64, device=nodes.device)
+    check(lib().fem_quadratic_value(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b), _ptr(u),
+                                    _ptr(L), _stream_ptr()), "fem_quadratic_value")
+    return L
+
+
+def csr_matvec(rowptr, colind, A, x, B=None, alpha=1.0, beta=1.0, out=None):
+    """y = alpha A x + beta B x on a CSR pattern (fem_csr_matvec)."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    nnz = colind.numel()
+    _check_dev(rowptr, torch.int64, "rowptr")
+    _check_dev(colind, torch.int32, "colind")
+    _check_dev(A, torch.float64, "A", (nnz,))
+    _check_dev(B, torch.float64, "B", (nnz,))
+    _check_dev(x, torch.float64, "x")
+    y = torch.empty(n, dtype=torch.float64, device=A.device) if out is None else out
+    _check_dev(y, torch.float64, "y", (n,))
+    check(lib().fem_csr_matvec(n, _ptr(rowptr), _ptr(colind), _ptr(A), _ptr(B), float(alpha), float(beta),
+                               _ptr(x), _ptr(y), _stream_ptr()), "fem_csr_matvec")
+    return y
 
 
 def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b=True,
@@ -226,7 +281,7 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, nodes, a, b, mesh, kind):
-            K, M = assemble(mesh, kind, nodes, a, b)
+            K, M = _assemble_values(mesh, kind, nodes, a, b)
             ctx.mesh = mesh
             ctx.kind = kind
             ctx.save_for_backward(nodes, a, b)
@@ -250,7 +305,76 @@ def _autograd_function():
     return FemAssemble
 
 
+def _quadratic_backward(ctx, gL):
+    """Gradients of L = u^T (K(a) + M(b)) u, scaled by the upstream gL: the
+    quadratic adjoint for nodes, a and b, and 2 (K + M) u for u (K and M from
+    the forward when it kept them, else assembled here)."""
+    nodes, a, b, u = ctx.saved_tensors[:4]
+    mesh, kind = ctx.mesh, ctx.kind
+    need_x, need_a, need_b, need_u = ctx.needs_input_grad[:4]
+    gn = ga = gb = gu = None
+    if need_x or need_a or need_b:
+        gn, ga, gb = assemble_backward_quadratic(mesh, kind, nodes, a, b, u, need_a=need_a, need_b=need_b,
+                                                 need_nodes=need_x)
+    if need_u:
+        if len(ctx.saved_tensors) > 4:
+            K, M = ctx.saved_tensors[4:6]
+        else:
+            K, M = _assemble_values(mesh, kind, nodes, a, b)
+        rowptr, colind = mesh.pattern_device(kind)
+        gu = csr_matvec(rowptr, colind, K, u, B=M, alpha=2.0, beta=2.0)
+    # chain rule: the adjoint kernels compute dL/d(.); the upstream factor
+    # (1 for L.backward()) multiplies them
+    gn, ga, gb, gu = (None if g is None else g.mul_(gL) for g in (gn, ga, gb, gu))
+    return gn, ga, gb, gu
+
+
+def _quadratic_functions():
+    torch = _torch()
+
+    class FemQuadratic(torch.autograd.Function):
+        """(nodes, a, b, u) -> L = u^T (K(a) + M(b)) u (fem_quadratic_value),
+        backward by the quadratic adjoint (fem_assemble_backward_quadratic)."""
+
+        @staticmethod
+        def forward(ctx, nodes, a, b, u, mesh, kind):
+            L = quadratic_value(mesh, kind, nodes, a, b, u)
+            ctx.mesh = mesh
+            ctx.kind = kind
+            ctx.save_for_backward(nodes, a, b, u)
+            return L
+
+        @staticmethod
+        def backward(ctx, gL):
+            return (*_quadratic_backward(ctx, gL), None, None)
+
+    class FemAssembleQuadratic(torch.autograd.Function):
+        """(nodes, a, b, u) -> (K values, M values, L): the assembled matrices
+        (fem_assemble; returned for the caller, not differentiated) and the
+        differentiable quadratic form L = u^T (K(a) + M(b)) u."""
+
+        @staticmethod
+        def forward(ctx, nodes, a, b, u, mesh, kind):
+            K, M = _assemble_values(mesh, kind, nodes, a, b)
+            L = quadratic_value(mesh, kind, nodes, a, b, u)
+            ctx.mesh = mesh
+            ctx.kind = kind
+            ctx.mark_non_differentiable(K, M)
+            if ctx.needs_input_grad[3]:
+                ctx.save_for_backward(nodes, a, b, u, K, M)
+            else:
+                ctx.save_for_backward(nodes, a, b, u)
+            return K, M, L
+
+        @staticmethod
+        def backward(ctx, gK, gM, gL):
+            return (*_quadratic_backward(ctx, gL), None, None)
+
+    return FemQuadratic, FemAssembleQuadratic
+
+
 _FA = None
+_FQ = None
 
 
 def FemAssemble():
@@ -260,9 +384,28 @@ def FemAssemble():
     return _FA
 
 
+def _fq():
+    global _FQ
+    if _FQ is None:
+        _FQ = _quadratic_functions()
+    return _FQ
+
+
 def assemble_autograd(mesh: Mesh, kind, nodes, a, b):
     """Differentiable (K, M) values with respect to nodes, a and b."""
     return FemAssemble().apply(nodes, a, b, mesh, kind)
+
+
+def quadratic_form(mesh: Mesh, kind, nodes, a, b, u):
+    """Differentiable L = u^T (K(a) + M(b)) u (0-dim tensor) with respect to
+    nodes, a, b and u, without assembling K and M in the forward."""
+    return _fq()[0].apply(nodes, a, b, u, mesh, kind)
+
+
+def assemble_quadratic(mesh: Mesh, kind, nodes, a, b, u):
+    """(K, M, L): the assembled values of K(a), M(b) and the differentiable
+    L = u^T (K(a) + M(b)) u, whose backward is the quadratic adjoint."""
+    return _fq()[1].apply(nodes, a, b, u, mesh, kind)
 
 
 class Batch:

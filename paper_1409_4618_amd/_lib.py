@@ -33,6 +33,10 @@ SIGNATURES = [
     ("fem_assemble", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6),
     ("fem_assemble_backward", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 9),
     ("fem_assemble_backward_quadratic", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 8),
+    ("fem_quadratic_value", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6),
+    ("fem_csr_matvec", ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     ("fem_status_query", ctypes.c_int, [ctypes.c_void_p]),
     ("fem_mesh_destroy", None, [ctypes.c_void_p]),
     ("fem_batch_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, c_void_pp]),

@@ -112,7 +112,7 @@ __device__ __forceinline__ void store_vertex2(double* sh, int v, double dx, doub
 // and the vertex derivatives from dPhi (through the edge vectors), dPsi (through
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
 template <int MODE>
-__device__ void bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+__device__ double2 bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -262,8 +262,9 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double
     const double rJ = 1.0 / J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
     const double ca = A.a ? A.a[e] : 1.0;
     const double cb = A.b ? A.b[e] : 1.0;
-    if (A.ga) A.ga[e] = (2.0 / 3.0) * Phi * arJ;
-    if (A.gb) A.gb[e] = (1.0 / 120.0) * Psi * arJ;
+    const double2 gab = make_double2((2.0 / 3.0) * Phi * arJ, (1.0 / 120.0) * Psi * arJ);
+    if (A.ga) A.ga[e] = gab.x;
+    if (A.gb) A.gb[e] = gab.y;
     if (A.partials) {
         const V3 w1 = sub(w[1], w[0]), w2 = sub(w[2], w[0]), w3 = sub(w[3], w[0]);
         const V3 dPsi[3] = {add(cross(w2, b3), cross(b2, w3)), add(cross(b3, w1), cross(w3, b1)),
@@ -282,11 +283,12 @@ __device__ void bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double
         store_vertex3(sh, 0, d0);
     }
     if (!(aJ > 0.0) || !isfinite(J)) atomicOr(A.err_word, ERR_DEGENERATE);
+    return gab;
 }
 
 // 3D Raviart-Thomas
 template <int MODE>
-__device__ void bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+__device__ double2 bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -352,8 +354,9 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double*
     const double ca = A.a ? A.a[e] : 1.0;
     const double cb = A.b ? A.b[e] : 1.0;
     const double rJ = 1.0 / g.J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
-    if (A.ga) A.ga[e] = 1.5 * hK * arJ;
-    if (A.gb) A.gb[e] = (1.0 / 120.0) * Omega * arJ;
+    const double2 gab = make_double2(1.5 * hK * arJ, (1.0 / 120.0) * Omega * arJ);
+    if (A.ga) A.ga[e] = gab.x;
+    if (A.gb) A.gb[e] = gab.y;
     if (A.partials) {
         const V3 S = add(add(g.y[1], g.y[2]), g.y[3]);
         V3 rp = {0.0, 0.0, 0.0};
@@ -378,11 +381,12 @@ __device__ void bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double*
         store_vertex3(sh, 0, d0);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+    return gab;
 }
 
 // 2D (both kinds)
 template <int MODE>
-__device__ void bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+__device__ double2 bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
     int gid[3];
     V2 x[3];
 #pragma unroll
@@ -481,8 +485,9 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double*
     const double ca = A.a ? A.a[e] : 1.0;
     const double cb = A.b ? A.b[e] : 1.0;
     const double rJ = 1.0 / g.J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
-    if (A.ga) A.ga[e] = 2.0 * hK * arJ;
-    if (A.gb) A.gb[e] = (1.0 / 24.0) * Psi * arJ;
+    const double2 gab = make_double2(2.0 * hK * arJ, (1.0 / 24.0) * Psi * arJ);
+    if (A.ga) A.ga[e] = gab.x;
+    if (A.gb) A.gb[e] = gab.y;
     if (A.partials) {
         const V2 w1 = {w[1].x - w[0].x, w[1].y - w[0].y};
         const V2 w2 = {w[2].x - w[0].x, w[2].y - w[0].y};
@@ -503,6 +508,7 @@ __device__ void bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double*
         store_vertex2(sh, 0, d0x, d0y);
     }
     if (!(aJ > 0.0) || !isfinite(g.J)) atomicOr(A.err_word, ERR_DEGENERATE);
+    return gab;
 }
 
 template <int KC, int MODE>
@@ -594,6 +600,80 @@ __global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, co
     }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) gnodes[v * DIM + c] = acc[c];
+}
+
+// Value of the quadratic form L = u^T (K(a) + M(b)) u. It is linear in the
+// coefficients, so L = sum_e (a_e dL/da_e + b_e dL/db_e), with dL/da_e, dL/db_e
+// the element sums of squares of the adjoint (no assembled matrix is read).
+// Each workgroup adds its elements' terms in a fixed tree order into one
+// partial; k_sum_partials then adds the partials in a fixed order, so the value
+// is deterministic.
+template <int KC>
+__global__ __launch_bounds__(BWD_BLOCK) void k_quadratic_value(const BwdArgs A, double* partials) {
+    __shared__ double red[BWD_BLOCK];
+    const int64_t e = (int64_t)blockIdx.x * BWD_BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (e < A.T) {
+        const SlotView sv{nullptr, nullptr};
+        double2 g;
+        if constexpr (KC == 2) g = bwd_ned3<BWD_QUADRATIC>(A, e, sv, nullptr);
+        else if constexpr (KC == 1) g = bwd_rt3<BWD_QUADRATIC>(A, e, sv, nullptr);
+        else g = bwd_tri<BWD_QUADRATIC>(A, e, sv, nullptr);
+        const double ca = A.a ? A.a[e] : 1.0;
+        const double cb = A.b ? A.b[e] : 1.0;
+        v = ca * g.x + cb * g.y;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = BWD_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// out[0] = sum of n partials: lane t adds t, t + 256, ... in order, then a
+// fixed tree over the lanes (one workgroup of 256).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* partials, int64_t n, double* out) {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += partials[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+int64_t quadratic_value_partials(int64_t n_elems) { return (n_elems + BWD_BLOCK - 1) / BWD_BLOCK; }
+
+fem_status launch_quadratic_value(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
+                                  const double* a, const double* b, const double* u, double* out,
+                                  double* partials, hipStream_t s) {
+    const int kc = kind_code(m->dim, kind);
+    BwdArgs A = {};
+    A.u = u;
+    A.elems2dofs = ds.elems2dofs;
+    A.elems = m->elems;
+    A.nodes = nodes;
+    A.a = a;
+    A.b = b;
+    A.T = m->T;
+    A.err_word = m->err_word;
+    const int64_t nb = quadratic_value_partials(m->T);
+    if (nb > 0) {
+        if (kc == 2) hipLaunchKernelGGL(k_quadratic_value<2>, dim3((unsigned)nb), dim3(BWD_BLOCK), 0, s, A, partials);
+        else if (kc == 1) hipLaunchKernelGGL(k_quadratic_value<1>, dim3((unsigned)nb), dim3(BWD_BLOCK), 0, s, A, partials);
+        else hipLaunchKernelGGL(k_quadratic_value<0>, dim3((unsigned)nb), dim3(BWD_BLOCK), 0, s, A, partials);
+        FEM_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nb, out);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
 }
 
 __global__ void k_fill_f64(double* p, int64_t n, double v) {

@@ -243,6 +243,20 @@ fem_status fem_assemble_backward_quadratic(fem_mesh m, fem_kind kind, const doub
     return launch_backward(m, ds, kind, nodes, a, b, nullptr, nullptr, u, ga, gb, gnodes, s);
 }
 
+fem_status fem_quadratic_value(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
+                               const double* b, const double* u, double* L, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_quadratic_value: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS)
+        return fail(FEM_EINVAL, "fem_quadratic_value: bad kind");
+    if (!nodes || !u || !L) return fail(FEM_EINVAL, "fem_quadratic_value: nodes, u or L is NULL");
+    DofSet& ds = dofset(m, kind);
+    if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+    if (!m->qv_partials) FEM_HIP(dmalloc(m, &m->qv_partials, std::max<int64_t>(1, quadratic_value_partials(m->T))));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    return launch_quadratic_value(m, ds, kind, nodes, a, b, u, L, m->qv_partials, s);
+}
+
 fem_status fem_status_query(fem_mesh m) {
     if (!m) return fail(FEM_EINVAL, "fem_status_query: mesh is NULL");
     int err = 0;
@@ -368,15 +382,26 @@ static fem_status build_work(fem_batch B) {
     return FEM_OK;
 }
 
+// What the tuned configuration depends on: per mesh its element count,
+// dimension and kind, its row count and nonzeros (the row structure), and
+// whether element-major tiles are usable for the whole batch, with their rows
+// per tile and LDS size. Batches that differ in any of these get their own
+// cache entries.
 static std::string batch_signature(fem_batch B) {
     std::ostringstream os;
     uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t x) {
+        h ^= x;
+        h *= 1099511628211ull;
+    };
+    mix(B->ema_ok ? 1u : 0u);
     for (size_t i = 0; i < B->meshes.size(); ++i) {
-        const uint64_t v[3] = {(uint64_t)B->meshes[i]->T, (uint64_t)B->meshes[i]->dim, (uint64_t)B->kinds[i]};
-        for (uint64_t x : v) {
-            h ^= x;
-            h *= 1099511628211ull;
-        }
+        DofSet& ds = dofset(B->meshes[i], B->kinds[i]);
+        const Pattern::Ema& em = ds.pat.ema[ema_index(256)];
+        const uint64_t v[8] = {(uint64_t)B->meshes[i]->T, (uint64_t)B->meshes[i]->dim, (uint64_t)B->kinds[i],
+                               (uint64_t)ds.pat.n_rows, (uint64_t)ds.pat.nnz, (uint64_t)em.R,
+                               (uint64_t)em.pmax, (uint64_t)B->meshes[i]->nonconforming};
+        for (uint64_t x : v) mix(x);
     }
     os << B->meshes.size() << "-" << std::hex << h;
     return os.str();
@@ -536,7 +561,12 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     const std::string dev = device_name();
     const std::string sig = batch_signature(B);
     int R = 0, sc = 0;
-    if (cache_lookup(cache_path, dev, sig, &R, &sc)) return fem_batch_set_config(B, R, sc);
+    // A cached configuration that this batch cannot use (element-major tiles
+    // unavailable, a tile too large for LDS) is ignored: the search below runs.
+    if (cache_lookup(cache_path, dev, sig, &R, &sc) && (R != 0 || B->ema_ok) &&
+        fem_batch_set_config(B, R, sc) == FEM_OK)
+        return FEM_OK;
+    g_last_error.clear();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     struct Events {  // destroyed on every return path
         hipEvent_t e0 = nullptr, e1 = nullptr;

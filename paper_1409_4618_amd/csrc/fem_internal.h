@@ -95,6 +95,7 @@ struct DofSet {
     // of its row's first entry and its column-offset record (built on first use)
     int32_t* slot_base = nullptr;  // [T*nloc] (< 2^31: nnz < 2^31 is checked when the pattern is built)
     uint64_t* slot_cp = nullptr;   // [T*nloc]
+    bool slot_map_built = false;   // set once every step of the build has succeeded
 };
 
 }  // namespace fem
@@ -114,12 +115,14 @@ struct fem_mesh_s {
     // adjoint node map (built on first use): (node, workgroup) pairs in node-major
     // order; see build_node_map
     double* elem_partials = nullptr; // [pairs][dim] vertex-derivative partial of each pair
+    double* qv_partials = nullptr;   // [ceil(T / 256)] workgroup sums of the quadratic-form value
     int32_t* node_ptr = nullptr;     // [V+1] pairs of each node (into bwd_npair)
     int32_t* bwd_npair = nullptr;    // [pairs] pair indices by node, ascending workgroup
     int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (pairs are workgroup-major)
     uint16_t* bwd_pst = nullptr;     // [pairs] first incidence of each pair, workgroup-local
     uint16_t* bwd_inc = nullptr;     // [T*(dim+1)+1] workgroup-local incidences, by workgroup, node, element
     int64_t bwd_pairs = 0;
+    bool node_map_built = false;     // set once every step of the build has succeeded
     int* err_word = nullptr;         // device error word
     // Some facet (3D face, 2D edge) has more than two elements, or two elements
     // with the same vertices. Such meshes take the row kernels, which sum every
@@ -223,6 +226,12 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
                            const double* a, const double* b, const double* gK,
                            const double* gM, const double* u, double* ga, double* gb,
                            double* gnodes, hipStream_t s);
+// Value of L = u^T (K(a) + M(b)) u into out[0] (device), through
+// quadratic_value_partials(T) device doubles of scratch.
+int64_t quadratic_value_partials(int64_t n_elems);
+fem_status launch_quadratic_value(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
+                                  const double* a, const double* b, const double* u, double* out,
+                                  double* partials, hipStream_t s);
 fem_status launch_batch(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
                         int rows_per_tile, int schedule, int grid, int pmax,
                         unsigned* counters, hipStream_t s);

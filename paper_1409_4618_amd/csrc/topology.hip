@@ -649,17 +649,48 @@ __global__ void k_slot_map(const int32_t* elems2dofs, const int64_t* rowptr, con
                            : (uint64_t)reinterpret_cast<const uint32_t*>(colpos)[j];
 }
 
+// Arrays of a map that is built on first use. They join the handle, and the
+// map counts as built, only when every step of the build has succeeded; on any
+// failure they are freed and their pointers cleared, so the next call builds
+// the map again instead of using a half-built one.
+struct Staged {
+    fem_mesh m;
+    std::vector<std::pair<void**, void*>> v;
+    bool keep = false;
+    template <class T>
+    hipError_t alloc(T** ptr, int64_t count) {
+        *ptr = nullptr;
+        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void**)ptr, bytes);
+        if (e == hipSuccess) v.push_back({reinterpret_cast<void**>(ptr), (void*)*ptr});
+        return e;
+    }
+    ~Staged() {
+        for (auto& q : v) {
+            if (keep) {
+                m->allocs.push_back(q.second);
+            } else {
+                (void)hipFree(q.second);
+                *q.first = nullptr;
+            }
+        }
+    }
+};
+
 fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
-    if (ds.slot_base) return FEM_OK;
+    if (ds.slot_map_built) return FEM_OK;
+    Staged st{m, {}};
     const int64_t n = m->T * ds.nloc;
-    FEM_HIP(dmalloc(m, &ds.slot_base, n > 0 ? n : 1));
-    FEM_HIP(dmalloc(m, &ds.slot_cp, n > 0 ? n : 1));
+    FEM_HIP(st.alloc(&ds.slot_base, n));
+    FEM_HIP(st.alloc(&ds.slot_cp, n));
     if (n > 0) {
         hipLaunchKernelGGL(k_slot_map, dim3(nblk(n)), dim3(TB), 0, s, ds.elems2dofs, ds.pat.rowptr,
                            ds.pat.slot_rank, ds.pat.colpos, ds.pat.cp_stride, n, ds.slot_base,
                            ds.slot_cp);
         FEM_HIP(hipGetLastError());
     }
+    st.keep = true;
+    ds.slot_map_built = true;
     return FEM_OK;
 }
 
@@ -720,21 +751,24 @@ __global__ void k_inc_wg_pairs(const uint64_t* keys, const uint32_t* scan, int64
 }
 
 fem_status build_node_map(fem_mesh m, hipStream_t s) {
-    if (m->node_ptr) return FEM_OK;
+    if (m->node_map_built) return FEM_OK;
+    Staged st{m, {}};
     const int nv = m->dim + 1;
     const int64_t n = m->T * nv;
     const int64_t n_blocks = (m->T + BWD_BLOCK - 1) / BWD_BLOCK;
     static_assert(BWD_BLOCK * 4 <= 65536, "workgroup-local incidence indices are 16-bit");
-    FEM_HIP(dmalloc(m, &m->node_ptr, m->V + 1));
-    FEM_HIP(dmalloc(m, &m->bwd_bptr, n_blocks + 1));
-    FEM_HIP(dmalloc(m, &m->bwd_inc, (n > 0 ? n : 1) + 1));   // +1: read as 32-bit words
+    FEM_HIP(st.alloc(&m->node_ptr, m->V + 1));
+    FEM_HIP(st.alloc(&m->bwd_bptr, n_blocks + 1));
+    FEM_HIP(st.alloc(&m->bwd_inc, (n > 0 ? n : 1) + 1));   // +1: read as 32-bit words
     FEM_HIP(hipMemsetAsync(m->node_ptr, 0, (m->V + 1) * sizeof(int32_t), s));
     FEM_HIP(hipMemsetAsync(m->bwd_bptr, 0, (n_blocks + 1) * sizeof(int32_t), s));
     FEM_HIP(hipMemsetAsync(m->bwd_inc, 0, ((n > 0 ? n : 1) + 1) * sizeof(uint16_t), s));
     if (n == 0) {
-        FEM_HIP(dmalloc(m, &m->bwd_pst, 1));
-        FEM_HIP(dmalloc(m, &m->bwd_npair, 1));
+        FEM_HIP(st.alloc(&m->bwd_pst, 1));
+        FEM_HIP(st.alloc(&m->bwd_npair, 1));
         m->bwd_pairs = 0;
+        st.keep = true;
+        m->node_map_built = true;
         return FEM_OK;
     }
     TmpBufs tb;
@@ -750,8 +784,8 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
     int64_t P = 0;
     if (fem_status st = read_count(tb.scan, tb.keys, n, s, &P)) return st;
     m->bwd_pairs = P;
-    FEM_HIP(dmalloc(m, &m->bwd_pst, P));
-    FEM_HIP(dmalloc(m, &m->bwd_npair, P));
+    FEM_HIP(st.alloc(&m->bwd_pst, P));
+    FEM_HIP(st.alloc(&m->bwd_npair, P));
     // node keys of the pairs, in the (now free) tmp key/value space after the
     // incidence keys: P <= n entries each
     uint64_t* nkey = tb.keys_tmp;
@@ -766,6 +800,8 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
     FEM_HIP(radix_sort_pairs(nkey, nval, tb.keys, tb.vals, P, bit_length((uint64_t)m->V - 1), s));
     FEM_HIP(hipMemcpyAsync(m->bwd_npair, nval, P * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     FEM_HIP(hipStreamSynchronize(s));
+    st.keep = true;
+    m->node_map_built = true;
     return FEM_OK;
 }
 

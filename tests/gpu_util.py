@@ -42,3 +42,21 @@ def relabel(nodes, elems, seed):
 def csr_rows_of(rowptr, colind, vals, r):
     s, e = int(rowptr[r]), int(rowptr[r + 1])
     return colind[s:e], vals[s:e]
+
+
+def _oracle_csr(args):
+    """Worker: the oracle's full assembly of one mesh (CPU only)."""
+    import oracle
+    nodes, elems, kind, a, b = args
+    csr, _ = oracle.assemble(nodes, elems, kind, a=a, b=b)
+    return csr.rowptr, csr.colind, csr.Kv, csr.Mv
+
+
+def oracle_csr_many(problems, workers=12):
+    """The oracle's full assembly of many meshes, in spawned CPU worker
+    processes (they import numpy and the oracle only, never the GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = [(p.nodes, p.elems, p.kind, p.a, p.b) for p in problems]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_oracle_csr, jobs, chunksize=1))

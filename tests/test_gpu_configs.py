@@ -2,9 +2,12 @@
 
 * topology (edge / face numbering, element maps, sign data): bit-exact against
   the oracle's full numbering;
-* CSR pattern and values: every row of a sample (first and last tiles, random
-  rows) against the oracle's row-wise assembly, pattern bit-exact and values
-  within relative Frobenius 1e-12;
+* CSR pattern and values: the whole matrices against the oracle's full
+  assembly, element by element, for the 2D 32x32 square and Kuhn 64^3 (the
+  oracle takes about half a minute on the latter); for the 96^3 and 128^3
+  meshes every row of a sample (first and last tiles, random rows) against the
+  oracle's row-wise assembly. Pattern bit-exact, values within relative
+  Frobenius 1e-12;
 * size-independent identities on the whole GPU output: nnz formula, bitwise
   symmetry, determinism, K G = 0 (Nedelec) and the constant-field identity
   u^T M(b) u = |c|^2 sum_K b_K |K|.
@@ -25,6 +28,8 @@ CONFIGS = {
     "kuhn128_ned3d": mg.kuhn128_ned,
     "kuhn96_ned3d": mg.kuhn96_ned_grad,
 }
+# configurations compared with the oracle on every value
+FULL = ("square32_ned2d", "kuhn64_ned3d")
 
 
 def sample_rows(n_rows, rng, k=300):
@@ -73,8 +78,22 @@ def test_full_size_config(cfg):
     else:
         assert nnz == F + 12 * T
 
-    # sampled rows against the oracle
     rng = np.random.default_rng(123)
+    if cfg in FULL:
+        # every value against the oracle's full assembly
+        say("    oracle: full assembly")
+        csr, _ = oracle.assemble(p.nodes, p.elems, kind, a=p.a, b=p.b, topo=topo)
+        assert np.array_equal(rowptr.cpu().numpy(), csr.rowptr)
+        assert np.array_equal(colind.cpu().numpy(), csr.colind)
+        for got, ref, nm in ((K, csr.Kv, "K"), (M, csr.Mv, "M")):
+            g = got.cpu().numpy()
+            e_f = rel_fro(g, ref)
+            e_max = np.abs(g - ref).max() / np.abs(ref).max()
+            say(f"    full {nm}: rel Frobenius {e_f:.2e}, max entry error / max entry {e_max:.2e}")
+            assert e_f <= TOL and e_max <= TOL
+        del csr
+
+    # sampled rows against the oracle's row-wise (dictionary) assembly
     rows = sample_rows(N, rng)
     say(f"    oracle rows: {rows.size}")
     ref, _ = oracle.assemble_rows(p.nodes, p.elems, kind, rows, a=p.a, b=p.b, topo=topo)

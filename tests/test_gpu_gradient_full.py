@@ -26,7 +26,7 @@ from oracle.gradient import grad_coefficients, grad_nodes
 
 pytestmark = pytest.mark.gpu
 
-GTOL = 1e-11
+GTOL = 1e-12
 
 
 def test_full_size_adjoint():

@@ -7,7 +7,7 @@ lengths, uneven tile element lists) and badly shaped elements (the smallest
 |det B_K| is a few hundredths of a percent of the median in 3D). The bars are
 the same as on the structured meshes: topology and CSR pattern bit-exact
 against the oracle, values within relative Frobenius 1e-12, bitwise symmetric
-and deterministic; the adjoint of L = u^T (K(a) + M(b)) u within 1e-11 of the
+and deterministic; the adjoint of L = u^T (K(a) + M(b)) u within 1e-12 of the
 oracle's gradient (relative to its largest entry), both entry points; a
 batch of mixed Delaunay meshes bitwise equal to single-mesh launches.
 """
@@ -21,7 +21,7 @@ from test_gpu_parity import check_against_oracle, run_case
 
 pytestmark = pytest.mark.gpu
 
-GTOL = 1e-11
+GTOL = 1e-12
 
 
 def delaunay_mesh(dim, n_points, seed):
