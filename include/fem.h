@@ -183,6 +183,26 @@ fem_status fem_quadratic_value(fem_mesh mesh, fem_kind kind, const double* nodes
                                const double* a, const double* b, const double* u,
                                double* L, void* stream);
 
+/* Allocation-free variant of fem_quadratic_value, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, kernels and result
+ * (bitwise) as fem_quadratic_value; it calls no hipMalloc, hipFree or other
+ * allocating routine. Its workgroup partials live in a fixed device array
+ * inside the library (4 MiB, one copy on each GPU the library runs on, held
+ * until the process ends), whose device address is looked up once per device
+ * on the first call there.
+ *   limit  n_elems <= 2^27 (134,217,728); larger meshes get FEM_EOVERFLOW
+ *          (fem_quadratic_value has no such limit)
+ *   device the mesh's device must be the current device (else FEM_EINVAL)
+ * Every call on one GPU shares that array: calls that overlap on one GPU (on
+ * different streams, or from different threads without ordering) race and
+ * give wrong values. Order them on one stream or synchronise between them.
+ * Asynchronous on `stream`. FEM_EINVAL if nodes, u or L is NULL;
+ * FEM_ENOTREADY if fem_pattern(kind) has not been called.                  */
+fem_status fem_quadratic_value_noalloc(fem_mesh mesh, fem_kind kind, const double* nodes,
+                                       const double* a, const double* b, const double* u,
+                                       double* L, void* stream);
+
 /* Sparse product on an assembled pattern: y = alpha A x + beta B x, where A and
  * B are value arrays on the same CSR pattern (for example K and M of
  * fem_assemble; B may be NULL, then y = alpha A x). Not part of the paper: the

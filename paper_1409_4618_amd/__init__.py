@@ -19,7 +19,7 @@ from typing import Optional, Sequence
 from ._lib import (FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
 __all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
-           "kind_code", "NED", "RT", "quadratic_value", "quadratic_form", "assemble_quadratic", "csr_matvec"]
+           "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_form", "assemble_quadratic", "csr_matvec"]
 
 NED = "ned"
 RT = "rt"
@@ -218,6 +218,20 @@ def quadratic_value(mesh: Mesh, kind, nodes, a, b, u):
     check(lib().fem_quadratic_value(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b), _ptr(u),
                                     _ptr(L), _stream_ptr()), "fem_quadratic_value")
     return L
+
+
+def quadratic_value_noalloc(mesh: Mesh, kind, nodes, a, b, u, out):
+    """L = u^T (K(a) + M(b)) u into the caller's 0-dim device tensor ``out``
+    (fem_quadratic_value_noalloc: no device allocation by the library or here;
+    meshes of at most 2^27 elements; calls overlapping on one GPU race)."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(kind)
+    _check_inputs(mesh, nodes, a, b)
+    _check_dev(u, torch.float64, "u", (n_rows,))
+    _check_dev(out, torch.float64, "out", ())
+    check(lib().fem_quadratic_value_noalloc(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b),
+                                            _ptr(u), _ptr(out), _stream_ptr()), "fem_quadratic_value_noalloc")
+    return out
 
 
 def csr_matvec(rowptr, colind, A, x, B=None, alpha=1.0, beta=1.0, out=None):
