@@ -31,9 +31,8 @@ from functools import lru_cache
 
 import numpy as np
 
-from . import reference as ref
-from .assembly import assemble, element_dofs, element_signs
-from .integrate import DEFAULT_M, affine_transformations
+from .assembly import assemble
+from .integrate import DEFAULT_M, hcurl_error_ned, load_vector_ned
 
 
 @lru_cache(maxsize=1)
@@ -76,51 +75,17 @@ def load_F(X: np.ndarray) -> np.ndarray:
     return v * _omega1(X)[:, None]
 
 
-def _mapped_basis(BmT: np.ndarray, xq: np.ndarray):
-    """s-free covariant images B^-T eta^_k at one reference point -> [T, n, 2]."""
-    vals = ref.eval_basis("ned", 2, xq[None, :])[0]         # [n, 2]
-    return np.einsum("tij,kj->tki", BmT, vals)
-
-
 def load_vector(nodes, elems, topo, F=load_F, m=None):
-    """f_i = int F . eta_i: per element, sum over the quadrature points of
-    w_q |det B_K| F(F_K(x^_q)) . s_k B_K^-T eta^_k(x^_q); then every element's
-    local values are added to their dofs in ascending element order."""
-    m = DEFAULT_M[2] if m is None else m
-    B, b, det = affine_transformations(nodes, elems)
-    BmT = np.swapaxes(np.linalg.inv(B), 1, 2)
-    S = element_signs(topo, "ned").astype(np.float64)
-    D = element_dofs(topo, "ned")
-    xq, wq = ref.quadrature(2, m)
-    loc = np.zeros(D.shape)
-    for i in range(len(wq)):
-        X = np.einsum("tij,j->ti", B, xq[i]) + b
-        phi = _mapped_basis(BmT, xq[i])                        # [T, 3, 2]
-        loc += wq[i] * np.abs(det)[:, None] * np.einsum("tki,ti->tk", phi, F(X))
-    loc *= S
-    return np.bincount(D.reshape(-1), weights=loc.reshape(-1), minlength=topo.n_edges)
+    """f_i = int F . eta_i (``integrate.load_vector_ned``) with the example's F."""
+    return load_vector_ned(nodes, elems, topo, F, DEFAULT_M[2] if m is None else m)
 
 
 def hcurl_error(nodes, elems, topo, v, E=exact_E, curlE=exact_curl_E, m=None):
     """(per-element ||E - v||_K^2 + ||curl(E - v)||_K^2 [T], total
-    sqrt(||E - v||^2 + ||curl(E - v)||^2)) for the Nedelec field with dof
+    sqrt(||E - v||^2 + ||curl(E - v)||^2)) for the Nedelec field with edge
     values v."""
-    m = DEFAULT_M[2] if m is None else m
-    B, b, det = affine_transformations(nodes, elems)
-    BmT = np.swapaxes(np.linalg.inv(B), 1, 2)
-    S = element_signs(topo, "ned").astype(np.float64)
-    D = element_dofs(topo, "ned")
-    ve = np.asarray(v)[D] * S                                  # [T, 3]
-    curl_v = (ve @ ref.curl_basis("ned", 2)) / det             # constant per element
-    xq, wq = ref.quadrature(2, m)
-    per = np.zeros(elems.shape[0])
-    for i in range(len(wq)):
-        X = np.einsum("tij,j->ti", B, xq[i]) + b
-        vh = np.einsum("tki,tk->ti", _mapped_basis(BmT, xq[i]), ve)
-        d = E(X) - vh
-        c = curlE(X) - curl_v
-        per += wq[i] * np.abs(det) * (np.sum(d * d, axis=1) + c * c)
-    return per, float(np.sqrt(np.sum(per)))
+    per, tot = hcurl_error_ned(nodes, elems, topo, v, E, curlE, DEFAULT_M[2] if m is None else m)
+    return per, float(np.sqrt(tot))
 
 
 def solve(nodes, elems, mu_inv=None, kappa=None, m=None):

@@ -135,46 +135,59 @@ def test_affine_maps_send_reference_vertices_to_the_element():
     assert np.allclose(det, np.linalg.det(B))
 
 
+def _mesh(dim, seed):
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        nodes, elems = mg.unit_square(6, 5)
+        return mg.perturb_interior(nodes, 1 / 6, 0.2, rng), elems, rng
+    nodes, elems = mg.kuhn_box(3, 2, 2)
+    return mg.perturb_interior(nodes, 1 / 3, 0.2, rng), elems, rng
+
+
 def _discrete_field(nodes, elems, topo, c):
-    """A Nedelec field w_h with dof values c as point functions on the mesh
-    (elementwise; the caller evaluates it only at interior points of the
-    element whose rows it receives, so here it is evaluated per element)."""
+    """A Nedelec field w_h with edge values c and its curl, as functions of
+    points X [T, d] where row t lies in element t (the way the quadrature loops
+    call them)."""
+    dim = elems.shape[1] - 1
     B, b, det = it.affine_transformations(nodes, elems)
-    BmT = np.swapaxes(np.linalg.inv(B), 1, 2)
+    Binv = np.linalg.inv(B)
+    BmT = np.swapaxes(Binv, 1, 2)
     S = element_signs(topo, "ned").astype(float)
     ce = c[element_dofs(topo, "ned")] * S
+    cref = R.curl_basis("ned", dim)
 
     def w(X):
-        xr = np.einsum("tij,tj->ti", np.linalg.inv(B), X - b)    # reference coordinates
-        vals = np.stack([P @ xr.T + q[:, None] for P, q in R.basis("ned", 2)], 0)  # [3, 2, T]
-        return np.einsum("tij,ktj,tk->ti", BmT, np.transpose(vals, (0, 2, 1)), ce)
+        xr = np.einsum("tij,tj->ti", Binv, X - b)                  # reference coordinates
+        vals = np.stack([xr @ P.T + q for P, q in R.basis("ned", dim)], 1)   # [T, n, d]
+        return np.einsum("tij,tkj,tk->ti", BmT, vals, ce)
 
     def curl(X):
-        return (ce @ R.curl_basis("ned", 2)) / det
+        if dim == 2:
+            return (ce @ cref) / det
+        return np.einsum("tij,kj,tk->ti", B, cref, ce) / det[:, None]
     return w, curl
 
 
-def test_load_vector_of_a_discrete_field_is_M_times_its_dofs():
-    rng = np.random.default_rng(4)
-    nodes, elems = mg.unit_square(6, 5)
-    nodes = mg.perturb_interior(nodes, 1 / 6, 0.2, rng)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vector_of_a_discrete_field_is_M_times_its_dofs(dim):
+    nodes, elems, rng = _mesh(dim, 4)
     csr, topo = oracle.assemble(nodes, elems, "ned")
     c = rng.normal(size=topo.n_edges)
     w, _ = _discrete_field(nodes, elems, topo, c)
-    f = ed.load_vector(nodes, elems, topo, F=w)
+    f = it.load_vector_ned(nodes, elems, topo, w)
     assert np.allclose(f, csr.scipy("M") @ c, rtol=0, atol=1e-13 * np.abs(f).max())
 
 
-def test_energy_error_against_a_discrete_field_is_the_matrix_norm():
-    rng = np.random.default_rng(5)
-    nodes, elems = mg.unit_square(6, 5)
-    nodes = mg.perturb_interior(nodes, 1 / 6, 0.2, rng)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_error_against_a_discrete_field_is_the_matrix_norm(dim):
+    nodes, elems, rng = _mesh(dim, 5)
     csr, topo = oracle.assemble(nodes, elems, "ned")
     c = rng.normal(size=topo.n_edges)
     d = rng.normal(size=topo.n_edges)
     w, cw = _discrete_field(nodes, elems, topo, c)
-    per, err = ed.hcurl_error(nodes, elems, topo, c + d, E=w, curlE=cw)
+    per, err2 = it.hcurl_error_ned(nodes, elems, topo, c + d, w, cw)
     A = csr.scipy("K") + csr.scipy("M")
-    assert abs(err ** 2 - d @ (A @ d)) < 1e-12 * (d @ (A @ d))
-    per0, err0 = ed.hcurl_error(nodes, elems, topo, c, E=w, curlE=cw)
-    assert err0 < 1e-13
+    assert abs(err2 - d @ (A @ d)) < 1e-12 * (d @ (A @ d))
+    assert abs(per.sum() - err2) < 1e-15 * err2
+    _, err0 = it.hcurl_error_ned(nodes, elems, topo, c, w, cw)
+    assert err0 < 1e-26
