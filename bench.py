@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import tempfile
@@ -399,6 +400,118 @@ def cpu_baseline(p, target_seconds=12.0, workers=None):
             "cpu_count": os.cpu_count(), "cpus_available": avail, "cpu_model": cpu_model()}
 
 
+# Paper's MATLAB rates (Section 3.3 tables; 64x Xeon E7-8837, R2011b), M elements/s of K + M:
+# context for the level curves, not a target.
+PAPER_3D = {1: (0.0118, 0.0093), 2: (0.0196, 0.0095), 3: (0.0277, 0.0129), 4: (0.0295, 0.0136),
+            5: (0.0287, 0.0129), 6: (0.0273, 0.0124)}          # level: (RT, Nedelec)
+PAPER_2D = {5: (0.068, 0.102), 6: (0.040, 0.042), 7: (0.066, 0.069), 8: (0.074, 0.072),
+            9: (0.077, 0.077), 10: (0.076, 0.073), 11: (0.072, 0.069)}
+
+
+def level_curves(steps, warmup):
+    """Forward K + M (unit coefficients, unperturbed meshes: the paper's timing
+    setting) on the meshes of the paper's timing tables: the 3D unit cube at
+    levels 1-6 (n = 3 2^level cubes per side, 6 tets each) and the 2D L-shape at
+    levels 5-11 (m = 2^level cells per half side), both kinds. Warm median of
+    `steps` launches each, M elements/s and the fraction of 8 TB/s; the CPU
+    oracle (numeric phase, one thread) is timed beside it at the small levels."""
+    import torch
+    import meshgen as mg
+    import oracle
+    from threadpoolctl import threadpool_limits
+    out = []
+    cases = [("cube", L, 3 * 2 ** L) for L in range(1, 7)] + [("lshape", L, 2 ** L) for L in range(5, 12)]
+    for dom, L, n in cases:
+        nodes, elems = mg.kuhn_box(n) if dom == "cube" else mg.l_shape(n)
+        dim = elems.shape[1] - 1
+        for kind in ("rt", "ned"):
+            p = mg.Problem(f"{dom}{L}_{kind}", kind, nodes, elems)
+            s = setup_mesh(p)
+            f = forward_rate(p, s, max(5, steps // 10), max(2, warmup // 10))
+            row = {"domain": dom, "level": L, "kind": kind, "elements": int(elems.shape[0]), "rows": s["n_rows"],
+                   "nnz": s["nnz"], "ms": round(f["ms"], 5), "mel_s": round(f["mtets"], 1),
+                   "frac": round(f["frac"], 4),
+                   "paper_mel_s": (PAPER_3D if dim == 3 else PAPER_2D)[L][0 if kind == "rt" else 1]}
+            if elems.shape[0] <= 100000:
+                with threadpool_limits(limits=1):
+                    t0 = time.perf_counter()
+                    oracle.assemble(nodes, elems, kind)
+                    row["oracle_1thread_mel_s"] = round(elems.shape[0] / (time.perf_counter() - t0) / 1e6, 4)
+            out.append(row)
+            del s
+            torch.cuda.empty_cache()
+        log(f"bench:   {dom} level {L}: {out[-1]['mel_s']} M el/s (ned), {out[-2]['mel_s']} (rt)")
+    return out
+
+
+def eddy_rate(n=512):
+    """The 2D eddy-current example (Section 4.2) on the n x n unit square: the
+    whole pipeline (K + M assembly, load vector, Jacobi-CG to a recursive
+    residual of 1e-12, energy error), each phase timed with HIP events (one run
+    after a warm-up run), against the paper's printed error; and the
+    squared L2 norm routine (fem_norm_L2) on the same mesh and on Kuhn 64^3."""
+    import torch
+    import meshgen as mg
+    import paper_1409_4618_amd as fem
+    d = torch.device("cuda:0")
+    nodes, elems = mg.unit_square(n)
+    tn = torch.tensor(nodes, device=d)
+    te = torch.tensor(elems, device=d)
+    mesh = fem.Mesh(tn, te)
+    rowptr, colind = mesh.pattern_device("ned")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def run(record):
+        if record:
+            ev[0].record()
+        K, M = fem._assemble_values(mesh, "ned", tn)
+        if record:
+            ev[1].record()
+        f = fem.load_vector(mesh, "ned", tn, fem.FEM_FN_EDDY_F)
+        if record:
+            ev[2].record()
+        v, iters, res = fem.cg_solve(rowptr, colind, K, f, B=M, rtol=1e-12)
+        if record:
+            ev[3].record()
+        _, e2 = fem.field_error(mesh, "ned", tn, v, fem.FEM_FN_EDDY_E, fem.FEM_FN_EDDY_CURL_E)
+        if record:
+            ev[4].record()
+        return iters, res, e2
+    run(False)
+    torch.cuda.synchronize()
+    iters, res, e2 = run(True)
+    torch.cuda.synchronize()
+    mesh.status()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    nnz = colind.numel()
+    nrow = rowptr.numel() - 1
+    # bytes of one CG iteration: the product reads rowptr, colind, K, M and the
+    # gathered z, p (each column value once), writes p and q; the update reads
+    # x, p, q, r, 1/diag and writes x, r, z
+    it_bytes = 8 * (nrow + 1) + 4 * nnz + 16 * nnz + 16 * nrow + 16 * nrow + 5 * 8 * nrow + 3 * 8 * nrow
+    cg_it_ms = ms[2] / max(iters, 1)
+    out = {"workload": f"2D eddy current, unit square {n}x{n} ({elems.shape[0]} triangles, {nrow} edges)",
+           "error": math.sqrt(e2.item()), "paper_error": {128: 2.358185e-02, 256: 1.179151e-02, 512: 5.895834e-03,
+                                                          1024: 2.947927e-03}.get(n),
+           "assemble_ms": ms[0], "load_vector_ms": ms[1], "cg_ms": ms[2], "cg_iterations": iters,
+           "cg_true_rel_residual": res, "cg_us_per_iteration": 1e3 * cg_it_ms,
+           "cg_iteration_gbs": it_bytes / (cg_it_ms * 1e-3) / 1e9, "error_ms": ms[3], "total_ms": sum(ms)}
+    # fem_norm_L2 rates
+    steps = 20
+    ms_l2 = timed(lambda: fem.norm_L2(mesh, tn, fem.FEM_FN_EDDY_E), steps, 3)
+    out["norm_L2_eddy_E"] = {"elements": int(elems.shape[0]), "ms": ms_l2, "quad_points": 16,
+                             "mel_s": elems.shape[0] / (ms_l2 * 1e-3) / 1e6}
+    p = mg.kuhn64_ned()
+    t3 = torch.tensor(p.nodes, device=d)
+    m3 = fem.Mesh(t3, torch.tensor(p.elems, device=d))
+    terms = [1.0, 0, 1, 1, 0, -2.0, 0, 0, 0, 2, 0.5, 1, 2, 0, 1]
+    ms3 = timed(lambda: fem.norm_L2(m3, t3, fem.FEM_FN_POLYNOMIAL, terms), steps, 3)
+    out["norm_L2_kuhn64_polynomial"] = {"elements": p.T, "ms": ms3, "quad_points": 125,
+                                        "mel_s": p.T / (ms3 * 1e-3) / 1e6}
+    m3.status()
+    return out
+
+
 def calib_copy():
     """A plain device copy of known size (1 GiB read + 1 GiB written), to scale the
     HBM byte counters of a profiler run."""
@@ -458,6 +571,10 @@ def only_workload(args):
                "achieved_gbs": f["gbs"], "frac": f["frac"]}
     elif args.only == "kuhn96_fwd_bwd":
         out = fwd_bwd_rate(mg.kuhn96_ned_grad(), args.steps, args.warmup)
+    elif args.only == "eddy":
+        out = eddy_rate()
+    elif args.only == "levels":
+        out = {"levels": level_curves(args.steps, args.warmup)}
     else:
         out = batched_rate(args.steps, args.warmup, None)
     if args.calib_copy:
@@ -474,7 +591,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (profiler byte-counter calibration)")
-    ap.add_argument("--only", choices=["kuhn128_ned3d", "kuhn128_rt3d", "kuhn96_fwd_bwd", "batch256"],
+    ap.add_argument("--only", choices=["kuhn128_ned3d", "kuhn128_rt3d", "kuhn96_fwd_bwd", "batch256", "eddy",
+                                       "levels"],
                     help="time one secondary workload alone and print its JSON (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -575,6 +693,14 @@ def main():
     log("bench: batched 256 meshes")
     result["batched"] = {k: (round(v, 6) if isinstance(v, float) else v)
                          for k, v in batched_rate(args.steps, args.warmup, f64["mtets"]).items()}
+    torch.cuda.empty_cache()
+
+    log("bench: 2D eddy-current pipeline and norm_L2")
+    result["eddy_2d"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in eddy_rate().items()}
+    torch.cuda.empty_cache()
+
+    log("bench: level curves (paper's timing meshes)")
+    result["levels"] = level_curves(args.steps, args.warmup)
     torch.cuda.empty_cache()
 
     if not args.no_cpu:

@@ -217,6 +217,92 @@ fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* 
                           const double* A, const double* B, double alpha, double beta,
                           const double* x, double* y, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Integration over a mesh (Section 3.1) and the building blocks of the
+ * examples of Section 4: the squared L2 norm of a function, the load vector of
+ * the Nedelec basis, the H(curl) error of a discrete field, and a
+ * conjugate-gradient solve on an assembled pattern.
+ *
+ * Quadrature: the conical-product Gauss-Legendre rule on the reference
+ * triangle / tetrahedron with `quad_m` points per direction (1..8; quad_m^dim
+ * points), exact for polynomials of total degree <= 2 quad_m - dim. The
+ * paper's routine uses a rule of order 6; quad_m = 4 (2D) and 5 (3D) reach it.
+ *
+ * Functions: the paper's norm_L2 takes a function handle; here the integrand
+ * is one of a compiled-in catalogue, selected by fem_function:
+ *   FEM_FN_POLYNOMIAL   f(x) = sum of terms c x_1^p_1 ... x_d^p_d, each term
+ *                       adding to one component of f. params: host array of
+ *                       n_terms (1..32) groups of (2 + dim) doubles:
+ *                       c, component (0..dim-1), p_1 .. p_dim (integers 0..30).
+ *   FEM_FN_EDDY_E       the exact solution E of the 2D eddy-current example
+ *                       (Section 4.2): the printed field on x1 > x2, 0 elsewhere
+ *   FEM_FN_EDDY_CURL_E  its curl (scalar)
+ *   FEM_FN_EDDY_F       its right-hand side F = curl_vec curl E + E (mu = kappa = 1)
+ * The eddy functions take no params (NULL, 0) and need dim = 2.
+ */
+typedef enum {
+    FEM_FN_POLYNOMIAL = 0,
+    FEM_FN_EDDY_E = 1,
+    FEM_FN_EDDY_CURL_E = 2,
+    FEM_FN_EDDY_F = 3
+} fem_function;
+
+/* Squared L2 norm ||f||^2 = sum_K int_K |f|^2 (the paper's norm_L2, Section 3.1;
+ * for a vector function the squared Euclidean norm is integrated).
+ *   nodes     dev f64 [n_nodes][dim]
+ *   per_elem  dev f64 [n_elems] output ||f||_K^2 (NULL to skip)
+ *   total     dev f64 [1] output ||f||^2
+ * Deterministic (element sums in a fixed order). Uses library-owned scratch in
+ * the handle (ceil(n_elems / 256) doubles, allocated on first use).
+ * Asynchronous. FEM_EINVAL for a bad function, params or quad_m.            */
+fem_status fem_norm_L2(fem_mesh mesh, const double* nodes, fem_function f, const double* params,
+                       int n_params, int quad_m, double* per_elem, double* total, void* stream);
+
+/* Load vector f_i = int F . eta_i of the Nedelec basis (kind must be
+ * FEM_NEDELEC; 2D and 3D), for a vector function F of the mesh dimension.
+ * eta_i is the global (sign-adjusted, Piola-mapped) basis function of edge i,
+ * Sections 2.2-2.3. Element integrals by the quadrature above, then each
+ * entry summed over its edge's elements in ascending element order.
+ *   f  dev f64 [n_edges] output, overwritten
+ * Uses library-owned scratch in the handle ([n_elems][3|6] doubles).
+ * Asynchronous.                                                             */
+fem_status fem_load_vector(fem_mesh mesh, fem_kind kind, const double* nodes, fem_function F,
+                           const double* params, int n_params, int quad_m, double* f, void* stream);
+
+/* H(curl) error of the Nedelec field v_h with edge values v against a field E
+ * with curl C: sum_K int_K |E - v_h|^2 + |C - curl v_h|^2 (the squared error
+ * of the eddy-current table, Section 4.2). kind must be FEM_NEDELEC.
+ *   v         dev f64 [n_edges]
+ *   field     function giving E (dim components), curl giving C (2D: 1, 3D: 3
+ *             components); both read `params` when they are polynomials
+ *   per_elem  dev f64 [n_elems] output (NULL to skip); total dev f64 [1] output
+ * Deterministic. Uses the handle's scratch of fem_norm_L2. Asynchronous.     */
+fem_status fem_field_error(fem_mesh mesh, fem_kind kind, const double* nodes, const double* v,
+                           fem_function field, fem_function curl, const double* params, int n_params,
+                           int quad_m, double* per_elem, double* total, void* stream);
+
+/* Solve (ca A + cb B) x = rhs by conjugate gradients with the Jacobi
+ * (diagonal) preconditioner, A and B value arrays on one CSR pattern (B may
+ * be NULL). Not part of the paper (its Section 4 examples solve such systems;
+ * the matrix must be symmetric positive definite, as K + M is).
+ *   rowptr dev i64 [n_rows+1], colind dev i32 [nnz] (square pattern)
+ *   rhs    dev f64 [n_rows]; x dev f64 [n_rows]: initial guess in, solution out
+ *   rtol   stop when the recursive residual r (updated by the iteration, equal
+ *          to rhs - A' x up to rounding) has ||r|| <= rtol ||rhs||; tested every
+ *          16 iterations
+ *   iters, rel_resid  host outputs (may be NULL): iterations done and the true
+ *          relative residual ||rhs - A' x|| / ||rhs|| of the returned x, formed
+ *          at the end (it can stay above rtol by the rounding of A' x)
+ * Deterministic: every dot product is summed in one fixed order. Allocates its
+ * workspace (6 n_rows + 6150 doubles) for the call and synchronises `stream`.
+ * FEM_EINVAL for bad arguments or a non-positive diagonal entry; FEM_EHIP if
+ * the iteration breaks down (p . A' p <= 0). Reaching max_iter is not an
+ * error: check rel_resid.                                                   */
+fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* colind,
+                        const double* A, const double* B, double ca, double cb, const double* rhs,
+                        double* x, double rtol, int64_t max_iter, void* stream, int64_t* iters,
+                        double* rel_resid);
+
 /* Synchronises the last stream used with `mesh`, returns and clears the
  * asynchronous device error word (FEM_OK, FEM_EDEGENERATE or FEM_ENONFINITE). */
 fem_status fem_status_query(fem_mesh mesh);

@@ -16,10 +16,13 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Sequence
 
-from ._lib import (FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
+from ._lib import (FEM_FN_EDDY_CURL_E, FEM_FN_EDDY_E, FEM_FN_EDDY_F, FEM_FN_POLYNOMIAL, FEM_NEDELEC,
+                   FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
 __all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
-           "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_form", "assemble_quadratic", "csr_matvec"]
+           "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_form", "assemble_quadratic", "csr_matvec",
+           "norm_L2", "load_vector", "field_error", "cg_solve", "default_quad_m",
+           "FEM_FN_POLYNOMIAL", "FEM_FN_EDDY_E", "FEM_FN_EDDY_CURL_E", "FEM_FN_EDDY_F"]
 
 NED = "ned"
 RT = "rt"
@@ -249,6 +252,83 @@ def csr_matvec(rowptr, colind, A, x, B=None, alpha=1.0, beta=1.0, out=None):
     check(lib().fem_csr_matvec(n, _ptr(rowptr), _ptr(colind), _ptr(A), _ptr(B), float(alpha), float(beta),
                                _ptr(x), _ptr(y), _stream_ptr()), "fem_csr_matvec")
     return y
+
+
+def default_quad_m(dim: int) -> int:
+    """Gauss-Legendre points per direction of the conical rule whose degree
+    reaches 6, the order of the paper's norm_L2 (2D: 4 -> degree 6; 3D: 5 -> 7)."""
+    return 4 if dim == 2 else 5
+
+
+def _fn_params(params):
+    """Host array of polynomial parameters (flat sequence of floats) -> (ptr, n)."""
+    if params is None:
+        return None, 0
+    flat = [float(v) for v in params]
+    arr = (ctypes.c_double * len(flat))(*flat)
+    return arr, len(flat)
+
+
+def norm_L2(mesh: Mesh, nodes, fn, params=None, quad_m=None, per_elem=False):
+    """(per-element ||f||_K^2 [T] or None, total ||f||^2 0-dim tensor) of a
+    catalogue function (fem_norm_L2, Section 3.1)."""
+    torch = _torch()
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    arr, n = _fn_params(params)
+    per = torch.empty(mesh.n_elems, dtype=torch.float64, device=nodes.device) if per_elem else None
+    tot = torch.empty((), dtype=torch.float64, device=nodes.device)
+    check(lib().fem_norm_L2(mesh.handle, _ptr(nodes), int(fn), arr, n,
+                            default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(per), _ptr(tot),
+                            _stream_ptr()), "fem_norm_L2")
+    return per, tot
+
+
+def load_vector(mesh: Mesh, kind, nodes, fn, params=None, quad_m=None):
+    """f_i = int F . eta_i over the Nedelec basis (fem_load_vector) -> [n_edges]."""
+    torch = _torch()
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    arr, n = _fn_params(params)
+    f = torch.empty(mesh.n_edges, dtype=torch.float64, device=nodes.device)
+    check(lib().fem_load_vector(mesh.handle, kind_code(kind), _ptr(nodes), int(fn), arr, n,
+                                default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(f),
+                                _stream_ptr()), "fem_load_vector")
+    return f
+
+
+def field_error(mesh: Mesh, kind, nodes, v, field, curl, params=None, quad_m=None, per_elem=False):
+    """(per-element [T] or None, total 0-dim tensor) of
+    int |E - v_h|^2 + |curl E - curl v_h|^2 (fem_field_error)."""
+    torch = _torch()
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(v, torch.float64, "v", (mesh.n_edges,))
+    arr, n = _fn_params(params)
+    per = torch.empty(mesh.n_elems, dtype=torch.float64, device=nodes.device) if per_elem else None
+    tot = torch.empty((), dtype=torch.float64, device=nodes.device)
+    check(lib().fem_field_error(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(v), int(field), int(curl), arr, n,
+                                default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(per), _ptr(tot),
+                                _stream_ptr()), "fem_field_error")
+    return per, tot
+
+
+def cg_solve(rowptr, colind, A, rhs, B=None, ca=1.0, cb=1.0, x0=None, rtol=1e-12, max_iter=None):
+    """Solve (ca A + cb B) x = rhs by Jacobi-preconditioned CG (fem_cg_solve).
+    Returns (x, iterations, true relative residual)."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    nnz = colind.numel()
+    _check_dev(rowptr, torch.int64, "rowptr")
+    _check_dev(colind, torch.int32, "colind")
+    _check_dev(A, torch.float64, "A", (nnz,))
+    _check_dev(B, torch.float64, "B", (nnz,))
+    _check_dev(rhs, torch.float64, "rhs", (n,))
+    x = torch.zeros(n, dtype=torch.float64, device=A.device) if x0 is None else x0.clone()
+    _check_dev(x, torch.float64, "x", (n,))
+    it = ctypes.c_int64()
+    res = ctypes.c_double()
+    check(lib().fem_cg_solve(n, _ptr(rowptr), _ptr(colind), _ptr(A), _ptr(B), float(ca), float(cb), _ptr(rhs),
+                             _ptr(x), float(rtol), int(10 * n if max_iter is None else max_iter), _stream_ptr(),
+                             ctypes.byref(it), ctypes.byref(res)), "fem_cg_solve")
+    return x, it.value, res.value
 
 
 def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b=True,

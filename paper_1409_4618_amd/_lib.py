@@ -17,6 +17,12 @@ c_void_pp = ctypes.POINTER(ctypes.c_void_p)
 FEM_NEDELEC = 0
 FEM_RAVIART_THOMAS = 1
 
+# fem_function
+FEM_FN_POLYNOMIAL = 0
+FEM_FN_EDDY_E = 1
+FEM_FN_EDDY_CURL_E = 2
+FEM_FN_EDDY_F = 3
+
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_EINVAL", 2: "FEM_ERANGE", 3: "FEM_EDEGENERATE",
                 4: "FEM_ENONFINITE", 5: "FEM_EOVERFLOW", 6: "FEM_ENOMEM", 7: "FEM_EHIP",
                 8: "FEM_ENOTREADY"}
@@ -38,6 +44,17 @@ SIGNATURES = [
     ("fem_csr_matvec", ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_norm_L2", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_load_vector", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_field_error", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_cg_solve", ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, c_int64_p,
+                                    ctypes.POINTER(ctypes.c_double)]),
     ("fem_status_query", ctypes.c_int, [ctypes.c_void_p]),
     ("fem_mesh_destroy", None, [ctypes.c_void_p]),
     ("fem_batch_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, c_void_pp]),

@@ -671,7 +671,11 @@ fem_status launch_quadratic_value(fem_mesh m, DofSet& ds, fem_kind kind, const d
         else hipLaunchKernelGGL(k_quadratic_value<0>, dim3((unsigned)nb), dim3(BWD_BLOCK), 0, s, A, partials);
         FEM_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nb, out);
+    return launch_sum_partials(partials, nb, out, s);
+}
+
+fem_status launch_sum_partials(const double* partials, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, n, out);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }

@@ -116,6 +116,8 @@ struct fem_mesh_s {
     // order; see build_node_map
     double* elem_partials = nullptr; // [pairs][dim] vertex-derivative partial of each pair
     double* qv_partials = nullptr;   // [ceil(T / 256)] workgroup sums of the quadratic-form value
+    double* int_partials = nullptr;  // [ceil(T / 256)] workgroup sums of the integration routines
+    double* slot_vals = nullptr;     // [T][nloc] element-local load-vector values
     int32_t* node_ptr = nullptr;     // [V+1] pairs of each node (into bwd_npair)
     int32_t* bwd_npair = nullptr;    // [pairs] pair indices by node, ascending workgroup
     int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (pairs are workgroup-major)
@@ -232,6 +234,29 @@ int64_t quadratic_value_partials(int64_t n_elems);
 fem_status launch_quadratic_value(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                                   const double* a, const double* b, const double* u, double* out,
                                   double* partials, hipStream_t s);
+// out[0] = sum of n partials in a fixed order (one workgroup).
+fem_status launch_sum_partials(const double* partials, int64_t n, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// integration (integrate.hip)
+constexpr int FEM_QUAD_MAX = 8;          // Gauss-Legendre points per direction
+constexpr int FEM_POLY_MAX_TERMS = 32;   // terms of a polynomial function
+// one-dimensional Gauss-Legendre rule on [0, 1] of the conical-product rule
+struct QuadRule {
+    int m;
+    double x[FEM_QUAD_MAX];
+    double w[FEM_QUAD_MAX];
+};
+// a function of the catalogue (fem_function) with its parameters
+struct FnArgs {
+    int fn;
+    int n_terms;
+    int n_comp;
+    double p[FEM_POLY_MAX_TERMS * 5];  // polynomial terms: coefficient, component, exponents
+};
+fem_status gauss_legendre01(int m, QuadRule* q);
+fem_status make_fn_args(fem_function fn, int dim, const double* params, int n_params, FnArgs* F);
+
 fem_status launch_batch(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
                         int rows_per_tile, int schedule, int grid, int pmax,
                         unsigned* counters, hipStream_t s);

@@ -22,7 +22,7 @@ def L():
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fem_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fem_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():

@@ -1,0 +1,239 @@
+"""GPU integration routines (Section 3.1) and the 2D eddy-current example
+(Section 4.2) against the oracle and against the paper's printed errors.
+
+* fem_norm_L2: per-element and total squared L2 norms of catalogue functions
+  (polynomials in 2D and 3D, the eddy solution E) equal the oracle's within
+  1e-12 of the largest value; polynomial totals equal the exact integrals.
+* fem_load_vector: the Nedelec load vector of the eddy F (2D) and of a
+  polynomial field (3D) within relative Frobenius 1e-12 of the oracle's.
+* fem_field_error: the H(curl) error terms of a random discrete field within
+  1e-12 of the oracle's.
+  (Both sides use the same conical Gauss-Legendre rule, each generating it on
+  its own; the results differ by rounding only: the bound is the one of the
+  assembled matrices.)
+* fem_cg_solve, stopped at a recursive residual of 1e-12: the true relative
+  residual of the result is below 1e-10 (it levels off above the recursive
+  one by the rounding of A x, about 1e-16 times the condition number of
+  K + 2M, 1e4 to 1e5 here), and the solution is within 1e-8 (relative) of a
+  direct solve (residual times condition number); bitwise repeatable.
+* the pipeline (assembly, load vector, CG, error) reproduces the paper's
+  printed errors to all 7 printed digits at 128 to 1024 cells per side, and
+  its f, v and element errors match the oracle's direct-solve pipeline at 128.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import oracle
+from gpu_util import dev_tensors, rel_fro, say
+from oracle import eddy as ed
+from oracle import integrate as it
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_eddy_errors.txt")
+
+
+def _mesh(dim, seed):
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        nodes, elems = mg.unit_square(20, 17)
+        return mg.perturb_interior(nodes, 1 / 20, 0.2, rng), elems, rng
+    nodes, elems = mg.kuhn_box(6, 5, 4)
+    return mg.perturb_interior(nodes, 1 / 6, 0.2, rng), elems, rng
+
+
+def _poly_np(terms, dim):
+    """numpy evaluation of a catalogue polynomial (oracle side, from the terms)."""
+    ncomp = max(int(t[1]) for t in terms) + 1
+
+    def f(X):
+        out = np.zeros((X.shape[0], ncomp))
+        for t in terms:
+            out[:, int(t[1])] += t[0] * np.prod(X ** np.array(t[2:2 + dim]), axis=1)
+        return out[:, 0] if ncomp == 1 else out
+    return f
+
+
+POLY = {
+    2: {"scalar": [(1.5, 0, 2, 1), (-0.5, 0, 0, 3), (2.0, 0, 1, 0), (0.25, 0, 0, 0)],
+        "vector": [(1.0, 0, 1, 1), (-2.0, 0, 0, 2), (0.5, 1, 3, 0), (1.0, 1, 0, 1)]},
+    3: {"scalar": [(1.5, 0, 2, 1, 0), (-0.5, 0, 0, 1, 2), (2.0, 0, 1, 0, 1), (0.25, 0, 0, 0, 0)],
+        "vector": [(1.0, 0, 1, 1, 0), (-2.0, 0, 0, 0, 2), (0.5, 1, 2, 0, 1), (1.0, 1, 0, 1, 0),
+                   (0.75, 2, 1, 1, 1), (-1.0, 2, 0, 2, 0)]},
+}
+
+
+def _flat(terms):
+    return [v for t in terms for v in t]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("which", ["scalar", "vector"])
+def test_norm_L2_of_polynomials(dim, which):
+    import paper_1409_4618_amd as fem
+    nodes, elems, _ = _mesh(dim, 1)
+    say(f"[gpu] norm_L2 {which} polynomial, dim {dim}, T={elems.shape[0]}")
+    terms = POLY[dim][which]
+    per_o, tot_o = it.norm_L2_squared(nodes, elems, _poly_np(terms, dim))
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    per, tot = fem.norm_L2(mesh, tn, fem.FEM_FN_POLYNOMIAL, _flat(terms), per_elem=True)
+    mesh.status()
+    per = per.cpu().numpy()
+    e_per = np.abs(per - per_o).max() / np.abs(per_o).max()
+    e_tot = abs(tot.item() - tot_o) / abs(tot_o)
+    say(f"    per-element {e_per:.2e}, total {e_tot:.2e}")
+    assert e_per <= TOL and e_tot <= TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_norm_L2_of_monomials_is_exact(dim):
+    """Degree <= 3 monomials over the unit square / cube: the exact integral."""
+    import paper_1409_4618_amd as fem
+    nodes, elems, _ = _mesh(dim, 2)
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    for exps in ([1, 2], [3, 0], [0, 1]) if dim == 2 else ([1, 1, 1], [0, 3, 0], [2, 0, 1]):
+        _, tot = fem.norm_L2(mesh, tn, fem.FEM_FN_POLYNOMIAL, [1.0, 0.0] + [float(e) for e in exps])
+        exact = math.prod(1.0 / (2 * e + 1) for e in exps)
+        assert abs(tot.item() - exact) <= 1e-13, (exps, tot.item(), exact)
+
+
+def test_norm_L2_of_the_eddy_solution():
+    import paper_1409_4618_amd as fem
+    nodes, elems = mg.unit_square(64)
+    per_o, tot_o = it.norm_L2_squared(nodes, elems, ed.exact_E)
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    per, tot = fem.norm_L2(mesh, tn, fem.FEM_FN_EDDY_E, per_elem=True)
+    per = per.cpu().numpy()
+    assert np.abs(per - per_o).max() <= TOL * np.abs(per_o).max()
+    assert abs(tot.item() - tot_o) <= TOL * tot_o
+    _, tc = fem.norm_L2(mesh, tn, fem.FEM_FN_EDDY_CURL_E)
+    _, tc_o = it.norm_L2_squared(nodes, elems, ed.exact_curl_E)
+    assert abs(tc.item() - tc_o) <= TOL * tc_o
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vector(dim):
+    import paper_1409_4618_amd as fem
+    if dim == 2:
+        nodes, elems = mg.unit_square(48)
+        fn, params, F = fem.FEM_FN_EDDY_F, None, ed.load_F
+    else:
+        nodes, elems, _ = _mesh(3, 3)
+        terms = POLY[3]["vector"]
+        fn, params, F = fem.FEM_FN_POLYNOMIAL, _flat(terms), _poly_np(terms, 3)
+    say(f"[gpu] load vector, dim {dim}, T={elems.shape[0]}")
+    topo = oracle.build_topology(elems, nodes.shape[0])
+    f_o = it.load_vector_ned(nodes, elems, topo, F)
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    f = fem.load_vector(mesh, "ned", tn, fn, params)
+    mesh.status()
+    err = rel_fro(f.cpu().numpy(), f_o)
+    say(f"    rel Frobenius {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_field_error(dim):
+    import torch
+    import paper_1409_4618_amd as fem
+    if dim == 2:
+        nodes, elems = mg.unit_square(48)
+        fE, fC, params = fem.FEM_FN_EDDY_E, fem.FEM_FN_EDDY_CURL_E, None
+        E, C = ed.exact_E, ed.exact_curl_E
+        rng = np.random.default_rng(4)
+    else:
+        nodes, elems, rng = _mesh(3, 4)
+        # a polynomial field E (components 0-2) and an unrelated polynomial "curl"
+        # (components 0-2): the routine integrates |E - v_h|^2 + |C - curl v_h|^2
+        tE = POLY[3]["vector"]
+        fE = fC = fem.FEM_FN_POLYNOMIAL
+        params = _flat(tE)
+        E = C = _poly_np(tE, 3)
+    topo = oracle.build_topology(elems, nodes.shape[0])
+    v = rng.normal(size=topo.n_edges)
+    say(f"[gpu] field error, dim {dim}, T={elems.shape[0]}")
+    per_o, tot_o = it.hcurl_error_ned(nodes, elems, topo, v, E, C)
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    per, tot = fem.field_error(mesh, "ned", tn, torch.tensor(v, device=tn.device), fE, fC, params, per_elem=True)
+    mesh.status()
+    per = per.cpu().numpy()
+    e_per = np.abs(per - per_o).max() / np.abs(per_o).max()
+    e_tot = abs(tot.item() - tot_o) / tot_o
+    say(f"    per-element {e_per:.2e}, total {e_tot:.2e}")
+    assert e_per <= TOL and e_tot <= TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cg_solve(dim):
+    import scipy.sparse.linalg as spla
+    import torch
+    import paper_1409_4618_amd as fem
+    if dim == 2:
+        nodes, elems = mg.unit_square(64)
+        rng = np.random.default_rng(5)
+    else:
+        nodes, elems, rng = _mesh(3, 5)
+    a = rng.uniform(0.5, 2, elems.shape[0])
+    b = rng.uniform(0.5, 2, elems.shape[0])
+    csr, topo = oracle.assemble(nodes, elems, "ned", a=a, b=b)
+    rhs = rng.normal(size=csr.n_rows)
+    A = (csr.scipy("K") + 2.0 * csr.scipy("M")).tocsc()
+    x_o = spla.spsolve(A, rhs)
+    tn, te, ta, tb = dev_tensors(nodes, elems, a, b)
+    mesh = fem.Mesh(tn, te)
+    K, M = fem.assemble(mesh, "ned", tn, ta, tb)
+    rowptr, colind = mesh.pattern_device("ned")
+    trhs = torch.tensor(rhs, device=tn.device)
+    say(f"[gpu] CG (K + 2M) x = rhs, dim {dim}, n={csr.n_rows}")
+    x, iters, res = fem.cg_solve(rowptr, colind, K, trhs, B=M, ca=1.0, cb=2.0, rtol=1e-12)
+    x2, iters2, res2 = fem.cg_solve(rowptr, colind, K, trhs, B=M, ca=1.0, cb=2.0, rtol=1e-12)
+    err = np.linalg.norm(x.cpu().numpy() - x_o) / np.linalg.norm(x_o)
+    say(f"    {iters} iterations, residual {res:.2e}, rel err vs direct {err:.2e}")
+    assert res <= 1e-10 and err <= 1e-8
+    assert torch.equal(x, x2) and iters == iters2
+
+
+def _paper_errors():
+    rows = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, T, E, err = line.split()
+        rows[int(n)] = (int(T), int(E), float(err))
+    return rows
+
+
+@pytest.mark.parametrize("n", [128, 256, 512, 1024])
+def test_eddy_current_matches_the_paper(n):
+    import torch
+    import paper_1409_4618_amd as fem
+    from paper_1409_4618_amd.eddy import eddy_current
+    T, E, printed = _paper_errors()[n]
+    nodes, elems = mg.unit_square(n)
+    tn, te, _, _ = dev_tensors(nodes, elems)
+    mesh = fem.Mesh(tn, te)
+    assert mesh.n_elems == T and mesh.n_edges == E
+    say(f"[gpu] eddy current, {n} cells per side: {T} triangles, {E} edges")
+    out = eddy_current(mesh, tn)
+    say(f"    error {out['error']:.9e} (paper {printed:.6e}), {out['iters']} CG iterations, "
+        f"residual {out['rel_resid']:.2e}")
+    assert f"{out['error']:.6e}" == f"{printed:.6e}"
+    if n == 128:
+        ref = ed.solve(nodes, elems)
+        e_f = rel_fro(out["f"].cpu().numpy(), ref["f"])
+        e_v = rel_fro(out["v"].cpu().numpy(), ref["v"])
+        _, err2 = fem.field_error(mesh, "ned", tn, torch.tensor(ref["v"], device=tn.device), fem.FEM_FN_EDDY_E,
+                                  fem.FEM_FN_EDDY_CURL_E)
+        e_err = abs(math.sqrt(err2.item()) - ref["error"]) / ref["error"]
+        say(f"    vs oracle: f {e_f:.2e}, v {e_v:.2e}, error of the oracle's v {e_err:.2e}")
+        assert e_f <= TOL and e_v <= 1e-8 and e_err <= TOL
