@@ -696,7 +696,8 @@ def main():
     torch.cuda.empty_cache()
 
     log("bench: 2D eddy-current pipeline and norm_L2")
-    result["eddy_2d"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in eddy_rate().items()}
+    result["eddy_2d"] = {k: (round(v, 6) if isinstance(v, float) and k.endswith("_ms") else v)
+                         for k, v in eddy_rate().items()}
     torch.cuda.empty_cache()
 
     log("bench: level curves (paper's timing meshes)")

@@ -379,17 +379,19 @@ def _autograd_function():
             ctx.mesh = mesh
             ctx.kind = kind
             ctx.save_for_backward(nodes, a, b)
+            # an output without a gradient reaches backward as None (a NULL
+            # weight array to the adjoint, which reads it as 0) instead of an
+            # nnz-sized zero tensor
+            ctx.set_materialize_grads(False)
             return K, M
 
         @staticmethod
         def backward(ctx, gK, gM):
             nodes, a, b = ctx.saved_tensors
-            _, nnz = ctx.mesh.pattern_info(ctx.kind)
-            z = None
-            if gK is None or gM is None:
-                z = torch.zeros(nnz, dtype=torch.float64, device=nodes.device)
-            gK = z if gK is None else gK.contiguous()
-            gM = z if gM is None else gM.contiguous()
+            if gK is None and gM is None:
+                return None, None, None, None, None
+            gK = None if gK is None else gK.contiguous()
+            gM = None if gM is None else gM.contiguous()
             gn, ga, gb = assemble_backward(ctx.mesh, ctx.kind, nodes, a, b, gK, gM,
                                            need_a=ctx.needs_input_grad[1],
                                            need_b=ctx.needs_input_grad[2],
@@ -454,6 +456,9 @@ def _quadratic_functions():
             ctx.mesh = mesh
             ctx.kind = kind
             ctx.mark_non_differentiable(K, M)
+            # K and M get no gradient: without this, autograd would fill two
+            # nnz-sized zero tensors for them on every backward
+            ctx.set_materialize_grads(False)
             if ctx.needs_input_grad[3]:
                 ctx.save_for_backward(nodes, a, b, u, K, M)
             else:
@@ -462,6 +467,8 @@ def _quadratic_functions():
 
         @staticmethod
         def backward(ctx, gK, gM, gL):
+            if gL is None:
+                return (None,) * 6
             return (*_quadratic_backward(ctx, gL), None, None)
 
     return FemQuadratic, FemAssembleQuadratic

@@ -93,16 +93,20 @@ __device__ __forceinline__ void load_u(const BwdArgs& A, int64_t e, double ue[NL
 
 // Vertex derivative of local vertex v of the lane's element, into the
 // workgroup's LDS slot of that incidence (summed per vertex afterwards).
+// Component-major layout, sh[(v * DIM + c) * BWD_BLOCK + lane]: the lanes of a
+// store write consecutive words (no bank conflicts).
+__device__ __forceinline__ int lds_at(int lane, int v, int dim) { return v * dim * BWD_BLOCK + lane; }
+constexpr int LDS_CS = BWD_BLOCK;  // stride between the components of one incidence
 __device__ __forceinline__ void store_vertex3(double* sh, int v, V3 d) {
-    double* p = sh + ((int)threadIdx.x * 4 + v) * 3;
+    double* p = sh + lds_at((int)threadIdx.x, v, 3);
     p[0] = d.x;
-    p[1] = d.y;
-    p[2] = d.z;
+    p[LDS_CS] = d.y;
+    p[2 * LDS_CS] = d.z;
 }
 __device__ __forceinline__ void store_vertex2(double* sh, int v, double dx, double dy) {
-    double* p = sh + ((int)threadIdx.x * 3 + v) * 2;
+    double* p = sh + lds_at((int)threadIdx.x, v, 2);
     p[0] = dx;
-    p[1] = dy;
+    p[LDS_CS] = dy;
 }
 
 // 3D Nedelec. With weights w_kl = s_k s_l gK_kl (gM likewise):
@@ -532,6 +536,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     const int64_t e0 = blk * BWD_BLOCK;
     if (e0 >= A.T) return;  // whole workgroup
     const int64_t e = e0 + threadIdx.x;
+    const bool live = e < A.T;
     const int n_inc = (int)((A.T - e0 < BWD_BLOCK ? A.T - e0 : BWD_BLOCK) * NV);
     int pb0 = 0, np = 0;
     if (A.partials) {
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     }
     const SlotView sv = SLOTS ? SlotView{s_base + (int)threadIdx.x * NLOC, s_cp + (int)threadIdx.x * NLOC}
                               : SlotView{A.slot_base + e * NLOC, A.slot_cp + e * NLOC};
-    if (e < A.T) {
+    if (live) {
         if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sv, sh);
         else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sv, sh);
         else bwd_tri<MODE>(A, e, sv, sh);
@@ -564,7 +569,8 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     if (!A.partials) return;  // uniform
     __syncthreads();
     // one partial per (vertex, workgroup): the workgroup's incidences of that
-    // vertex, in ascending element order
+    // vertex, in ascending element order; incidence (lane, v) sits at
+    // sh[(v * DIM + c) * BWD_BLOCK + lane]
     for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) {
         const int i0 = s_pst[j];
         const int i1 = j + 1 < np ? s_pst[j + 1] : n_inc;
@@ -573,8 +579,10 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
         for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
         for (int i = i0; i < i1; ++i) {
             const int slot = s_inc[i];
+            const int lane = slot / NV;
+            const double* q = sh + lds_at(lane, slot - lane * NV, DIM);
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) acc[c] += sh[slot * DIM + c];
+            for (int c = 0; c < DIM; ++c) acc[c] += q[c * LDS_CS];
         }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) A.partials[(int64_t)(pb0 + j) * DIM + c] = acc[c];

@@ -86,33 +86,37 @@ fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* 
 // eddy-current problem of Section 4.2, whose matrix K + M is symmetric
 // positive definite).
 //
-// Each iteration is two kernels over a persistent grid of CG_GRID workgroups
-// (workgroup g takes row chunks g, g + CG_GRID, ...; a thread sums its
-// contributions in chunk order and the workgroup by a fixed tree, so every
-// dot product is computed in one fixed order: deterministic):
+// One iteration is four kernels:
 //   1. q = A' p_new with p_new = z + beta p_old formed on the fly (the update
 //      of p fused into the product; p_old and p_new are separate buffers),
-//      p_new written, and the dot p_new . q. The last workgroup to finish
-//      forms alpha = rz / (p . q).
-//   2. x += alpha p, r -= alpha q, z = r / diag(A'), and the dots r . z, r . r.
-//      The last workgroup forms beta = rz_new / rz and keeps r . r.
-// The "last workgroup" takes a ticket from a device counter after its partial
-// is written and fenced; it reads the partials in index order and resets the
-// counter. The host reads r . r (the recursive residual) every CG_CHECK
-// iterations to test convergence, and the true residual b - A' x of the result
-// is formed once at the end. The two differ by the rounding of the recursive
-// updates and of A' x itself: for the eddy-current matrices, whose stiffness
-// entries grow like h^-2 while A' x stays of the size of b, the true relative
-// residual levels off well above the recursive one (restarting from the true
-// residual was tried: it tripled the iterations without lowering it).
+//      p_new written, and per-workgroup partials of p_new . q;
+//   2. one workgroup adds the partials and forms alpha = rz / (p . q);
+//   3. x += alpha p, r -= alpha q, z = r / diag(A'), partials of r . z, r . r;
+//   4. one workgroup forms beta = rz_new / rz and keeps r . r.
+// The scalars stay on the device. A workgroup takes row chunks g, g + grid, ...
+// (the grids are as large as the rows allow, at most CG_GRID workgroups, so the
+// dependent loads of many rows are in flight at once); a thread adds its
+// contributions in chunk order and the workgroup by a fixed tree, and the
+// partials are added in index order: every dot product has one fixed order for
+// a given n (deterministic). No atomics: a single counter taken by every
+// workgroup of a large grid serialises at the memory side. A row takes G
+// lanes, G = 4, 8 or 16 by the mean row length (2D Nedelec rows have 5
+// entries, 3D Nedelec rows 13 to 27). The CG_CHECK iterations between two
+// convergence tests are captured once in a HIP graph and replayed.
+//
+// The host reads r . r (the recursive residual) every CG_CHECK iterations to
+// test convergence, and the true residual b - A' x of the result is formed
+// once at the end. The two differ by the rounding of the recursive updates and
+// of A' x itself: for the eddy-current matrices, whose stiffness entries grow
+// like h^-2 while A' x stays of the size of b, the true relative residual levels
+// off well above the recursive one (restarting from the true residual was
+// tried: it tripled the iterations without lowering it).
 // ===========================================================================
 namespace fem {
 
 constexpr int CG_BLOCK = 256;
-constexpr int CG_G = 8;                      // lanes per row in the products
-constexpr int CG_ROWS = CG_BLOCK / CG_G;     // rows per chunk of the products
-constexpr int CG_GRID = 2048;
-constexpr int CG_CHECK = 16;
+constexpr int CG_GRID = 8192;                // most workgroups of a grid (partials per dot)
+constexpr int CG_CHECK = 16;                 // iterations per convergence test (even: p buffers alternate)
 
 enum { S_ALPHA = 0, S_BETA, S_RZ, S_RR, S_BB, S_PQ, S_FLAG, S_N };
 
@@ -131,7 +135,6 @@ struct CgArgs {
     double* dinv;
     double* part;      // [3][CG_GRID] workgroup partials
     double* scal;      // [S_N] scalars
-    unsigned* ticket;
 };
 
 __device__ __forceinline__ double cg_block_sum(double v, double* red) {
@@ -147,41 +150,31 @@ __device__ __forceinline__ double cg_block_sum(double v, double* red) {
     return s;
 }
 
-// Writes this workgroup's NV partials, takes a ticket; returns true in the last
-// workgroup, which then sees every partial.
 template <int NV>
-__device__ __forceinline__ bool cg_partials(const CgArgs& C, const double (&v)[NV], double* red) {
-    __shared__ bool s_last;
+__device__ __forceinline__ void cg_partials(const CgArgs& C, const double (&v)[NV], double* red) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const double s = cg_block_sum(v[k], red);
         if (threadIdx.x == 0) C.part[k * CG_GRID + blockIdx.x] = s;
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(C.ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last;
 }
 
-// Sum of partial row k in index order (last workgroup only; all threads).
-__device__ __forceinline__ double cg_total(const CgArgs& C, int k, double* red) {
+// Sum of the first nb partials of row k in index order (one workgroup).
+__device__ __forceinline__ double cg_total(const CgArgs& C, int k, int nb, double* red) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += CG_BLOCK) v += C.part[k * CG_GRID + i];
+    for (int i = threadIdx.x; i < nb; i += CG_BLOCK) v += C.part[k * CG_GRID + i];
     return cg_block_sum(v, red);
 }
 
 // Row i of A' x (G lanes per row: lane j takes entries j, j + G, ...; then a
-// fixed xor tree); x_j = z_j + beta p_j when P is given.
-template <bool FUSED>
+// fixed xor tree); x_j = z_j + beta p_j when FUSED.
+template <int G, bool FUSED>
 __device__ __forceinline__ double cg_row(const CgArgs& C, int64_t i, int j, const double* x, const double* p,
                                          double beta) {
     double sa = 0.0, sb = 0.0;
     if (i < C.n) {
         const int64_t e1 = C.rowptr[i + 1];
-        for (int64_t e = C.rowptr[i] + j; e < e1; e += CG_G) {
+        for (int64_t e = C.rowptr[i] + j; e < e1; e += G) {
             const int32_t c = C.colind[e];
             const double xv = FUSED ? fma(beta, p[c], x[c]) : x[c];
             sa += C.A[e] * xv;
@@ -190,7 +183,7 @@ __device__ __forceinline__ double cg_row(const CgArgs& C, int64_t i, int j, cons
     }
     double s = C.ca * sa + C.cb * sb;
 #pragma unroll
-    for (int m = 1; m < CG_G; m <<= 1) s += __shfl_xor(s, m, CG_G);
+    for (int m = 1; m < G; m <<= 1) s += __shfl_xor(s, m, G);
     return s;
 }
 
@@ -207,17 +200,18 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_diag(const CgArgs C) {
     C.dinv[i] = 1.0 / d;
 }
 
-// r = rhs - A' x, z = r / d, p_old = 0; dots r . z, r . r, rhs . rhs.
+// r = rhs - A' x, z = r / d, p_old = 0; partials of r . z, r . r, rhs . rhs.
 // With FINAL only r . r is formed (true residual of the result).
-template <bool FINAL>
+template <int G, bool FINAL>
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_residual(const CgArgs C, double* p_old) {
+    constexpr int ROWS = CG_BLOCK / G;
     __shared__ double red[CG_BLOCK];
-    const int lr = threadIdx.x / CG_G, j = threadIdx.x % CG_G;
+    const int lr = threadIdx.x / G, j = threadIdx.x % G;
     double rz = 0.0, rr = 0.0, bb = 0.0;
-    const int64_t chunks = (C.n + CG_ROWS - 1) / CG_ROWS;
+    const int64_t chunks = (C.n + ROWS - 1) / ROWS;
     for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
-        const int64_t i = ch * CG_ROWS + lr;
-        const double ax = cg_row<false>(C, i, j, C.x, nullptr, 0.0);
+        const int64_t i = ch * ROWS + lr;
+        const double ax = cg_row<G, false>(C, i, j, C.x, nullptr, 0.0);
         if (i < C.n && j == 0) {
             const double ri = C.rhs[i] - ax;
             rr += ri * ri;
@@ -232,32 +226,21 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_residual(const CgArgs C, double
         }
     }
     const double v[3] = {rz, rr, bb};
-    if (cg_partials<3>(C, v, red)) {
-        const double trz = cg_total(C, 0, red);
-        const double trr = cg_total(C, 1, red);
-        const double tbb = cg_total(C, 2, red);
-        if (threadIdx.x == 0) {
-            C.scal[S_RR] = trr;
-            if (!FINAL) {
-                C.scal[S_RZ] = trz;
-                C.scal[S_BB] = tbb;
-                C.scal[S_BETA] = 0.0;
-            }
-            *C.ticket = 0u;
-        }
-    }
+    cg_partials<3>(C, v, red);
 }
 
-// q = A' (z + beta p_old), p_new = z + beta p_old, alpha = rz / (p_new . q)
+// q = A' (z + beta p_old), p_new = z + beta p_old; partials of p_new . q
+template <int G>
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_product(const CgArgs C, const double* p_old, double* p_new) {
+    constexpr int ROWS = CG_BLOCK / G;
     __shared__ double red[CG_BLOCK];
-    const int lr = threadIdx.x / CG_G, j = threadIdx.x % CG_G;
+    const int lr = threadIdx.x / G, j = threadIdx.x % G;
     const double beta = C.scal[S_BETA];
     double pq = 0.0;
-    const int64_t chunks = (C.n + CG_ROWS - 1) / CG_ROWS;
+    const int64_t chunks = (C.n + ROWS - 1) / ROWS;
     for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
-        const int64_t i = ch * CG_ROWS + lr;
-        const double qi = cg_row<true>(C, i, j, C.z, p_old, beta);
+        const int64_t i = ch * ROWS + lr;
+        const double qi = cg_row<G, true>(C, i, j, C.z, p_old, beta);
         if (i < C.n && j == 0) {
             const double pi = fma(beta, p_old[i], C.z[i]);
             p_new[i] = pi;
@@ -266,22 +249,10 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_product(const CgArgs C, const d
         }
     }
     const double v[1] = {pq};
-    if (cg_partials<1>(C, v, red)) {
-        const double tpq = cg_total(C, 0, red);
-        if (threadIdx.x == 0) {
-            C.scal[S_PQ] = tpq;
-            if (!(tpq > 0.0) || !isfinite(tpq)) {
-                C.scal[S_ALPHA] = 0.0;
-                atomicOr(reinterpret_cast<int*>(C.scal + S_FLAG), 2);
-            } else {
-                C.scal[S_ALPHA] = C.scal[S_RZ] / tpq;
-            }
-            *C.ticket = 0u;
-        }
-    }
+    cg_partials<1>(C, v, red);
 }
 
-// x += alpha p, r -= alpha q, z = r / d; beta = rz_new / rz
+// x += alpha p, r -= alpha q, z = r / d; partials of r . z and r . r
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_update(const CgArgs C, const double* p) {
     __shared__ double red[CG_BLOCK];
     const double alpha = C.scal[S_ALPHA];
@@ -296,18 +267,82 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_update(const CgArgs C, const do
         rr += ri * ri;
     }
     const double v[2] = {rz, rr};
-    if (cg_partials<2>(C, v, red)) {
-        const double trz = cg_total(C, 0, red);
-        const double trr = cg_total(C, 1, red);
+    cg_partials<2>(C, v, red);
+}
+
+// The scalars from the partials of the kernel before (one workgroup).
+enum { CG_AFTER_RESIDUAL = 0, CG_AFTER_FINAL, CG_AFTER_PRODUCT, CG_AFTER_UPDATE };
+template <int STAGE>
+__global__ __launch_bounds__(CG_BLOCK) void k_cg_scalars(const CgArgs C, int nb) {
+    __shared__ double red[CG_BLOCK];
+    if constexpr (STAGE == CG_AFTER_RESIDUAL) {
+        const double trz = cg_total(C, 0, nb, red);
+        const double trr = cg_total(C, 1, nb, red);
+        const double tbb = cg_total(C, 2, nb, red);
+        if (threadIdx.x == 0) {
+            C.scal[S_RZ] = trz;
+            C.scal[S_RR] = trr;
+            C.scal[S_BB] = tbb;
+            C.scal[S_BETA] = 0.0;
+        }
+    } else if constexpr (STAGE == CG_AFTER_FINAL) {
+        const double trr = cg_total(C, 1, nb, red);
+        if (threadIdx.x == 0) C.scal[S_RR] = trr;
+    } else if constexpr (STAGE == CG_AFTER_PRODUCT) {
+        const double tpq = cg_total(C, 0, nb, red);
+        if (threadIdx.x == 0) {
+            C.scal[S_PQ] = tpq;
+            if (!(tpq > 0.0) || !isfinite(tpq)) {
+                C.scal[S_ALPHA] = 0.0;
+                atomicOr(reinterpret_cast<int*>(C.scal + S_FLAG), 2);
+            } else {
+                C.scal[S_ALPHA] = C.scal[S_RZ] / tpq;
+            }
+        }
+    } else {
+        const double trz = cg_total(C, 0, nb, red);
+        const double trr = cg_total(C, 1, nb, red);
         if (threadIdx.x == 0) {
             const double old = C.scal[S_RZ];
             C.scal[S_BETA] = old != 0.0 ? trz / old : 0.0;
             C.scal[S_RZ] = trz;
             C.scal[S_RR] = trr;
-            *C.ticket = 0u;
         }
     }
 }
+
+// Launch helpers (G selected at run time).
+struct CgLaunch {
+    CgArgs C;
+    int G;
+    unsigned grid_rows, grid_elem;
+    hipStream_t s;
+
+    void residual(bool final_, double* p_old) const {
+        const dim3 g(grid_rows), b(CG_BLOCK);
+        if (G == 4) {
+            if (final_) hipLaunchKernelGGL((k_cg_residual<4, true>), g, b, 0, s, C, p_old);
+            else hipLaunchKernelGGL((k_cg_residual<4, false>), g, b, 0, s, C, p_old);
+        } else if (G == 8) {
+            if (final_) hipLaunchKernelGGL((k_cg_residual<8, true>), g, b, 0, s, C, p_old);
+            else hipLaunchKernelGGL((k_cg_residual<8, false>), g, b, 0, s, C, p_old);
+        } else {
+            if (final_) hipLaunchKernelGGL((k_cg_residual<16, true>), g, b, 0, s, C, p_old);
+            else hipLaunchKernelGGL((k_cg_residual<16, false>), g, b, 0, s, C, p_old);
+        }
+        if (final_) hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_FINAL>, dim3(1), b, 0, s, C, (int)grid_rows);
+        else hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_RESIDUAL>, dim3(1), b, 0, s, C, (int)grid_rows);
+    }
+    void iteration(const double* p_old, double* p_new) const {
+        const dim3 g(grid_rows), b(CG_BLOCK);
+        if (G == 4) hipLaunchKernelGGL(k_cg_product<4>, g, b, 0, s, C, p_old, p_new);
+        else if (G == 8) hipLaunchKernelGGL(k_cg_product<8>, g, b, 0, s, C, p_old, p_new);
+        else hipLaunchKernelGGL(k_cg_product<16>, g, b, 0, s, C, p_old, p_new);
+        hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_PRODUCT>, dim3(1), b, 0, s, C, (int)grid_rows);
+        hipLaunchKernelGGL(k_cg_update, dim3(grid_elem), b, 0, s, C, p_new);
+        hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_UPDATE>, dim3(1), b, 0, s, C, (int)grid_elem);
+    }
+};
 
 }  // namespace fem
 
@@ -321,17 +356,35 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     if (!rowptr || !colind || !A || !rhs || !x) return fail(FEM_EINVAL, "fem_cg_solve: NULL argument");
     if (!(rtol >= 0.0) || max_iter < 0) return fail(FEM_EINVAL, "fem_cg_solve: rtol < 0 or max_iter < 0");
     if (x == rhs) return fail(FEM_EINVAL, "fem_cg_solve: x and rhs must not be the same buffer");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t us = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = n_rows;
-    // workspace: r, z, q, p (two), 1/diag, partials, scalars, ticket
+    // workspace: r, z, q, p (two), 1/diag, partials, scalars
     const size_t vec = (size_t)n * sizeof(double);
     const size_t bytes = 6 * vec + 3 * CG_GRID * sizeof(double) + S_N * sizeof(double) + 256;
-    char* ws = nullptr;
-    FEM_HIP(hipMalloc(reinterpret_cast<void**>(&ws), bytes));
-    struct Free {
-        char* p;
-        ~Free() { (void)hipFree(p); }
-    } guard{ws};
+    // The solve runs on a stream of its own (HIP graphs cannot be captured on
+    // the null stream), ordered after the caller's work and before anything
+    // the caller queues next.
+    struct Res {
+        char* ws = nullptr;
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~Res() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (s) (void)hipStreamSynchronize(s);
+            if (ev) (void)hipEventDestroy(ev);
+            if (s) (void)hipStreamDestroy(s);
+            if (ws) (void)hipFree(ws);
+        }
+    } R;
+    FEM_HIP(hipMalloc(reinterpret_cast<void**>(&R.ws), bytes));
+    FEM_HIP(hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
+    FEM_HIP(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
+    FEM_HIP(hipEventRecord(R.ev, us));
+    FEM_HIP(hipStreamWaitEvent(R.s, R.ev, 0));
+    const hipStream_t s = R.s;
     CgArgs C;
     C.n = n;
     C.rowptr = rowptr;
@@ -342,7 +395,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     C.cb = B ? cb : 0.0;
     C.rhs = rhs;
     C.x = x;
-    C.r = reinterpret_cast<double*>(ws);
+    C.r = reinterpret_cast<double*>(R.ws);
     C.z = C.r + n;
     C.q = C.z + n;
     double* p0 = C.q + n;
@@ -350,14 +403,19 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     C.dinv = p1 + n;
     C.part = C.dinv + n;
     C.scal = C.part + 3 * CG_GRID;
-    C.ticket = reinterpret_cast<unsigned*>(C.scal + S_N);
-    FEM_HIP(hipMemsetAsync(C.scal, 0, S_N * sizeof(double) + sizeof(unsigned) * 4, s));
-    const int64_t chunks = (n + CG_ROWS - 1) / CG_ROWS;
-    const unsigned grid_rows = (unsigned)std::min<int64_t>(CG_GRID, chunks);
-    const unsigned grid_elem = (unsigned)std::min<int64_t>(CG_GRID, (n + CG_BLOCK - 1) / CG_BLOCK);
-    const unsigned grid_diag = (unsigned)((n + CG_BLOCK - 1) / CG_BLOCK);
-    hipLaunchKernelGGL(k_cg_diag, dim3(grid_diag), dim3(CG_BLOCK), 0, s, C);
-    hipLaunchKernelGGL(k_cg_residual<false>, dim3(grid_rows), dim3(CG_BLOCK), 0, s, C, p0);
+    FEM_HIP(hipMemsetAsync(C.scal, 0, S_N * sizeof(double), s));
+    // lanes per row from the mean row length
+    int64_t nnz = 0;
+    FEM_HIP(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEM_HIP(hipStreamSynchronize(s));
+    CgLaunch L;
+    L.C = C;
+    L.G = nnz <= 8 * n ? 4 : nnz <= 16 * n ? 8 : 16;
+    L.grid_rows = (unsigned)std::min<int64_t>(CG_GRID, (n + CG_BLOCK / L.G - 1) / (CG_BLOCK / L.G));
+    L.grid_elem = (unsigned)std::min<int64_t>(CG_GRID, (n + CG_BLOCK - 1) / CG_BLOCK);
+    L.s = s;
+    hipLaunchKernelGGL(k_cg_diag, dim3((unsigned)((n + CG_BLOCK - 1) / CG_BLOCK)), dim3(CG_BLOCK), 0, s, C);
+    L.residual(false, p0);
     FEM_HIP(hipGetLastError());
     double host[S_N];
     FEM_HIP(hipMemcpyAsync(host, C.scal, sizeof(host), hipMemcpyDeviceToHost, s));
@@ -371,10 +429,20 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     bool converged = bb == 0.0 || rr <= target;
     while (!converged && it < max_iter) {
         const int64_t steps = std::min<int64_t>(CG_CHECK, max_iter - it);
-        for (int64_t k = 0; k < steps; ++k) {
-            hipLaunchKernelGGL(k_cg_product, dim3(grid_rows), dim3(CG_BLOCK), 0, s, C, p0, p1);
-            hipLaunchKernelGGL(k_cg_update, dim3(grid_elem), dim3(CG_BLOCK), 0, s, C, p1);
-            std::swap(p0, p1);
+        if (steps == CG_CHECK) {
+            // CG_CHECK iterations (an even number, so p ends in p0 again) as one graph
+            if (!R.exec) {
+                FEM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < CG_CHECK; ++k) L.iteration(k % 2 ? p1 : p0, k % 2 ? p0 : p1);
+                FEM_HIP(hipStreamEndCapture(s, &R.graph));
+                FEM_HIP(hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0));
+            }
+            FEM_HIP(hipGraphLaunch(R.exec, s));
+        } else {
+            for (int64_t k = 0; k < steps; ++k) {
+                L.iteration(p0, p1);
+                std::swap(p0, p1);
+            }
         }
         FEM_HIP(hipGetLastError());
         it += steps;
@@ -386,10 +454,13 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
         converged = rr <= target || !std::isfinite(rr);
     }
     // true residual of the result
-    hipLaunchKernelGGL(k_cg_residual<true>, dim3(grid_rows), dim3(CG_BLOCK), 0, s, C, p0);
+    L.residual(true, p0);
     FEM_HIP(hipGetLastError());
     FEM_HIP(hipMemcpyAsync(host, C.scal, sizeof(host), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
+    // work the caller queues next on its stream runs after the solve
+    FEM_HIP(hipEventRecord(R.ev, s));
+    FEM_HIP(hipStreamWaitEvent(us, R.ev, 0));
     if (iters) *iters = it;
     if (rel_resid) *rel_resid = bb > 0.0 ? std::sqrt(host[S_RR] / bb) : 0.0;
     return FEM_OK;

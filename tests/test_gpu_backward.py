@@ -356,6 +356,39 @@ def test_assemble_is_differentiable(case):
         assert err <= GTOL, (nm, err)
 
 
+@pytest.mark.parametrize("case", ["ned3", "rt3"])
+def test_assemble_gradient_of_one_matrix(case):
+    """A loss of K alone (M gets no gradient: it reaches the backward as None,
+    a NULL weight array read as 0, with no zero tensor formed): the gradients
+    equal fem_assemble_backward's with gM = NULL bitwise and the oracle's with
+    gM = 0 within 1e-12."""
+    import torch
+    import paper_1409_4618_amd as fem
+    nodes, elems, kind, a, b, rng = make_case(case, 23)
+    say(f"[gpu] gradient of a loss of K only: {case}")
+    csr, topo = oracle.assemble(nodes, elems, kind, a=a, b=b)
+    wK = rng.normal(size=csr.nnz)
+    zero = np.zeros(csr.nnz)
+    pos = positions(csr, oracle.element_dofs(topo, kind))
+    ga_o, gb_o = grad_coefficients(nodes, elems, kind, topo, pos, wK, zero)
+    gn_o = grad_nodes(nodes, elems, kind, topo, pos, wK, zero, a, b)
+    tn, te, ta, tb = dev_tensors(nodes, elems, a, b)
+    mesh = fem.Mesh(tn, te)
+    tK = torch.tensor(wK, device=tn.device)
+    gn, ga, gb = fem.assemble_backward(mesh, kind, tn, ta, tb, tK, None)
+    leaves = [t.clone().requires_grad_(True) for t in (tn, ta, tb)]
+    K, M = fem.assemble(mesh, kind, *leaves)
+    (tK * K).sum().backward()
+    mesh.status()
+    assert torch.equal(leaves[0].grad, gn) and torch.equal(leaves[1].grad, ga) and torch.equal(leaves[2].grad, gb)
+    assert not gb.any()
+    for got, ref, nm in ((ga, ga_o, "a"), (gn, gn_o, "x")):
+        got = got.cpu().numpy()
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say(f"    dL/d{nm}: max rel err {err:.2e}")
+        assert err <= GTOL, (nm, err)
+
+
 @pytest.mark.parametrize("case", ["ned3", "rt3", "ned2"])
 def test_csr_matvec(case):
     """fem_csr_matvec: alpha K x + beta M x and alpha K x against the oracle
