@@ -512,6 +512,42 @@ def eddy_rate(n=512):
     return out
 
 
+def majorant_rate(n2=1024, n3=48):
+    """The majorant minimisation of Section 4.1 (Algorithm 1) on the unit square
+    (n2 x n2 cells, 2 n2^2 triangles) and the unit cube (Kuhn n3^3): the whole
+    run (P1 assembly, load, boundary elimination and CG; per beta iteration the
+    RT right-hand side, CG on (1 + beta) C^2 K + (1 + 1/beta) M and the majorant
+    terms) timed with HIP events after a warm-up run, and the iterations'
+    beta, majorant and efficiency index (2D: against the paper's printed table)."""
+    import torch
+    import meshgen as mg
+    import paper_1409_4618_amd as fem
+    from paper_1409_4618_amd.majorant import minimise
+    d = torch.device("cuda:0")
+    out = {}
+    for dim, n in ((2, n2), (3, n3)):
+        nodes, elems = mg.unit_square(n) if dim == 2 else mg.kuhn_box(n)
+        tn = torch.tensor(nodes, device=d)
+        mesh = fem.Mesh(tn, torch.tensor(elems, device=d))
+        minimise(mesh, tn)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = minimise(mesh, tn)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{dim}d"] = {"workload": (f"unit square {n}x{n}" if dim == 2 else f"Kuhn {n}^3") +
+                          f" ({elems.shape[0]} elements), bubble solution",
+                          "ms": e0.elapsed_time(e1), "error_grad": r["error"],
+                          "cg_iterations_v": r["cg_iterations_v"],
+                          "iterations": [{"beta": it["beta"], "majorant": it["majorant"], "ieff": it["ieff"],
+                                          "cg_iterations": it["cg_iterations"]} for it in r["iterations"]]}
+    out["2d"]["paper"] = {1024: [(1.000, 0.000412, 1.73), (3.294, 0.000363, 1.52), (3.294, 0.000363, 1.52)],
+                          256: [(1.000, 0.001648, 1.73), (3.294, 0.001453, 1.52), (3.294, 0.001453, 1.52)]}.get(n2)
+    return out
+
+
 def calib_copy():
     """A plain device copy of known size (1 GiB read + 1 GiB written), to scale the
     HBM byte counters of a profiler run."""
@@ -573,6 +609,8 @@ def only_workload(args):
         out = fwd_bwd_rate(mg.kuhn96_ned_grad(), args.steps, args.warmup)
     elif args.only == "eddy":
         out = eddy_rate()
+    elif args.only == "majorant":
+        out = majorant_rate()
     elif args.only == "levels":
         out = {"levels": level_curves(args.steps, args.warmup)}
     else:
@@ -592,7 +630,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (profiler byte-counter calibration)")
     ap.add_argument("--only", choices=["kuhn128_ned3d", "kuhn128_rt3d", "kuhn96_fwd_bwd", "batch256", "eddy",
-                                       "levels"],
+                                       "majorant", "levels"],
                     help="time one secondary workload alone and print its JSON (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -698,6 +736,10 @@ def main():
     log("bench: 2D eddy-current pipeline and norm_L2")
     result["eddy_2d"] = {k: (round(v, 6) if isinstance(v, float) and k.endswith("_ms") else v)
                          for k, v in eddy_rate().items()}
+    torch.cuda.empty_cache()
+
+    log("bench: majorant minimisation")
+    result["majorant"] = majorant_rate()
     torch.cuda.empty_cache()
 
     log("bench: level curves (paper's timing meshes)")

@@ -238,13 +238,21 @@ fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* 
  *                       (Section 4.2): the printed field on x1 > x2, 0 elsewhere
  *   FEM_FN_EDDY_CURL_E  its curl (scalar)
  *   FEM_FN_EDDY_F       its right-hand side F = curl_vec curl E + E (mu = kappa = 1)
- * The eddy functions take no params (NULL, 0) and need dim = 2.
+ *   FEM_FN_BUBBLE_U     the bubble u = prod_i x_i (x_i - 1) of the majorant
+ *                       example (Section 4.1), 2D or 3D (scalar)
+ *   FEM_FN_BUBBLE_GRAD_U  its gradient (dim components)
+ *   FEM_FN_BUBBLE_F     f = -Lap u (scalar)
+ * The eddy and bubble functions take no params (NULL, 0); the eddy functions
+ * need dim = 2.
  */
 typedef enum {
     FEM_FN_POLYNOMIAL = 0,
     FEM_FN_EDDY_E = 1,
     FEM_FN_EDDY_CURL_E = 2,
-    FEM_FN_EDDY_F = 3
+    FEM_FN_EDDY_F = 3,
+    FEM_FN_BUBBLE_U = 4,
+    FEM_FN_BUBBLE_GRAD_U = 5,
+    FEM_FN_BUBBLE_F = 6
 } fem_function;
 
 /* Squared L2 norm ||f||^2 = sum_K int_K |f|^2 (the paper's norm_L2, Section 3.1;
@@ -302,6 +310,76 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
                         const double* A, const double* B, double ca, double cb, const double* rhs,
                         double* x, double rtol, int64_t max_iter, void* stream, int64_t* iters,
                         double* rel_resid);
+
+/* ---------------------------------------------------------------------------
+ * The majorant minimisation of Section 4.1: linear nodal (P1) elements for the
+ * approximation v of -Lap u = f (u = 0 on the boundary), and the
+ * Raviart-Thomas quantities of the majorant functional. The global
+ * Raviart-Thomas basis on an element is phi_k = s_k (x - x_p) / det B_K, p the
+ * vertex opposite local dof k (the Piola image of the printed basis with the
+ * signed determinant, Section 2.1; with the sign data of Section 2.3 its
+ * normal component is continuous), div phi_k = s_k d / det B_K.
+ */
+
+/* Nodal CSR pattern of the P1 stiffness matrix: row i holds node i and its
+ * edge neighbours, columns ascending (n_rows = n_nodes, nnz = n_nodes +
+ * 2 n_edges). Built on first use together with each node's list of element
+ * incidences and the boundary-node flags (nodes of facets that belong to one
+ * element); synchronises `stream`. Borrowed device pointers, valid until
+ * fem_mesh_destroy. FEM_EOVERFLOW if nnz >= 2^31.                          */
+fem_status fem_p1_pattern(fem_mesh mesh, void* stream, int64_t* n_rows, int64_t* nnz,
+                          const int64_t** rowptr, const int32_t** colind);
+
+/* P1 stiffness K_ij = sum_K a_K int_K grad(lambda_i) . grad(lambda_j) on the
+ * pattern of fem_p1_pattern (a NULL = 1). Entry (i, j) is summed over the
+ * elements of edge {i, j}, (i, i) over the elements of node i, each in
+ * ascending element order (deterministic). K dev f64 [nnz] output.
+ * FEM_ENOTREADY before fem_p1_pattern. Asynchronous.                       */
+fem_status fem_p1_assemble(fem_mesh mesh, const double* nodes, const double* a, double* K,
+                           void* stream);
+
+/* P1 load vector F_i = int f lambda_i of a scalar catalogue function, by the
+ * quadrature above; element values summed per node in ascending element
+ * order. F dev f64 [n_nodes] output. Uses the handle's element scratch.
+ * FEM_ENOTREADY before fem_p1_pattern. Asynchronous.                       */
+fem_status fem_p1_load(fem_mesh mesh, const double* nodes, fem_function f, const double* params,
+                       int n_params, int quad_m, double* F, void* stream);
+
+/* Boundary condition v = 0 on the boundary nodes by symmetric elimination:
+ * their rows and columns of K become those of the identity and their entries
+ * of rhs 0 (either pointer may be NULL). FEM_ENOTREADY before fem_p1_pattern.
+ * Asynchronous.                                                             */
+fem_status fem_p1_dirichlet(fem_mesh mesh, double* K, double* rhs, void* stream);
+
+/* Energy error sum_K int_K |g - grad v|^2 of the P1 field v (dev [n_nodes])
+ * against a vector function g (the exact gradient: FEM_FN_BUBBLE_GRAD_U, or a
+ * polynomial); per_elem dev [n_elems] (NULL to skip), total dev [1]. Uses the
+ * handle's scratch of fem_norm_L2. Asynchronous.                           */
+fem_status fem_p1_grad_error(fem_mesh mesh, const double* nodes, const double* v, fem_function g,
+                             const double* params, int n_params, int quad_m, double* per_elem,
+                             double* total, void* stream);
+
+/* Right-hand side of the discrete majorant problem (Section 4.1):
+ *   rhs_i = c_div int f div phi_i + c_grad int grad v . phi_i
+ * over the Raviart-Thomas basis (edges in 2D, faces in 3D), for a scalar
+ * function f and the P1 field v (dev [n_nodes]); the problem of Section 4.1
+ * takes c_div = -(1 + beta) C^2, c_grad = 1 + 1/beta. Element values summed
+ * per dof in ascending element order. rhs dev f64 [n_rows of
+ * fem_pattern(FEM_RAVIART_THOMAS)] output. Uses the handle's element
+ * scratch. Asynchronous.                                                    */
+fem_status fem_rt_majorant_rhs(fem_mesh mesh, const double* nodes, const double* v, fem_function f,
+                               const double* params, int n_params, int quad_m, double c_div,
+                               double c_grad, double* rhs, void* stream);
+
+/* The two terms of the majorant for the P1 field v and the Raviart-Thomas
+ * field y (dof values, dev [n_rows]): terms[0] = ||grad v - y||^2,
+ * terms[1] = ||div y + f||^2 (dev f64 [2] output), each summed in a fixed
+ * order. The majorant is sqrt((1 + 1/beta) terms[0] + (1 + beta) C^2 terms[1])
+ * and the optimal beta sqrt(terms[0]) / (C sqrt(terms[1])). Uses the handle's
+ * scratch of fem_norm_L2. Asynchronous.                                    */
+fem_status fem_majorant_terms(fem_mesh mesh, const double* nodes, const double* v, const double* y,
+                              fem_function f, const double* params, int n_params, int quad_m,
+                              double* terms, void* stream);
 
 /* Synchronises the last stream used with `mesh`, returns and clears the
  * asynchronous device error word (FEM_OK, FEM_EDEGENERATE or FEM_ENONFINITE). */

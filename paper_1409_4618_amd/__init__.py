@@ -16,13 +16,15 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Sequence
 
-from ._lib import (FEM_FN_EDDY_CURL_E, FEM_FN_EDDY_E, FEM_FN_EDDY_F, FEM_FN_POLYNOMIAL, FEM_NEDELEC,
-                   FEM_RAVIART_THOMAS, FemError, check, hip, lib)
+from ._lib import (FEM_FN_BUBBLE_F, FEM_FN_BUBBLE_GRAD_U, FEM_FN_BUBBLE_U, FEM_FN_EDDY_CURL_E, FEM_FN_EDDY_E,
+                   FEM_FN_EDDY_F, FEM_FN_POLYNOMIAL, FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
 __all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
            "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_form", "assemble_quadratic", "csr_matvec",
            "norm_L2", "load_vector", "field_error", "cg_solve", "default_quad_m",
-           "FEM_FN_POLYNOMIAL", "FEM_FN_EDDY_E", "FEM_FN_EDDY_CURL_E", "FEM_FN_EDDY_F"]
+           "FEM_FN_POLYNOMIAL", "FEM_FN_EDDY_E", "FEM_FN_EDDY_CURL_E", "FEM_FN_EDDY_F", "FEM_FN_BUBBLE_U",
+           "FEM_FN_BUBBLE_GRAD_U", "FEM_FN_BUBBLE_F", "p1_pattern", "p1_assemble", "p1_load", "p1_dirichlet",
+           "p1_grad_error", "rt_majorant_rhs", "majorant_terms"]
 
 NED = "ned"
 RT = "rt"
@@ -329,6 +331,100 @@ def cg_solve(rowptr, colind, A, rhs, B=None, ca=1.0, cb=1.0, x0=None, rtol=1e-12
                              _ptr(x), float(rtol), int(10 * n if max_iter is None else max_iter), _stream_ptr(),
                              ctypes.byref(it), ctypes.byref(res)), "fem_cg_solve")
     return x, it.value, res.value
+
+
+def p1_pattern(mesh: Mesh):
+    """(rowptr, colind) copies of the nodal P1 pattern (fem_p1_pattern)."""
+    torch = _torch()
+    cache = mesh.__dict__.setdefault("_p1", None)
+    if cache is None:
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        rp = ctypes.c_void_p()
+        ci = ctypes.c_void_p()
+        check(lib().fem_p1_pattern(mesh.handle, _stream_ptr(), ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(rp),
+                                   ctypes.byref(ci)), "fem_p1_pattern")
+        cache = (_copy_from_device(rp.value, n.value + 1, torch.int64), _copy_from_device(ci.value, nnz.value,
+                                                                                          torch.int32))
+        mesh.__dict__["_p1"] = cache
+    return cache
+
+
+def p1_assemble(mesh: Mesh, nodes, a=None):
+    """P1 stiffness values [nnz] on p1_pattern(mesh) (fem_p1_assemble)."""
+    torch = _torch()
+    rowptr, colind = p1_pattern(mesh)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(a, torch.float64, "a", (mesh.n_elems,))
+    K = torch.empty(colind.numel(), dtype=torch.float64, device=nodes.device)
+    check(lib().fem_p1_assemble(mesh.handle, _ptr(nodes), _ptr(a), _ptr(K), _stream_ptr()), "fem_p1_assemble")
+    return K
+
+
+def p1_load(mesh: Mesh, nodes, fn, params=None, quad_m=None):
+    """F_i = int f lambda_i [n_nodes] (fem_p1_load)."""
+    torch = _torch()
+    p1_pattern(mesh)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    arr, n = _fn_params(params)
+    F = torch.empty(mesh.n_nodes, dtype=torch.float64, device=nodes.device)
+    check(lib().fem_p1_load(mesh.handle, _ptr(nodes), int(fn), arr, n,
+                            default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(F), _stream_ptr()),
+          "fem_p1_load")
+    return F
+
+
+def p1_dirichlet(mesh: Mesh, K=None, rhs=None):
+    """Eliminate the boundary nodes in place (fem_p1_dirichlet)."""
+    torch = _torch()
+    _, colind = p1_pattern(mesh)
+    _check_dev(K, torch.float64, "K", (colind.numel(),))
+    _check_dev(rhs, torch.float64, "rhs", (mesh.n_nodes,))
+    check(lib().fem_p1_dirichlet(mesh.handle, _ptr(K), _ptr(rhs), _stream_ptr()), "fem_p1_dirichlet")
+
+
+def p1_grad_error(mesh: Mesh, nodes, v, fn, params=None, quad_m=None, per_elem=False):
+    """(per-element [T] or None, total 0-dim tensor) of int |g - grad v|^2 (fem_p1_grad_error)."""
+    torch = _torch()
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(v, torch.float64, "v", (mesh.n_nodes,))
+    arr, n = _fn_params(params)
+    per = torch.empty(mesh.n_elems, dtype=torch.float64, device=nodes.device) if per_elem else None
+    tot = torch.empty((), dtype=torch.float64, device=nodes.device)
+    check(lib().fem_p1_grad_error(mesh.handle, _ptr(nodes), _ptr(v), int(fn), arr, n,
+                                  default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(per), _ptr(tot),
+                                  _stream_ptr()), "fem_p1_grad_error")
+    return per, tot
+
+
+def rt_majorant_rhs(mesh: Mesh, nodes, v, fn, c_div, c_grad, params=None, quad_m=None, out=None):
+    """c_div int f div phi_i + c_grad int grad v . phi_i over the RT basis (fem_rt_majorant_rhs)."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(RT)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(v, torch.float64, "v", (mesh.n_nodes,))
+    arr, n = _fn_params(params)
+    rhs = torch.empty(n_rows, dtype=torch.float64, device=nodes.device) if out is None else out
+    _check_dev(rhs, torch.float64, "rhs", (n_rows,))
+    check(lib().fem_rt_majorant_rhs(mesh.handle, _ptr(nodes), _ptr(v), int(fn), arr, n,
+                                    default_quad_m(mesh.dim) if quad_m is None else int(quad_m), float(c_div),
+                                    float(c_grad), _ptr(rhs), _stream_ptr()), "fem_rt_majorant_rhs")
+    return rhs
+
+
+def majorant_terms(mesh: Mesh, nodes, v, y, fn, params=None, quad_m=None):
+    """Device tensor [2]: ||grad v - y||^2 and ||div y + f||^2 (fem_majorant_terms)."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(RT)
+    _check_dev(nodes, torch.float64, "nodes", (mesh.n_nodes, mesh.dim))
+    _check_dev(v, torch.float64, "v", (mesh.n_nodes,))
+    _check_dev(y, torch.float64, "y", (n_rows,))
+    arr, n = _fn_params(params)
+    out = torch.empty(2, dtype=torch.float64, device=nodes.device)
+    check(lib().fem_majorant_terms(mesh.handle, _ptr(nodes), _ptr(v), _ptr(y), int(fn), arr, n,
+                                   default_quad_m(mesh.dim) if quad_m is None else int(quad_m), _ptr(out),
+                                   _stream_ptr()), "fem_majorant_terms")
+    return out
 
 
 def assemble_backward(mesh: Mesh, kind, nodes, a, b, gK, gM, need_a=True, need_b=True,

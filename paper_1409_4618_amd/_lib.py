@@ -22,6 +22,9 @@ FEM_FN_POLYNOMIAL = 0
 FEM_FN_EDDY_E = 1
 FEM_FN_EDDY_CURL_E = 2
 FEM_FN_EDDY_F = 3
+FEM_FN_BUBBLE_U = 4
+FEM_FN_BUBBLE_GRAD_U = 5
+FEM_FN_BUBBLE_F = 6
 
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_EINVAL", 2: "FEM_ERANGE", 3: "FEM_EDEGENERATE",
                 4: "FEM_ENONFINITE", 5: "FEM_EOVERFLOW", 6: "FEM_ENOMEM", 7: "FEM_EHIP",
@@ -55,6 +58,21 @@ SIGNATURES = [
                                     ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, c_int64_p,
                                     ctypes.POINTER(ctypes.c_double)]),
+    ("fem_p1_pattern", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_int64_p, c_int64_p, c_void_pp,
+                                      c_void_pp]),
+    ("fem_p1_assemble", ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    ("fem_p1_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_p1_dirichlet", ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    ("fem_p1_grad_error", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_rt_majorant_rhs", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    ("fem_majorant_terms", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     ("fem_status_query", ctypes.c_int, [ctypes.c_void_p]),
     ("fem_mesh_destroy", None, [ctypes.c_void_p]),
     ("fem_batch_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, c_void_pp]),

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfem.so")
-SOURCES = ["radix_sort.hip", "topology.hip", "assemble.hip", "adjoint.hip", "solve.hip", "integrate.hip", "noalloc.hip", "api.hip"]
+SOURCES = ["radix_sort.hip", "topology.hip", "assemble.hip", "adjoint.hip", "solve.hip", "integrate.hip", "p1.hip", "noalloc.hip", "api.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

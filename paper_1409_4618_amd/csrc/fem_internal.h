@@ -118,6 +118,14 @@ struct fem_mesh_s {
     double* qv_partials = nullptr;   // [ceil(T / 256)] workgroup sums of the quadratic-form value
     double* int_partials = nullptr;  // [ceil(T / 256)] workgroup sums of the integration routines
     double* slot_vals = nullptr;     // [T][nloc] element-local load-vector values
+    // linear nodal (P1) elements (built on first use by fem_p1_pattern)
+    bool p1_built = false;
+    int64_t p1_nnz = 0;
+    int64_t* p1_rowptr = nullptr;    // [V+1] nodal CSR pattern
+    int32_t* p1_colind = nullptr;    // [p1_nnz]
+    int32_t* vs_ptr = nullptr;       // [V+1] incidences (e * (dim+1) + v) of each node,
+    int32_t* vs_slot = nullptr;      // [T*(dim+1)] ascending element order
+    uint8_t* bnd_nodes = nullptr;    // [V] 1 for the nodes of boundary facets
     int32_t* node_ptr = nullptr;     // [V+1] pairs of each node (into bwd_npair)
     int32_t* bwd_npair = nullptr;    // [pairs] pair indices by node, ascending workgroup
     int32_t* bwd_bptr = nullptr;     // [workgroups+1] pairs of each workgroup (pairs are workgroup-major)
@@ -255,6 +263,8 @@ struct FnArgs {
     double p[FEM_POLY_MAX_TERMS * 5];  // polynomial terms: coefficient, component, exponents
 };
 fem_status gauss_legendre01(int m, QuadRule* q);
+// the handle's scratch for fixed-order element sums (2 ceil(T / 256) doubles)
+fem_status ensure_int_partials(fem_mesh m);
 fem_status make_fn_args(fem_function fn, int dim, const double* params, int n_params, FnArgs* F);
 
 fem_status launch_batch(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,

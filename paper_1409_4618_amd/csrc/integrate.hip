@@ -29,10 +29,9 @@
 
 #include "element.h"
 #include "fem_internal.h"
+#include "quad.h"
 
 namespace fem {
-
-constexpr int INT_BLOCK = 256;
 
 // ---------------------------------------------------------------------------
 // quadrature (host)
@@ -114,181 +113,16 @@ fem_status make_fn_args(fem_function fn, int dim, const double* params, int n_pa
             if (dim != 2) return fail(FEM_EINVAL, "the eddy-current functions are two-dimensional");
             F->n_comp = 1;
             return FEM_OK;
+        case FEM_FN_BUBBLE_U:
+        case FEM_FN_BUBBLE_F:
+            F->n_comp = 1;
+            return FEM_OK;
+        case FEM_FN_BUBBLE_GRAD_U:
+            F->n_comp = dim;
+            return FEM_OK;
         default:
             return fail(FEM_EINVAL, "unknown function");
     }
-}
-
-__device__ __forceinline__ double ipow(double x, int e) {
-    double r = 1.0;
-    for (int i = 0; i < e; ++i) r *= x;
-    return r;
-}
-
-// The 2D eddy-current example (Section 4.2) on x1 > x2 (zero elsewhere), with
-// g = x2 (x1 - x2)^2 (x1 - 1)^2 and h = dg/dx1 = 2 x2 A B C,
-// A = x1 - x2, B = x1 - 1, C = 2 x1 - x2 - 1:
-//   E = (sin 2 pi x1 + 2 pi cos(2 pi x1) A,  sin g - sin 2 pi x1),
-//   curl E = dE2/dx1 - dE1/dx2 = h cos g,
-//   F = curl_vec curl E + E = (d(curl E)/dx2 + E1, -d(curl E)/dx1 + E2),
-//   d(curl E)/dx1 = h_1 cos g - h^2 sin g,  d(curl E)/dx2 = h_2 cos g - h g_2 sin g,
-//   h_1 = 2 x2 (B C + A C + 2 A B),  h_2 = 2 (A B C - x2 B C - x2 A B),
-//   g_2 = dg/dx2 = A B^2 (x1 - 3 x2).
-__device__ __forceinline__ void eddy_eval(int fn, double x1, double x2, double* out) {
-    if (!(x1 > x2)) {
-        out[0] = 0.0;
-        out[1] = 0.0;
-        return;
-    }
-    const double A = x1 - x2, B = x1 - 1.0, C = 2.0 * x1 - x2 - 1.0;
-    const double g = x2 * A * A * B * B;
-    const double h = 2.0 * x2 * A * B * C;
-    double sg, cg;
-    sincos(g, &sg, &cg);
-    if (fn == FEM_FN_EDDY_CURL_E) {
-        out[0] = h * cg;
-        return;
-    }
-    double s2, c2;
-    sincospi(2.0 * x1, &s2, &c2);
-    const double E1 = s2 + 2.0 * M_PI * c2 * A;
-    const double E2 = sg - s2;
-    if (fn == FEM_FN_EDDY_E) {
-        out[0] = E1;
-        out[1] = E2;
-        return;
-    }
-    const double h1 = 2.0 * x2 * (B * C + A * C + 2.0 * A * B);
-    const double h2 = 2.0 * (A * B * C - x2 * B * C - x2 * A * B);
-    const double g2 = A * B * B * (x1 - 3.0 * x2);
-    const double dc1 = h1 * cg - h * h * sg;
-    const double dc2 = h2 * cg - h * g2 * sg;
-    out[0] = dc2 + E1;
-    out[1] = -dc1 + E2;
-}
-
-// f at the physical point x (dim coordinates) into out[0 .. n_comp-1].
-template <int DIM>
-__device__ __forceinline__ void eval_fn(const FnArgs& F, const double* x, double* out) {
-    if (F.fn == FEM_FN_POLYNOMIAL) {
-        constexpr int W = 2 + DIM;
-        for (int c = 0; c < F.n_comp; ++c) out[c] = 0.0;
-        for (int t = 0; t < F.n_terms; ++t) {
-            const double* p = F.p + t * W;
-            double v = p[0];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) v *= ipow(x[d], (int)p[2 + d]);
-            out[(int)p[1]] += v;
-        }
-    } else {
-        eddy_eval(F.fn, x[0], x[1], out);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// element geometry for quadrature: vertices, cofactor vectors, J
-template <int DIM>
-struct QElem {
-    double x0[DIM];
-    double B[DIM][DIM];     // columns b_j = x_j - x_0
-    double c[DIM + 1][DIM]; // c_a = J grad lambda_a
-    double J;
-};
-
-template <int DIM>
-__device__ __forceinline__ QElem<DIM> q_elem(const double* nodes, const int* gid) {
-    QElem<DIM> g;
-    double x[DIM + 1][DIM];
-#pragma unroll
-    for (int v = 0; v <= DIM; ++v)
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) x[v][d] = nodes[(int64_t)gid[v] * DIM + d];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) g.x0[d] = x[0][d];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) g.B[d][j] = x[j + 1][d] - x[0][d];
-    if constexpr (DIM == 2) {
-        const V2 b1 = {g.B[0][0], g.B[1][0]}, b2 = {g.B[0][1], g.B[1][1]};
-        g.J = b1.x * b2.y - b1.y * b2.x;
-        g.c[1][0] = b2.y;
-        g.c[1][1] = -b2.x;
-        g.c[2][0] = -b1.y;
-        g.c[2][1] = b1.x;
-    } else {
-        const V3 b1 = {g.B[0][0], g.B[1][0], g.B[2][0]};
-        const V3 b2 = {g.B[0][1], g.B[1][1], g.B[2][1]};
-        const V3 b3 = {g.B[0][2], g.B[1][2], g.B[2][2]};
-        const V3 c1 = cross(b2, b3), c2 = cross(b3, b1), c3 = cross(b1, b2);
-        g.J = dot(b1, c1);
-        g.c[1][0] = c1.x; g.c[1][1] = c1.y; g.c[1][2] = c1.z;
-        g.c[2][0] = c2.x; g.c[2][1] = c2.y; g.c[2][2] = c2.z;
-        g.c[3][0] = c3.x; g.c[3][1] = c3.y; g.c[3][2] = c3.z;
-    }
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double s = 0.0;
-#pragma unroll
-        for (int a = 1; a <= DIM; ++a) s += g.c[a][d];
-        g.c[0][d] = -s;
-    }
-    return g;
-}
-
-// Loop over the points of the conical rule: f(xhat, weight).
-template <int DIM, class Fn>
-__device__ __forceinline__ void for_points(const QuadRule& q, Fn&& f) {
-    if constexpr (DIM == 2) {
-        for (int i = 0; i < q.m; ++i) {
-            const double u = q.x[i];
-            for (int j = 0; j < q.m; ++j) {
-                const double xh[2] = {u, q.x[j] * (1.0 - u)};
-                f(xh, q.w[i] * q.w[j] * (1.0 - u));
-            }
-        }
-    } else {
-        for (int i = 0; i < q.m; ++i) {
-            const double u = q.x[i];
-            for (int j = 0; j < q.m; ++j) {
-                const double v = q.x[j];
-                for (int k = 0; k < q.m; ++k) {
-                    const double xh[3] = {u, v * (1.0 - u), q.x[k] * (1.0 - u) * (1.0 - v)};
-                    f(xh, q.w[i] * q.w[j] * q.w[k] * (1.0 - u) * (1.0 - u) * (1.0 - v));
-                }
-            }
-        }
-    }
-}
-
-template <int DIM>
-__device__ __forceinline__ void phys_point(const QElem<DIM>& g, const double* xh, double* x) {
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double s = g.x0[d];
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) s += g.B[d][j] * xh[j];
-        x[d] = s;
-    }
-}
-
-template <int DIM>
-__device__ __forceinline__ void load_gid(const int32_t* elems, int64_t e, int* gid) {
-#pragma unroll
-    for (int v = 0; v <= DIM; ++v) gid[v] = elems[e * (DIM + 1) + v];
-}
-
-// Fixed-order workgroup sum of v into partials[blockIdx.x].
-__device__ __forceinline__ void block_sum(double v, double* partials) {
-    __shared__ double red[INT_BLOCK];
-    red[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int w = INT_BLOCK / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -489,10 +323,151 @@ __global__ __launch_bounds__(INT_BLOCK) void k_hcurl_error(const int32_t* __rest
     block_sum(acc, partials);
 }
 
-static fem_status ensure_int_partials(fem_mesh m) {
+fem_status ensure_int_partials(fem_mesh m) {
     if (!m->int_partials)
-        FEM_HIP(dmalloc(m, &m->int_partials, std::max<int64_t>(1, (m->T + INT_BLOCK - 1) / INT_BLOCK)));
+        FEM_HIP(dmalloc(m, &m->int_partials, 2 * std::max<int64_t>(1, (m->T + INT_BLOCK - 1) / INT_BLOCK)));
     return FEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Raviart-Thomas quantities of the majorant (Section 4.1). Global basis on an
+// element: phi_k = s_k (x - x_(p_k)) / J with p_k the vertex opposite local dof
+// k (2D: vertex k; 3D: vertex 3 - k) and J = det B_K signed (the
+// contravariant Piola image of the printed basis x^ - p^_k, Section 2.1, with
+// which the sign data make the normal component continuous); div phi_k =
+// s_k d / J.
+template <int DIM>
+__device__ __forceinline__ int rt_opp(int k) { return DIM == 2 ? k : 3 - k; }
+
+template <int DIM>
+__device__ __forceinline__ void rt_signs_of(const int* gid, double* s) {
+    if constexpr (DIM == 2) tri_signs(gid, s);
+    else rt3_signs(gid, s);
+}
+
+// grad v of the P1 field v on the element
+template <int DIM>
+__device__ __forceinline__ void p1_grad(const QElem<DIM>& g, const int* gid, const double* v, double rJ, double* gv) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) t += v[gid[a]] * g.c[a][d];
+        gv[d] = t * rJ;
+    }
+}
+
+// loc[e][k] = c_div int f div phi_k + c_grad int grad v . phi_k
+template <int DIM>
+__global__ __launch_bounds__(INT_BLOCK) void k_rt_majorant_local(const int32_t* __restrict__ elems,
+                                                                  const double* __restrict__ nodes,
+                                                                  const double* __restrict__ v, int64_t T,
+                                                                  const QuadRule q, const FnArgs F, double c_div,
+                                                                  double c_grad, double* __restrict__ loc) {
+    constexpr int NLOC = DIM + 1;
+    const int64_t e = (int64_t)blockIdx.x * INT_BLOCK + threadIdx.x;
+    if (e >= T) return;
+    int gid[DIM + 1];
+    load_gid<DIM>(elems, e, gid);
+    const QElem<DIM> g = q_elem<DIM>(nodes, gid);
+    const double rJ = 1.0 / g.J;
+    double s[NLOC];
+    rt_signs_of<DIM>(gid, s);
+    double gv[DIM];
+    p1_grad<DIM>(g, gid, v, rJ, gv);
+    // vertices x_p = x_0 + B e_p (p >= 1)
+    double fint = 0.0;        // int f over the reference element (times the weights)
+    double gx[NLOC];          // int grad v . (x - x_p) per opposite vertex p
+#pragma unroll
+    for (int k = 0; k < NLOC; ++k) gx[k] = 0.0;
+    for_points<DIM>(q, [&](const double* xh, double w) {
+        double x[DIM], fv[3] = {0.0, 0.0, 0.0};
+        phys_point<DIM>(g, xh, x);
+        eval_fn<DIM>(F, x, fv);
+        fint += w * fv[0];
+        // grad v . (x - x_p): x - x_0 = B xh, x_p - x_0 = B e_p
+        double gB[DIM];  // grad v . b_j
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) t += gv[d] * g.B[d][j];
+            gB[j] = t;
+        }
+        double base = 0.0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) base += gB[j] * xh[j];
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k) {
+            const int p = rt_opp<DIM>(k);
+            gx[k] += w * (p == 0 ? base : base - gB[p - 1]);
+        }
+    });
+    const double aJ = fabs(g.J);
+#pragma unroll
+    for (int k = 0; k < NLOC; ++k)
+        loc[e * NLOC + k] = s[k] * aJ * rJ * (c_div * DIM * fint + c_grad * gx[k]);
+}
+
+// per element ||grad v - y_h||_K^2 and ||div y_h + f||_K^2 into two partial rows
+template <int DIM>
+__global__ __launch_bounds__(INT_BLOCK) void k_majorant_terms(const int32_t* __restrict__ elems,
+                                                               const double* __restrict__ nodes,
+                                                               const int32_t* __restrict__ elems2dofs,
+                                                               const double* __restrict__ v,
+                                                               const double* __restrict__ y, int64_t T,
+                                                               const QuadRule q, const FnArgs F,
+                                                               double* __restrict__ partials, int64_t nb) {
+    constexpr int NLOC = DIM + 1;
+    const int64_t e = (int64_t)blockIdx.x * INT_BLOCK + threadIdx.x;
+    double a2 = 0.0, b2 = 0.0;
+    if (e < T) {
+        int gid[DIM + 1];
+        load_gid<DIM>(elems, e, gid);
+        const QElem<DIM> g = q_elem<DIM>(nodes, gid);
+        const double rJ = 1.0 / g.J;
+        double s[NLOC];
+        rt_signs_of<DIM>(gid, s);
+        double gv[DIM];
+        p1_grad<DIM>(g, gid, v, rJ, gv);
+        double ye[NLOC], ysum = 0.0;
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k) {
+            ye[k] = s[k] * y[elems2dofs[e * NLOC + k]] * rJ;
+            ysum += ye[k];
+        }
+        const double divy = DIM * ysum;
+        // y_h(x) = sum_k ye_k (x - x_(p_k)) = ysum (x - x_0) - sum_k ye_k (x_(p_k) - x_0)
+        double yoff[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NLOC; ++k) {
+                const int p = rt_opp<DIM>(k);
+                if (p > 0) t += ye[k] * g.B[d][p - 1];
+            }
+            yoff[d] = t;
+        }
+        for_points<DIM>(q, [&](const double* xh, double w) {
+            double x[DIM], fv[3] = {0.0, 0.0, 0.0};
+            phys_point<DIM>(g, xh, x);
+            eval_fn<DIM>(F, x, fv);
+            double t = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const double yh = ysum * (x[d] - g.x0[d]) - yoff[d];
+                t += (gv[d] - yh) * (gv[d] - yh);
+            }
+            a2 += w * t;
+            b2 += w * (divy + fv[0]) * (divy + fv[0]);
+        });
+        const double aJ = fabs(g.J);
+        a2 *= aJ;
+        b2 *= aJ;
+    }
+    block_sum(a2, partials);
+    block_sum(b2, partials + nb);
 }
 
 static unsigned int_grid(int64_t n) { return (unsigned)((n + INT_BLOCK - 1) / INT_BLOCK); }
@@ -578,6 +553,59 @@ fem_status fem_field_error(fem_mesh m, fem_kind kind, const double* nodes, const
                            m->edges.elems2dofs, v, m->T, q, FE, FC, per_elem, m->int_partials, m->err_word);
     FEM_HIP(hipGetLastError());
     return launch_sum_partials(m->int_partials, grid, total, s);
+}
+
+fem_status fem_rt_majorant_rhs(fem_mesh m, const double* nodes, const double* v, fem_function f,
+                               const double* params, int n_params, int quad_m, double c_div, double c_grad,
+                               double* rhs, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_rt_majorant_rhs: mesh is NULL");
+    if (!nodes || !v || !rhs) return fail(FEM_EINVAL, "fem_rt_majorant_rhs: nodes, v or rhs is NULL");
+    QuadRule q;
+    if (fem_status st = gauss_legendre01(quad_m, &q)) return st;
+    FnArgs F;
+    if (fem_status st = make_fn_args(f, m->dim, params, n_params, &F)) return st;
+    if (F.n_comp != 1) return fail(FEM_EINVAL, "fem_rt_majorant_rhs: f must be scalar");
+    DofSet& ds = m->dim == 3 ? m->faces : m->edges;
+    if (!m->slot_vals) FEM_HIP(dmalloc(m, &m->slot_vals, (size_t)m->T * m->edges.nloc));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    const unsigned grid = int_grid(m->T);
+    if (m->dim == 3)
+        hipLaunchKernelGGL(k_rt_majorant_local<3>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, v, m->T, q, F,
+                           c_div, c_grad, m->slot_vals);
+    else
+        hipLaunchKernelGGL(k_rt_majorant_local<2>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, v, m->T, q, F,
+                           c_div, c_grad, m->slot_vals);
+    FEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dof_sum, dim3(int_grid(ds.n)), dim3(INT_BLOCK), 0, s, ds.rs_ptr, ds.rs_slot, m->slot_vals,
+                       ds.n, rhs);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
+fem_status fem_majorant_terms(fem_mesh m, const double* nodes, const double* v, const double* y, fem_function f,
+                              const double* params, int n_params, int quad_m, double* terms, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_majorant_terms: mesh is NULL");
+    if (!nodes || !v || !y || !terms) return fail(FEM_EINVAL, "fem_majorant_terms: NULL argument");
+    QuadRule q;
+    if (fem_status st = gauss_legendre01(quad_m, &q)) return st;
+    FnArgs F;
+    if (fem_status st = make_fn_args(f, m->dim, params, n_params, &F)) return st;
+    if (F.n_comp != 1) return fail(FEM_EINVAL, "fem_majorant_terms: f must be scalar");
+    if (fem_status st = ensure_int_partials(m)) return st;
+    DofSet& ds = m->dim == 3 ? m->faces : m->edges;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    const unsigned grid = int_grid(m->T);
+    if (m->dim == 3)
+        hipLaunchKernelGGL(k_majorant_terms<3>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, ds.elems2dofs, v,
+                           y, m->T, q, F, m->int_partials, (int64_t)grid);
+    else
+        hipLaunchKernelGGL(k_majorant_terms<2>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, ds.elems2dofs, v,
+                           y, m->T, q, F, m->int_partials, (int64_t)grid);
+    FEM_HIP(hipGetLastError());
+    if (fem_status st = launch_sum_partials(m->int_partials, grid, terms, s)) return st;
+    return launch_sum_partials(m->int_partials + grid, grid, terms + 1, s);
 }
 
 }  // extern "C"
