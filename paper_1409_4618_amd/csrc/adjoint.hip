@@ -524,8 +524,8 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     // anyway). For the other kinds the extra LDS would cost occupancy.
     constexpr bool SLOTS = MODE != BWD_QUADRATIC && KC == 2;
     __shared__ double sh[NINC * DIM];
-    __shared__ uint16_t s_inc[NINC];
-    __shared__ uint16_t s_pst[NINC];
+    __shared__ uint32_t s_inc_w[NINC / 2];          // incidences, two u16 per word
+    __shared__ uint32_t s_pst_w[NINC / 2 + 64];     // pair starts, from the even index at or below the first
     __shared__ int32_t s_base[SLOTS ? BWD_BLOCK * NLOC : 1];
     __shared__ uint64_t s_cp[SLOTS ? BWD_BLOCK * NLOC : 1];
     // XCD-aware element order: workgroup b runs on XCD b % 8, so give each XCD
@@ -538,25 +538,47 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     const int64_t e = e0 + threadIdx.x;
     const bool live = e < A.T;
     const int n_inc = (int)((A.T - e0 < BWD_BLOCK ? A.T - e0 : BWD_BLOCK) * NV);
+    const int lane = (int)threadIdx.x & 63;
+    const int wave0 = (int)threadIdx.x & ~63;  // first lane of the wavefront (uniform)
     int pb0 = 0, np = 0;
+    const uint16_t* s_inc = reinterpret_cast<const uint16_t*>(s_inc_w);
+    const uint16_t* s_pst = reinterpret_cast<const uint16_t*>(s_pst_w);
     if (A.partials) {
-        // the workgroup's part of the node map, into LDS first: its loads are
-        // in flight while the elements are computed
+        // The workgroup's part of the node map goes straight from memory into
+        // LDS (global_load_lds: no registers, no wait before the barrier that
+        // precedes its use), so its loads are in flight while the elements
+        // are computed. Words past the list's end read the last word again.
         pb0 = A.bptr[blk];
         np = A.bptr[blk + 1] - pb0;
         const uint32_t* w = reinterpret_cast<const uint32_t*>(A.inc + e0 * NV);  // 4-byte aligned: e0 * NV is even
-        for (int i = (int)threadIdx.x; 2 * i < n_inc; i += BWD_BLOCK)
-            reinterpret_cast<uint32_t*>(s_inc)[i] = w[i];
-        for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) s_pst[j] = A.pst[pb0 + j];
+        const int n_w = (n_inc + 1) / 2;
+        for (int j = wave0; j < n_w; j += BWD_BLOCK)
+            __builtin_amdgcn_global_load_lds(w + min(j + lane, n_w - 1),
+                                             (__attribute__((address_space(3))) void*)(s_inc_w + j), 4, 0, 0);
+        // pair starts from the even u16 index at or below pb0 (the list has
+        // one u16 of padding, so the last word read is in bounds)
+        const uint32_t* wp = reinterpret_cast<const uint32_t*>(A.pst + (pb0 & ~1));
+        const int n_pw = (np + (pb0 & 1) + 1) / 2;
+        for (int j = wave0; j < n_pw; j += BWD_BLOCK)
+            __builtin_amdgcn_global_load_lds(wp + min(j + lane, n_pw - 1),
+                                             (__attribute__((address_space(3))) void*)(s_pst_w + j), 4, 0, 0);
+        s_pst += pb0 & 1;
     }
     if constexpr (SLOTS) {
         // the workgroup's slot records are contiguous (element-major): one
-        // coalesced pass into LDS instead of a dependent load per row
+        // pass into LDS (as above) instead of a dependent load per row
         const int n_sl = n_inc / NV * NLOC;
-        for (int i = (int)threadIdx.x; i < n_sl; i += BWD_BLOCK) {
-            s_base[i] = A.slot_base[e0 * NLOC + i];
-            s_cp[i] = A.slot_cp[e0 * NLOC + i];
-        }
+        const uint32_t* wb = reinterpret_cast<const uint32_t*>(A.slot_base + e0 * NLOC);
+        const uint32_t* wc = reinterpret_cast<const uint32_t*>(A.slot_cp + e0 * NLOC);
+        uint32_t* lb = reinterpret_cast<uint32_t*>(s_base);
+        uint32_t* lc = reinterpret_cast<uint32_t*>(s_cp);
+        for (int j = wave0; j < n_sl; j += BWD_BLOCK)
+            __builtin_amdgcn_global_load_lds(wb + min(j + lane, n_sl - 1),
+                                             (__attribute__((address_space(3))) void*)(lb + j), 4, 0, 0);
+        for (int j = wave0; j < 2 * n_sl; j += BWD_BLOCK)
+            __builtin_amdgcn_global_load_lds(wc + min(j + lane, 2 * n_sl - 1),
+                                             (__attribute__((address_space(3))) void*)(lc + j), 4, 0, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
     const SlotView sv = SLOTS ? SlotView{s_base + (int)threadIdx.x * NLOC, s_cp + (int)threadIdx.x * NLOC}
@@ -567,6 +589,8 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
         else bwd_tri<MODE>(A, e, sv, sh);
     }
     if (!A.partials) return;  // uniform
+    // the node map's loads into LDS are complete in every wavefront
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     // one partial per (vertex, workgroup): the workgroup's incidences of that
     // vertex, in ascending element order; incidence (lane, v) sits at

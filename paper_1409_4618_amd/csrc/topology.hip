@@ -707,9 +707,9 @@ fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
 //       (e - b*BWD_BLOCK)*(dim+1) + v, sorted by (node, element);
 //   bwd_bptr [workgroups+1]: the pairs of workgroup b are bptr[b] .. bptr[b+1],
 //       in ascending node order; pair q's partial is partials[q];
-//   bwd_pst [pairs] u16: the workgroup-local position in bwd_inc of the first
-//       incidence of each pair (the pair ends where the next one starts, or at
-//       the end of the workgroup's incidences);
+//   bwd_pst [pairs + 1] u16: the workgroup-local position in bwd_inc of the
+//       first incidence of each pair (the pair ends where the next one starts,
+//       or at the end of the workgroup's incidences); one u16 of padding;
 //   node_ptr [V+1], bwd_npair [pairs]: the pairs of each node, ascending
 //       workgroup.
 __global__ void k_inc_wg_keys(const int32_t* elems, int64_t n, int nv, int64_t V, uint64_t* keys,
@@ -784,7 +784,7 @@ fem_status build_node_map(fem_mesh m, hipStream_t s) {
     int64_t P = 0;
     if (fem_status st = read_count(tb.scan, tb.keys, n, s, &P)) return st;
     m->bwd_pairs = P;
-    FEM_HIP(st.alloc(&m->bwd_pst, P));
+    FEM_HIP(st.alloc(&m->bwd_pst, P + 1));  // +1: read as 32-bit words
     FEM_HIP(st.alloc(&m->bwd_npair, P));
     // node keys of the pairs, in the (now free) tmp key/value space after the
     // incidence keys: P <= n entries each
