@@ -80,6 +80,17 @@ __device__ __forceinline__ void gather_row(const BwdArgs& A, const SlotView& sv,
     }
 }
 
+// The element's coefficients (a NULL array reads the constant 1), loaded
+// without a branch and at the start of the element's work: a conditional load
+// sits in a block of its own, and the wait for it comes at the end of that
+// block, a memory round trip of its own.
+__device__ const double kUnitCoefficient = 1.0;
+__device__ __forceinline__ double2 load_coeffs(const BwdArgs& A, int64_t e) {
+    const double* pa = A.a ? A.a + e : &kUnitCoefficient;
+    const double* pb = A.b ? A.b + e : &kUnitCoefficient;
+    return make_double2(*pa, *pb);
+}
+
 // u at the element's dofs (quadratic mode only)
 template <int NLOC, int MODE>
 __device__ __forceinline__ void load_u(const BwdArgs& A, int64_t e, double ue[NLOC]) {
@@ -117,6 +128,7 @@ __device__ __forceinline__ void store_vertex2(double* sh, int v, double dx, doub
 // the cofactor vectors) and d|J| = |J| tr(B^-1 dB).
 template <int MODE>
 __device__ double2 bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+    const double2 cab = load_coeffs(A, e);
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -264,8 +276,8 @@ __device__ double2 bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, dou
     const double J = dot(b1, c[1]);
     const double aJ = fabs(J);
     const double rJ = 1.0 / J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
-    const double ca = A.a ? A.a[e] : 1.0;
-    const double cb = A.b ? A.b[e] : 1.0;
+    const double ca = cab.x;
+    const double cb = cab.y;
     const double2 gab = make_double2((2.0 / 3.0) * Phi * arJ, (1.0 / 120.0) * Psi * arJ);
     if (A.ga) A.ga[e] = gab.x;
     if (A.gb) A.gb[e] = gab.y;
@@ -293,6 +305,7 @@ __device__ double2 bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, dou
 // 3D Raviart-Thomas
 template <int MODE>
 __device__ double2 bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+    const double2 cab = load_coeffs(A, e);
     int gid[4];
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
@@ -355,8 +368,8 @@ __device__ double2 bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, doub
 #pragma unroll
     for (int p = 1; p < 4; ++p) ru += rho[p] * g.u[p];
     const double Omega = hM * g.base - 5.0 * ru + 20.0 * cross_term;
-    const double ca = A.a ? A.a[e] : 1.0;
-    const double cb = A.b ? A.b[e] : 1.0;
+    const double ca = cab.x;
+    const double cb = cab.y;
     const double rJ = 1.0 / g.J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
     const double2 gab = make_double2(1.5 * hK * arJ, (1.0 / 120.0) * Omega * arJ);
     if (A.ga) A.ga[e] = gab.x;
@@ -391,6 +404,7 @@ __device__ double2 bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, doub
 // 2D (both kinds)
 template <int MODE>
 __device__ double2 bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, double* sh) {
+    const double2 cab = load_coeffs(A, e);
     int gid[3];
     V2 x[3];
 #pragma unroll
@@ -486,8 +500,8 @@ __device__ double2 bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, doub
             }
         }
     }
-    const double ca = A.a ? A.a[e] : 1.0;
-    const double cb = A.b ? A.b[e] : 1.0;
+    const double ca = cab.x;
+    const double cb = cab.y;
     const double rJ = 1.0 / g.J, arJ = fabs(rJ);  // the one division; |1/J| = 1/|J| exactly
     const double2 gab = make_double2(2.0 * hK * arJ, (1.0 / 24.0) * Psi * arJ);
     if (A.ga) A.ga[e] = gab.x;
@@ -651,9 +665,8 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_quadratic_value(const BwdArgs A, 
         if constexpr (KC == 2) g = bwd_ned3<BWD_QUADRATIC>(A, e, sv, nullptr);
         else if constexpr (KC == 1) g = bwd_rt3<BWD_QUADRATIC>(A, e, sv, nullptr);
         else g = bwd_tri<BWD_QUADRATIC>(A, e, sv, nullptr);
-        const double ca = A.a ? A.a[e] : 1.0;
-        const double cb = A.b ? A.b[e] : 1.0;
-        v = ca * g.x + cb * g.y;
+        const double2 cab = load_coeffs(A, e);
+        v = cab.x * g.x + cab.y * g.y;
     }
     red[threadIdx.x] = v;
     __syncthreads();
