@@ -264,20 +264,44 @@ def fwd_bwd_rate(p, steps, warmup):
 
 def small_mesh_latency(steps, warmup):
     """The 2D 32x32 unit square (2,048 triangles, unit coefficients): launch-bound,
-    so reported as microseconds per assembly, direct launch and HIP-graph replay
-    (a one-mesh batch)."""
+    so reported as microseconds per assembly: direct launch, fem_assemble
+    captured in a HIP graph (one assembly per replay, and 16 per replay), and
+    the one-mesh persistent batch kernel's graph."""
+    import torch
     import meshgen as mg
     import paper_1409_4618_amd as fem
     p = mg.square_ned32()
     s = setup_mesh(p)
     run = lambda: fem.assemble_into(s["mesh"], p.kind, s["nodes"], None, None, s["K"], s["M"])
     us_direct = timed(run, steps, warmup) * 1e3
+
+    def capture(n):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(n):
+                run()
+        torch.cuda.synchronize()
+        return g
+
+    g1, g16 = capture(1), capture(16)
+    us_graph = timed(g1.replay, steps, warmup) * 1e3
+    us_graph16 = timed(g16.replay, steps, warmup) * 1e3 / 16
     B = fem.Batch([s["mesh"]], [p.kind])
     B.bind([s["nodes"]], [None], [None], [s["K"]], [s["M"]])
-    us_graph = timed(B.graph_launch, steps, warmup) * 1e3
+    us_batch = timed(B.graph_launch, steps, warmup) * 1e3
     s["mesh"].status()
     return {"workload": "square32_ned2d: 2D Nedelec K+M, unit square 32x32 (2,048 triangles), unit coefficients",
-            "us_direct": us_direct, "us_graph": us_graph, "nnz": s["nnz"]}
+            "us_direct": us_direct, "us_graph": us_graph, "us_graph_x16_per_assembly": us_graph16,
+            "us_batch_kernel_graph": us_batch, "nnz": s["nnz"],
+            "note": "us_graph: fem_assemble captured in a HIP graph (torch.cuda.CUDAGraph), one replay per "
+                    "assembly; us_graph_x16_per_assembly: 16 assemblies captured in one graph; "
+                    "us_batch_kernel_graph: the one-mesh persistent batch kernel's graph"}
 
 
 def batched_rate(steps, warmup, ref_mtets, scale=1.0):
@@ -613,6 +637,8 @@ def only_workload(args):
         out = majorant_rate()
     elif args.only == "levels":
         out = {"levels": level_curves(args.steps, args.warmup)}
+    elif args.only == "small2d":
+        out = small_mesh_latency(args.steps, args.warmup)
     else:
         out = batched_rate(args.steps, args.warmup, None)
     if args.calib_copy:
@@ -630,7 +656,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (profiler byte-counter calibration)")
     ap.add_argument("--only", choices=["kuhn128_ned3d", "kuhn128_rt3d", "kuhn96_fwd_bwd", "batch256", "eddy",
-                                       "majorant", "levels"],
+                                       "majorant", "levels", "small2d"],
                     help="time one secondary workload alone and print its JSON (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
