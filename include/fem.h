@@ -66,8 +66,11 @@ typedef struct fem_batch_s* fem_batch;
 
 typedef enum {
     FEM_NEDELEC = 0,         /* H(curl): curl-curl stiffness + mass, dofs on edges        */
-    FEM_RAVIART_THOMAS = 1   /* H(div): div-div stiffness + mass, dofs on edges (2D) /
+    FEM_RAVIART_THOMAS = 1,  /* H(div): div-div stiffness + mass, dofs on edges (2D) /
                                 faces (3D)                                                 */
+    FEM_KIND_RANGE_MIN = -0x7FFFFFFF - 1,  /* not kinds: they widen the enum to the range of
+    FEM_KIND_RANGE_MAX = 0x7FFFFFFF         int, so any int a caller passes is a valid value
+                                            (and rejected with FEM_EINVAL)                    */
 } fem_kind;
 
 typedef enum {
@@ -252,7 +255,9 @@ typedef enum {
     FEM_FN_EDDY_F = 3,
     FEM_FN_BUBBLE_U = 4,
     FEM_FN_BUBBLE_GRAD_U = 5,
-    FEM_FN_BUBBLE_F = 6
+    FEM_FN_BUBBLE_F = 6,
+    FEM_FN_RANGE_MIN = -0x7FFFFFFF - 1,  /* not functions: they widen the enum to the range
+    FEM_FN_RANGE_MAX = 0x7FFFFFFF         of int (any other value is rejected with FEM_EINVAL) */
 } fem_function;
 
 /* Squared L2 norm ||f||^2 = sum_K int_K |f|^2 (the paper's norm_L2, Section 3.1;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fem_internal.h"
+#include "tune_cache.h"
 
 namespace fem {
 
@@ -416,44 +417,6 @@ static std::string device_name() {
     for (char& c : n)
         if (c == '"' || c == '\n') c = '_';
     return n + "-cu" + std::to_string(p.multiProcessorCount);
-}
-
-// Cache file: one JSON object per line,
-// {"device": "...", "signature": "...", "rows_per_tile": R, "schedule": S, "ms": t}
-static bool cache_lookup(const char* path, const std::string& dev, const std::string& sig, int* R,
-                         int* sched) {
-    if (!path) return false;
-    std::ifstream f(path);
-    if (!f) return false;
-    std::string line;
-    bool found = false;
-    while (std::getline(f, line)) {
-        if (line.find("\"device\": \"" + dev + "\"") == std::string::npos) continue;
-        if (line.find("\"signature\": \"" + sig + "\"") == std::string::npos) continue;
-        const size_t pr = line.find("\"rows_per_tile\": ");
-        const size_t ps = line.find("\"schedule\": ");
-        if (pr == std::string::npos || ps == std::string::npos) continue;
-        const int r = std::atoi(line.c_str() + pr + 17);
-        const int sc = std::atoi(line.c_str() + ps + 12);
-        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2) {
-            *R = r;
-            *sched = sc;
-            found = true;  // last matching line wins
-        }
-    }
-    return found;
-}
-
-static void cache_store(const char* path, const std::string& dev, const std::string& sig, int R,
-                        int sched, double ms) {
-    if (!path) return;
-    std::ofstream f(path, std::ios::app);
-    if (!f) return;
-    char buf[512];
-    std::snprintf(buf, sizeof(buf),
-                  "{\"device\": \"%s\", \"signature\": \"%s\", \"rows_per_tile\": %d, \"schedule\": %d, \"ms\": %.6f}\n",
-                  dev.c_str(), sig.c_str(), R, sched, ms);
-    f << buf;
 }
 
 }  // namespace fem
