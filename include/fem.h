@@ -410,26 +410,35 @@ fem_status fem_batch_bind(fem_batch batch, const double* const* nodes,
                           const double* const* a, const double* const* b,
                           double* const* K_vals, double* const* M_vals);
 
-/* Autotuner: times every candidate (tiling, schedule) with the bound
- * buffers on `stream`, keeps the fastest, and records it in the JSON cache file
+/* Autotuner: times every candidate (tiling with its workgroup size, schedule)
+ * with the bound buffers on `stream`: element-major tiles of 256 and of 128
+ * lanes, row tiles of 64/128/256 rows, each with the three schedules. Keeps
+ * the fastest, and records it in the JSON cache file
  * `cache_path` (NULL = no file). If the file already holds an entry for this
  * device and batch signature, that entry is used without timing. Synchronises. */
 fem_status fem_batch_tune(fem_batch batch, const char* cache_path, void* stream);
 
 /* Which configuration the batch uses (host outputs, may be NULL):
  * tiling, schedule (0 static, 1 dynamic queue, 2 LPT-sorted dynamic queue),
- * number of work items, persistent grid size. Tiling (`rows_per_tile`):
- *   0            element-major tiles of 256-lane workgroups, rows per tile
- *                chosen per mesh (the default when every mesh's tile element
- *                lists fit a workgroup);
- *   64, 128, 256 row tiles of that many rows, one or more lanes per row.    */
-fem_status fem_batch_config(fem_batch batch, int* rows_per_tile, int* schedule,
+ * workgroup size, number of work items, persistent grid size. Tiling
+ * (`rows_per_tile`):
+ *   0            element-major tiles, one element per lane, in workgroups of
+ *                `threads` lanes (128 or 256: the elements per tile and the
+ *                wavefronts per workgroup); rows per tile chosen per mesh so
+ *                that a tile's element list fits its workgroup (the default,
+ *                with 256, when every mesh's tiles fit);
+ *   64, 128, 256 row tiles of that many rows, one or more lanes per row, in
+ *                workgroups of 256 lanes (`threads` = 256).                 */
+fem_status fem_batch_config(fem_batch batch, int* rows_per_tile, int* schedule, int* threads,
                             int64_t* n_work, int* grid);
 
 /* Select a configuration by hand (skips tuning). FEM_EINVAL for a tiling
- * outside {0, 64, 128, 256} (or 0 when element-major tiles are unavailable)
- * or a schedule outside 0..2.                                               */
-fem_status fem_batch_set_config(fem_batch batch, int rows_per_tile, int schedule);
+ * outside {0, 64, 128, 256} (or 0 when element-major tiles are unavailable),
+ * a schedule outside 0..2, or `threads` other than 128/256 for element-major
+ * tiles and 0/256 for row tiles. The 128-lane element-major tiles are built on
+ * first use (device allocations; synchronises the device); FEM_EINVAL if some
+ * mesh's tiles do not fit 128 lanes.                                          */
+fem_status fem_batch_set_config(fem_batch batch, int rows_per_tile, int schedule, int threads);
 
 /* One persistent launch over all bound meshes. Asynchronous; contains no
  * memset or allocation, so it may be captured into a HIP graph. Launches of

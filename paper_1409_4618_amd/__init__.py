@@ -654,17 +654,21 @@ class Batch:
         p = None if cache_path is None else cache_path.encode()
         check(lib().fem_batch_tune(self._h, p, _stream_ptr()), "fem_batch_tune")
 
-    def set_config(self, rows_per_tile: int, schedule: int):
-        check(lib().fem_batch_set_config(self._h, rows_per_tile, schedule), "fem_batch_set_config")
+    def set_config(self, rows_per_tile: int, schedule: int, threads: int = 256):
+        """Tiling (0 = element-major, or 64/128/256 rows), schedule (0..2) and,
+        for element-major tiles, the workgroup size (128 or 256)."""
+        check(lib().fem_batch_set_config(self._h, rows_per_tile, schedule, threads), "fem_batch_set_config")
 
     def config(self):
         R = ctypes.c_int()
         s = ctypes.c_int()
+        t = ctypes.c_int()
         nw = ctypes.c_int64()
         g = ctypes.c_int()
-        check(lib().fem_batch_config(self._h, ctypes.byref(R), ctypes.byref(s), ctypes.byref(nw),
+        check(lib().fem_batch_config(self._h, ctypes.byref(R), ctypes.byref(s), ctypes.byref(t), ctypes.byref(nw),
                                      ctypes.byref(g)), "fem_batch_config")
-        return {"rows_per_tile": R.value, "schedule": s.value, "n_work": nw.value, "grid": g.value}
+        return {"rows_per_tile": R.value, "schedule": s.value, "threads": t.value, "n_work": nw.value,
+                "grid": g.value}
 
     def assemble(self):
         check(lib().fem_batch_assemble(self._h, _stream_ptr()), "fem_batch_assemble")

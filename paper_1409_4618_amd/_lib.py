@@ -79,9 +79,9 @@ SIGNATURES = [
     ("fem_batch_bind", ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 5),
     ("fem_batch_tune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p]),
     ("fem_batch_config", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
-                                        ctypes.POINTER(ctypes.c_int), c_int64_p,
-                                        ctypes.POINTER(ctypes.c_int)]),
-    ("fem_batch_set_config", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                        c_int64_p, ctypes.POINTER(ctypes.c_int)]),
+    ("fem_batch_set_config", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("fem_batch_assemble", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("fem_batch_graph_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("fem_batch_destroy", None, [ctypes.c_void_p]),

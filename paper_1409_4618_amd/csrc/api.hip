@@ -290,7 +290,9 @@ struct fem_batch_s {
     int grid = 0;
     int pmax = 0;
     int lds_bytes = 0;      // element-major tiles: largest tile LDS over the meshes
-    bool ema_ok = false;    // every mesh has usable element-major tiles
+    bool ema_ok = false;    // every mesh has usable element-major tiles (256 lanes)
+    int nt = 256;           // element-major tiles: workgroup size, 128 or 256
+    int ema128 = -1;        // 128-lane tiles: -1 not built yet, 0 unusable, 1 usable
     bool work_valid = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -308,9 +310,27 @@ static void drop_graph(fem_batch B) {
     B->graph_valid = false;
 }
 
+// Element-major tiles of 128-lane workgroups for every mesh (built on first
+// use, by the tuner or a configuration that asks for them).
+static fem_status ensure_ema128(fem_batch B) {
+    if (B->ema128 >= 0) return FEM_OK;
+    bool ok = true;
+    for (size_t i = 0; i < B->meshes.size(); ++i) {
+        DofSet& ds = dofset(B->meshes[i], B->kinds[i]);
+        if (fem_status st = build_ema(B->meshes[i], ds, 128, nullptr)) return st;
+        ok = ok && ds.pat.ema[ema_index(128)].usable && !B->meshes[i]->nonconforming;
+    }
+    B->ema128 = ok ? 1 : 0;
+    return FEM_OK;
+}
+
 static fem_status build_work(fem_batch B) {
     const bool ema = B->R == 0;
     if (ema && !B->ema_ok) return fail(FEM_EINVAL, "fem_batch: element-major tiles unavailable for this batch");
+    if (ema && B->nt == 128) {
+        if (fem_status st = ensure_ema128(B)) return st;
+        if (B->ema128 != 1) return fail(FEM_EINVAL, "fem_batch: 128-lane element-major tiles unavailable for this batch");
+    }
     // an earlier launch of this batch, on any stream, may still be reading the
     // work list and the mesh table that are rewritten below
     FEM_HIP(hipDeviceSynchronize());
@@ -325,7 +345,7 @@ static fem_status build_work(fem_batch B) {
     for (size_t i = 0; i < B->meshes.size(); ++i) {
         fem_mesh m = B->meshes[i];
         DofSet& ds = dofset(m, B->kinds[i]);
-        const Pattern::Ema& E = ds.pat.ema[ema_index(256)];
+        const Pattern::Ema& E = ds.pat.ema[ema_index(B->nt)];
         const int R = ema ? E.R : B->R;
         const int64_t nt = ema ? E.n_tiles : (ds.pat.n_rows + R - 1) / R;
         if (ema)
@@ -362,7 +382,7 @@ static fem_status build_work(fem_batch B) {
     if (ema) {
         if (B->lds_bytes > lds_limit_bytes())
             return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
-        per_cu = batch_ema_blocks_per_cu(B->lds_bytes);
+        per_cu = batch_ema_blocks_per_cu(B->lds_bytes, B->nt);
     } else {
         const int bytes = B->pmax * 16;
         if (bytes > lds_limit_bytes())
@@ -373,7 +393,7 @@ static fem_status build_work(fem_batch B) {
     // rebuild the device table with the tiling of this configuration
     for (size_t i = 0; i < B->host_table.size(); ++i) {
         MeshDev& md = B->host_table[i];
-        if (ema) fill_ema(dofset(B->meshes[i], B->kinds[i]), 256, &md);
+        if (ema) fill_ema(dofset(B->meshes[i], B->kinds[i]), B->nt, &md);
         else md.n_tiles = (md.n_rows + B->R - 1) / B->R;
     }
     if (B->bound)
@@ -485,21 +505,26 @@ fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double*
     return build_work(B);  // sets the tiling fields of the table and uploads it
 }
 
-fem_status fem_batch_set_config(fem_batch B, int R, int schedule) {
+fem_status fem_batch_set_config(fem_batch B, int R, int schedule, int threads) {
     if (!B) return fail(FEM_EINVAL, "fem_batch_set_config: batch is NULL");
     if ((R != 0 && R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > 2)
         return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 0/64/128/256, schedule 0..2");
+    if (R == 0 ? (threads != 128 && threads != 256) : (threads != 0 && threads != 256))
+        return fail(FEM_EINVAL, "fem_batch_set_config: threads must be 128 or 256 for element-major tiles, "
+                                "0 or 256 for row tiles");
     if (R == 0 && !B->ema_ok)
         return fail(FEM_EINVAL, "fem_batch_set_config: element-major tiles unavailable for this batch");
     B->R = R;
     B->schedule = schedule;
+    B->nt = R == 0 ? threads : 256;
     return build_work(B);
 }
 
-fem_status fem_batch_config(fem_batch B, int* R, int* schedule, int64_t* n_work, int* grid) {
+fem_status fem_batch_config(fem_batch B, int* R, int* schedule, int* threads, int64_t* n_work, int* grid) {
     if (!B) return fail(FEM_EINVAL, "fem_batch_config: batch is NULL");
     if (R) *R = B->R;
     if (schedule) *schedule = B->schedule;
+    if (threads) *threads = B->nt;
     if (n_work) *n_work = B->n_work;
     if (grid) *grid = B->grid;
     return FEM_OK;
@@ -512,7 +537,7 @@ fem_status fem_batch_assemble(fem_batch B, void* stream) {
         if (fem_status st = build_work(B)) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (B->R == 0)
-        return launch_batch_ema(B->table_dev, B->work_dev, B->n_work, B->schedule, B->grid, B->lds_bytes,
+        return launch_batch_ema(B->table_dev, B->work_dev, B->n_work, B->schedule, B->grid, B->lds_bytes, B->nt,
                                 B->counters, s);
     return launch_batch(B->table_dev, B->work_dev, B->n_work, B->R, B->schedule, B->grid, B->pmax,
                         B->counters, s);
@@ -523,11 +548,11 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     if (!B->bound) return fail(FEM_ENOTREADY, "fem_batch_tune: call fem_batch_bind first");
     const std::string dev = device_name();
     const std::string sig = batch_signature(B);
-    int R = 0, sc = 0;
+    int R = 0, sc = 0, nt = 256;
     // A cached configuration that this batch cannot use (element-major tiles
     // unavailable, a tile too large for LDS) is ignored: the search below runs.
-    if (cache_lookup(cache_path, dev, sig, &R, &sc) && (R != 0 || B->ema_ok) &&
-        fem_batch_set_config(B, R, sc) == FEM_OK)
+    if (cache_lookup(cache_path, dev, sig, &R, &sc, &nt) && (R != 0 || B->ema_ok) &&
+        fem_batch_set_config(B, R, sc, R == 0 ? nt : 256) == FEM_OK)
         return FEM_OK;
     g_last_error.clear();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -542,11 +567,15 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     FEM_HIP(hipEventCreate(&ev.e1));
     const hipEvent_t e0 = ev.e0, e1 = ev.e1;
     double best = 1e30;
-    int bestR = B->ema_ok ? 0 : 128, bestS = 1;
-    const int Rs[4] = {0, 64, 128, 256};
-    for (int ri = B->ema_ok ? 0 : 1; ri < 4; ++ri) {
+    int bestR = B->ema_ok ? 0 : 128, bestS = 1, bestT = 256;
+    // tilings: element-major tiles of 256 and of 128 lanes (the elements per
+    // tile and the wavefronts per workgroup), then row tiles of 64/128/256 rows
+    const int Rs[5] = {0, 0, 64, 128, 256};
+    const int Ts[5] = {256, 128, 256, 256, 256};
+    for (int ri = B->ema_ok ? 0 : 2; ri < 5; ++ri) {
         for (int sched = 0; sched < 3; ++sched) {
             B->R = Rs[ri];
+            B->nt = Ts[ri];
             B->schedule = sched;
             if (build_work(B) != FEM_OK) continue;  // e.g. tile too large for LDS
             bool ok = true;
@@ -565,11 +594,13 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
                 best = t;
                 bestR = Rs[ri];
                 bestS = sched;
+                bestT = Ts[ri];
             }
         }
     }
-    fem_status st = fem_batch_set_config(B, bestR, bestS);
-    if (st == FEM_OK) cache_store(cache_path, dev, sig, bestR, bestS, best);
+    g_last_error.clear();
+    fem_status st = fem_batch_set_config(B, bestR, bestS, bestT);
+    if (st == FEM_OK) cache_store(cache_path, dev, sig, bestR, bestS, bestT, best);
     return st;
 }
 

@@ -793,23 +793,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_
     }
 }
 
-fem_status launch_batch_ema(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
-                            int grid, int lds_bytes, unsigned* counters, hipStream_t s) {
-    if (n_work == 0) return FEM_OK;
-    if (lds_bytes > lds_limit_bytes())
-        return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
-    FEM_HIP(set_lds(k_batch_ema<256>, lds_bytes));
-    hipLaunchKernelGGL((k_batch_ema<256>), dim3((unsigned)grid), dim3(256), lds_bytes, s, table, work,
-                       n_work, schedule, counters);
+template <int NT>
+static fem_status launch_batch_ema_t(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
+                                     int grid, int lds_bytes, unsigned* counters, hipStream_t s) {
+    FEM_HIP(set_lds(k_batch_ema<NT>, lds_bytes));
+    hipLaunchKernelGGL((k_batch_ema<NT>), dim3((unsigned)grid), dim3(NT), lds_bytes, s, table, work, n_work,
+                       schedule, counters);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
 
-int batch_ema_blocks_per_cu(int lds_bytes) {
+fem_status launch_batch_ema(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
+                            int grid, int lds_bytes, int nt, unsigned* counters, hipStream_t s) {
+    if (n_work == 0) return FEM_OK;
+    if (lds_bytes > lds_limit_bytes())
+        return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
+    if (nt == 128)
+        return launch_batch_ema_t<128>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
+    return launch_batch_ema_t<256>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
+}
+
+int batch_ema_blocks_per_cu(int lds_bytes, int nt) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_ema<256>, 256, lds_bytes) != hipSuccess ||
-        n <= 0)
-        n = 1;
+    const hipError_t e =
+        nt == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_ema<128>, 128, lds_bytes)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_ema<256>, 256, lds_bytes);
+    if (e != hipSuccess || n <= 0) n = 1;
     return n;
 }
 

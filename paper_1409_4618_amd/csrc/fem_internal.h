@@ -276,9 +276,10 @@ int cu_count();
 int default_rows_per_tile(int kind_code);
 fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s);
 // batched element-major tiles (workgroups of 256 lanes)
+// nt: workgroup size of the element-major tiles (128 or 256)
 fem_status launch_batch_ema(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
-                            int schedule, int grid, int lds_bytes, unsigned* counters,
+                            int schedule, int grid, int lds_bytes, int nt, unsigned* counters,
                             hipStream_t s);
-int batch_ema_blocks_per_cu(int lds_bytes);
+int batch_ema_blocks_per_cu(int lds_bytes, int nt);
 
 }  // namespace fem

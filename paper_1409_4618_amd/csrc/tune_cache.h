@@ -2,10 +2,12 @@
 // the host-only sanitizer check of its parsing.
 //
 // One JSON object per line,
-//   {"device": "...", "signature": "...", "rows_per_tile": R, "schedule": S, "ms": t}
+//   {"device": "...", "signature": "...", "rows_per_tile": R, "schedule": S, "threads": N, "ms": t}
 // A lookup takes the last line whose device and signature match and whose
-// rows per tile (0, 64, 128, 256) and schedule (0-2) are valid; malformed,
-// truncated or foreign lines are skipped. A store appends one line.
+// rows per tile (0, 64, 128, 256), schedule (0-2) and threads (128 or 256 for
+// element-major tiles, 256 for row tiles; 256 when the field is absent) are
+// valid; malformed, truncated or foreign lines are skipped. A store appends
+// one line.
 #pragma once
 
 #include <cstdio>
@@ -38,7 +40,7 @@ inline bool cache_field(const std::string& line, const char* key, int* out) {
 }
 
 inline bool cache_lookup(const char* path, const std::string& dev, const std::string& sig, int* R,
-                         int* sched) {
+                         int* sched, int* threads) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -49,12 +51,16 @@ inline bool cache_lookup(const char* path, const std::string& dev, const std::st
     while (std::getline(f, line)) {
         if (line.find(kd) == std::string::npos) continue;
         if (line.find(ks) == std::string::npos) continue;
-        int r = -1, sc = -1;
+        int r = -1, sc = -1, nt = 256;
         if (!cache_field(line, "\"rows_per_tile\": ", &r) || !cache_field(line, "\"schedule\": ", &sc))
             continue;
-        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2) {
+        if (line.find("\"threads\": ") != std::string::npos && !cache_field(line, "\"threads\": ", &nt))
+            continue;
+        const bool nt_ok = r == 0 ? (nt == 128 || nt == 256) : nt == 256;
+        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2 && nt_ok) {
             *R = r;
             *sched = sc;
+            *threads = nt;
             found = true;  // last matching line wins
         }
     }
@@ -62,7 +68,7 @@ inline bool cache_lookup(const char* path, const std::string& dev, const std::st
 }
 
 inline void cache_store(const char* path, const std::string& dev, const std::string& sig, int R, int sched,
-                        double ms) {
+                        int threads, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     if (!f) return;
@@ -70,7 +76,7 @@ inline void cache_store(const char* path, const std::string& dev, const std::str
     // characters that need no JSON escaping); the line length is not bounded
     // by a fixed buffer
     f << "{\"device\": \"" << dev << "\", \"signature\": \"" << sig << "\", \"rows_per_tile\": " << R
-      << ", \"schedule\": " << sched << ", \"ms\": ";
+      << ", \"schedule\": " << sched << ", \"threads\": " << threads << ", \"ms\": ";
     char buf[64];
     std::snprintf(buf, sizeof(buf), "%.6f", ms);
     f << buf << "}\n";

@@ -31,9 +31,9 @@ static void write_file(const std::string& path, const std::string& text) {
 
 static void check_cache(const std::string& dir) {
     const std::string p = dir + "/cache.jsonl";
-    int R = -7, S = -7;
-    CHECK(!fem::cache_lookup(nullptr, "dev", "sig", &R, &S));
-    CHECK(!fem::cache_lookup((dir + "/missing.jsonl").c_str(), "dev", "sig", &R, &S));
+    int R = -7, S = -7, N = -7;
+    CHECK(!fem::cache_lookup(nullptr, "dev", "sig", &R, &S, &N));
+    CHECK(!fem::cache_lookup((dir + "/missing.jsonl").c_str(), "dev", "sig", &R, &S, &N));
     std::string junk;
     junk += "\n";                                              // empty line
     junk += "{\"device\": \"dev\", \"signature\": \"sig\", \"rows_per_tile\": ";  // truncated
@@ -44,24 +44,31 @@ static void check_cache(const std::string& dir) {
     junk += "{\"device\": \"dev\", \"signature\": \"sig\", \"rows_per_tile\": x, \"schedule\": 0}\n";
     junk += "{\"device\": \"other\", \"signature\": \"sig\", \"rows_per_tile\": 256, \"schedule\": 2}\n";
     junk += "{\"device\": \"dev\", \"signature\": \"sig2\", \"rows_per_tile\": 256, \"schedule\": 2}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 0, \"schedule\": 1, \"threads\": 128}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 64, \"schedule\": 1, \"threads\": 128}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 0, \"schedule\": 0, \"threads\": 512}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 0, \"schedule\": 0, \"threads\": }\n";
     junk += std::string(200000, 'z') + "\n";                  // a long line
     junk += std::string("\0\x01\xff", 3) + "\n";              // binary bytes
     junk += "{\"device\": \"dev\", \"signature\": \"sig\", \"rows_per_tile\": 0, \"schedule\": 2, \"ms\": 0.5}";  // no newline
     write_file(p, junk);
-    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig", &R, &S));
-    CHECK(R == 0 && S == 2);  // the last valid matching line wins
-    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig2", &R, &S) && R == 256 && S == 2);
-    CHECK(!fem::cache_lookup(p.c_str(), "dev", "nosuch", &R, &S));
+    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig", &R, &S, &N));
+    CHECK(R == 0 && S == 2 && N == 256);  // the last valid matching line wins; no threads field: 256
+    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig2", &R, &S, &N) && R == 256 && S == 2);
+    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig3", &R, &S, &N) && R == 0 && S == 1 && N == 128);
+    CHECK(!fem::cache_lookup(p.c_str(), "dev", "nosuch", &R, &S, &N));
     // store, then read back
     const std::string q = dir + "/store.jsonl";
     write_file(q, "");
     const std::string longsig(5000, 'a');
-    fem::cache_store(q.c_str(), "gfx950-cu256", longsig, 128, 1, 0.123456);
-    fem::cache_store(q.c_str(), "gfx950-cu256", "s", 64, 0, 1e300);
-    fem::cache_store(nullptr, "d", "s", 64, 0, 1.0);
+    fem::cache_store(q.c_str(), "gfx950-cu256", longsig, 128, 1, 256, 0.123456);
+    fem::cache_store(q.c_str(), "gfx950-cu256", "s", 64, 0, 256, 1e300);
+    fem::cache_store(q.c_str(), "gfx950-cu256", "t", 0, 2, 128, 0.5);
+    fem::cache_store(nullptr, "d", "s", 64, 0, 256, 1.0);
     R = S = -1;
-    CHECK(fem::cache_lookup(q.c_str(), "gfx950-cu256", longsig, &R, &S) && R == 128 && S == 1);
-    CHECK(fem::cache_lookup(q.c_str(), "gfx950-cu256", "s", &R, &S) && R == 64 && S == 0);
+    CHECK(fem::cache_lookup(q.c_str(), "gfx950-cu256", longsig, &R, &S, &N) && R == 128 && S == 1);
+    CHECK(fem::cache_lookup(q.c_str(), "gfx950-cu256", "s", &R, &S, &N) && R == 64 && S == 0 && N == 256);
+    CHECK(fem::cache_lookup(q.c_str(), "gfx950-cu256", "t", &R, &S, &N) && R == 0 && S == 2 && N == 128);
     int v = 0;
     CHECK(!fem::cache_field("\"k\": ", "\"k\": ", &v));
     CHECK(fem::cache_field("\"k\": 12x", "\"k\": ", &v) && v == 12);
@@ -156,7 +163,7 @@ static void check_abi() {
     CHECK(fem_batch_create(nullptr, nullptr, 3, &b) == FEM_EINVAL && b == nullptr);
     CHECK(fem_batch_create(nullptr, nullptr, 0, nullptr) == FEM_EINVAL);
     CHECK(fem_batch_tune(nullptr, nullptr, nullptr) == FEM_EINVAL);
-    CHECK(fem_batch_set_config(nullptr, 64, 0) == FEM_EINVAL);
+    CHECK(fem_batch_set_config(nullptr, 64, 0, 256) == FEM_EINVAL);
     CHECK(fem_status_query(nullptr) == FEM_EINVAL);
     fem_mesh_destroy(nullptr);
     fem_batch_destroy(nullptr);

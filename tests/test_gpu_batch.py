@@ -47,19 +47,19 @@ def test_single_meshes_match_oracle(batch_setup):
         assert rel_fro(M.cpu().numpy(), csr.Mv) <= TOL
 
 
-@pytest.mark.parametrize("rows", [0, 64, 128, 256])
+@pytest.mark.parametrize("rows,threads", [(0, 256), (0, 128), (64, 256), (128, 256), (256, 256)])
 @pytest.mark.parametrize("schedule", [0, 1, 2])
-def test_batch_equals_single_launches(batch_setup, rows, schedule):
+def test_batch_equals_single_launches(batch_setup, rows, threads, schedule):
     import torch
     import paper_1409_4618_amd as fem
     probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
-    say(f"[gpu] batch rows={rows} schedule={schedule}")
+    say(f"[gpu] batch rows={rows} threads={threads} schedule={schedule}")
     B = fem.Batch(meshes, kinds)
     for K, M in zip(Ks, Ms):
         K.fill_(float("nan"))
         M.fill_(float("nan"))
     B.bind(nodes, a, b, Ks, Ms)
-    B.set_config(rows, schedule)
+    B.set_config(rows, schedule, threads)
     B.assemble()
     B.assemble()  # the device work counter resets itself between launches
     torch.cuda.synchronize()
@@ -67,17 +67,24 @@ def test_batch_equals_single_launches(batch_setup, rows, schedule):
         assert torch.equal(K, Kr) and torch.equal(M, Mr)
     cfg = B.config()
     assert cfg["rows_per_tile"] == rows and cfg["schedule"] == schedule and cfg["grid"] >= 1
+    assert cfg["threads"] == threads
+    if rows == 64 and schedule == 0:
+        # workgroup sizes that do not go with the tiling are refused on the host
+        for bad in ((64, 0, 128), (0, 0, 64), (0, 0, 0), (128, 1, 512)):
+            with pytest.raises(fem.FemError):
+                B.set_config(*bad)
+        assert B.config()["rows_per_tile"] == 64
 
 
-@pytest.mark.parametrize("rows", [0, 128])
-def test_graph_replay_equals_direct(batch_setup, rows):
+@pytest.mark.parametrize("rows,threads", [(0, 256), (0, 128), (128, 256)])
+def test_graph_replay_equals_direct(batch_setup, rows, threads):
     import torch
     import paper_1409_4618_amd as fem
     probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
-    say(f"[gpu] batch graph replays, rows={rows}")
+    say(f"[gpu] batch graph replays, rows={rows} threads={threads}")
     B = fem.Batch(meshes, kinds)
     B.bind(nodes, a, b, Ks, Ms)
-    B.set_config(rows, 1)
+    B.set_config(rows, 1, threads)
     for rep in range(3):
         for K, M in zip(Ks, Ms):
             K.zero_()
@@ -105,12 +112,14 @@ def test_autotuner_and_cache(batch_setup, tmp_path):
     assert len(lines) == 1
     rec = json.loads(lines[0])
     assert rec["rows_per_tile"] == cfg["rows_per_tile"] and rec["schedule"] == cfg["schedule"]
+    assert rec["threads"] == cfg["threads"] and cfg["threads"] in (128, 256)
     # a second batch with the same signature reads the cache instead of timing
     B2 = fem.Batch(meshes, kinds)
     B2.bind(nodes, a, b, Ks, Ms)
     B2.set_config(64 if cfg["rows_per_tile"] != 64 else 128, 0)
     B2.tune(cache)
     assert B2.config()["rows_per_tile"] == cfg["rows_per_tile"]
+    assert B2.config()["threads"] == cfg["threads"] and B2.config()["schedule"] == cfg["schedule"]
     assert len(open(cache).read().strip().splitlines()) == 1
     B2.assemble()
     torch.cuda.synchronize()
