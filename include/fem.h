@@ -307,7 +307,7 @@ fem_status fem_field_error(fem_mesh mesh, fem_kind kind, const double* nodes, co
  *          relative residual ||rhs - A' x|| / ||rhs|| of the returned x, formed
  *          at the end (it can stay above rtol by the rounding of A' x)
  * Deterministic: every dot product is summed in one fixed order. Allocates its
- * workspace (6 n_rows + 24615 doubles) for the call and synchronises `stream`.
+ * workspace (6 n_rows + 8229 doubles) for the call and synchronises `stream`.
  * FEM_EINVAL for bad arguments or a non-positive diagonal entry; FEM_EHIP if
  * the iteration breaks down (p . A' p <= 0). Reaching max_iter is not an
  * error: check rel_resid.                                                   */

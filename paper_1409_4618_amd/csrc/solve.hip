@@ -86,23 +86,26 @@ fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* 
 // eddy-current problem of Section 4.2, whose matrix K + M is symmetric
 // positive definite).
 //
-// One iteration is four kernels:
+// One iteration is two kernels:
 //   1. q = A' p_new with p_new = z + beta p_old formed on the fly (the update
 //      of p fused into the product; p_old and p_new are separate buffers),
 //      p_new written, and per-workgroup partials of p_new . q;
-//   2. one workgroup adds the partials and forms alpha = rz / (p . q);
-//   3. x += alpha p, r -= alpha q, z = r / diag(A'), partials of r . z, r . r;
-//   4. one workgroup forms beta = rz_new / rz and keeps r . r.
-// The scalars stay on the device. A workgroup takes row chunks g, g + grid, ...
-// (the grids are as large as the rows allow, at most CG_GRID workgroups, so the
-// dependent loads of many rows are in flight at once); a thread adds its
-// contributions in chunk order and the workgroup by a fixed tree, and the
-// partials are added in index order: every dot product has one fixed order for
-// a given n (deterministic). No atomics: a single counter taken by every
-// workgroup of a large grid serialises at the memory side. A row takes G
-// lanes, G = 4, 8 or 16 by the mean row length (2D Nedelec rows have 5
-// entries, 3D Nedelec rows 13 to 27). The CG_CHECK iterations between two
-// convergence tests are captured once in a HIP graph and replayed.
+//   2. x += alpha p, r -= alpha q, z = r / diag(A'), partials of r . z, r . r.
+// Neither scalar has a kernel of its own: every workgroup of a kernel adds the
+// partials of the kernel before (at most CG_GRID of them, 16 KB) in the same
+// fixed order and forms the scalar itself, so all of them hold the same value
+// (beta = rz_k / rz_(k-1) in the product, alpha = rz_k / (p . q) in the
+// update). rz_k, which the update needs after the product's partials of it
+// are gone, is kept by workgroup 0 of the product in one of two slots chosen
+// by the parity of the iteration (the other slot, rz_(k-1), is being read by
+// the product's other workgroups). A workgroup takes row chunks g, g + grid,
+// ...; a thread adds its contributions in chunk order and the workgroup by a
+// fixed tree (wavefront butterflies, then the four wavefront sums): every dot
+// product has one fixed order for a given n (deterministic). No atomics on
+// the sums.
+// A row takes G lanes, G = 4, 8 or 16 by the mean row length (2D Nedelec rows
+// have 5 entries, 3D Nedelec rows 13 to 27). The CG_CHECK iterations between
+// two convergence tests are captured once in a HIP graph and replayed.
 //
 // The host reads r . r (the recursive residual) every CG_CHECK iterations to
 // test convergence, and the true residual b - A' x of the result is formed
@@ -115,10 +118,16 @@ fem_status fem_csr_matvec(int64_t n_rows, const int64_t* rowptr, const int32_t* 
 namespace fem {
 
 constexpr int CG_BLOCK = 256;
-constexpr int CG_GRID = 8192;                // most workgroups of a grid (partials per dot)
+// Most workgroups of a grid, and so of partials per dot product: eight per CU
+// on 256 CUs, about what is resident at once. Every workgroup of the next
+// kernel adds all of them (16 KB), so more would cost more in those sums than
+// it gains in loads in flight: at 787,456 rows an iteration took 62 us with the
+// scalars in kernels of their own, and 51, 44, 56 and 55 us with 1024, 2048,
+// 3072 and 4096 workgroups (512: 67 us).
+constexpr int CG_GRID = 2048;
 constexpr int CG_CHECK = 16;                 // iterations per convergence test (even: p buffers alternate)
 
-enum { S_ALPHA = 0, S_BETA, S_RZ, S_RR, S_BB, S_PQ, S_FLAG, S_N };
+enum { S_RZ0 = 0, S_RZ1, S_RR, S_BB, S_FLAG, S_N };
 
 struct CgArgs {
     int64_t n;
@@ -133,36 +142,38 @@ struct CgArgs {
     double* z;
     double* q;
     double* dinv;
-    double* part;      // [3][CG_GRID] workgroup partials
+    double* part;      // [3][CG_GRID] partials of the residual and update kernels (r.z, r.r, b.b)
+    double* part_pq;   // [CG_GRID] partials of the product kernel (p.q)
     double* scal;      // [S_N] scalars
 };
 
+// Sum over the workgroup, the same value in every thread: a butterfly within
+// each wavefront (lane 0's order), then the four wavefront sums in a fixed
+// order. red: 4 doubles of LDS.
 __device__ __forceinline__ double cg_block_sum(double v, double* red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
 #pragma unroll
-    for (int w = CG_BLOCK / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double s = red[0];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double s = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return s;
 }
 
 template <int NV>
-__device__ __forceinline__ void cg_partials(const CgArgs& C, const double (&v)[NV], double* red) {
+__device__ __forceinline__ void cg_partials(double* part, const double (&v)[NV], double* red) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const double s = cg_block_sum(v[k], red);
-        if (threadIdx.x == 0) C.part[k * CG_GRID + blockIdx.x] = s;
+        if (threadIdx.x == 0) part[k * CG_GRID + blockIdx.x] = s;
     }
 }
 
-// Sum of the first nb partials of row k in index order (one workgroup).
-__device__ __forceinline__ double cg_total(const CgArgs& C, int k, int nb, double* red) {
+// Sum of the first nb partials of one row in index order per thread, then the
+// fixed tree: every workgroup gets the same value.
+__device__ __forceinline__ double cg_total(const double* part, int nb, double* red) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += CG_BLOCK) v += C.part[k * CG_GRID + i];
+    for (int i = threadIdx.x; i < nb; i += CG_BLOCK) v += part[i];
     return cg_block_sum(v, red);
 }
 
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_diag(const CgArgs C) {
 template <int G, bool FINAL>
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_residual(const CgArgs C, double* p_old) {
     constexpr int ROWS = CG_BLOCK / G;
-    __shared__ double red[CG_BLOCK];
+    __shared__ double red[4];
     const int lr = threadIdx.x / G, j = threadIdx.x % G;
     double rz = 0.0, rr = 0.0, bb = 0.0;
     const int64_t chunks = (C.n + ROWS - 1) / ROWS;
@@ -226,16 +237,22 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_residual(const CgArgs C, double
         }
     }
     const double v[3] = {rz, rr, bb};
-    cg_partials<3>(C, v, red);
+    cg_partials<3>(C.part, v, red);
 }
 
-// q = A' (z + beta p_old), p_new = z + beta p_old; partials of p_new . q
+// q = A' (z + beta p_old), p_new = z + beta p_old; partials of p_new . q.
+// beta = rz_k / rz_(k-1): rz_k from the partials of the kernel before (nb of
+// them), rz_(k-1) from slot 1 - par; workgroup 0 keeps rz_k in slot par.
 template <int G>
-__global__ __launch_bounds__(CG_BLOCK) void k_cg_product(const CgArgs C, const double* p_old, double* p_new) {
+__global__ __launch_bounds__(CG_BLOCK) void k_cg_product(const CgArgs C, const double* p_old, double* p_new,
+                                                         int par, int nb) {
     constexpr int ROWS = CG_BLOCK / G;
-    __shared__ double red[CG_BLOCK];
+    __shared__ double red[4];
     const int lr = threadIdx.x / G, j = threadIdx.x % G;
-    const double beta = C.scal[S_BETA];
+    const double rz = cg_total(C.part, nb, red);
+    const double rz_prev = C.scal[S_RZ0 + (1 - par)];
+    const double beta = rz_prev != 0.0 ? rz / rz_prev : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) C.scal[S_RZ0 + par] = rz;
     double pq = 0.0;
     const int64_t chunks = (C.n + ROWS - 1) / ROWS;
     for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
@@ -249,13 +266,17 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_product(const CgArgs C, const d
         }
     }
     const double v[1] = {pq};
-    cg_partials<1>(C, v, red);
+    cg_partials<1>(C.part_pq, v, red);
 }
 
-// x += alpha p, r -= alpha q, z = r / d; partials of r . z and r . r
-__global__ __launch_bounds__(CG_BLOCK) void k_cg_update(const CgArgs C, const double* p) {
-    __shared__ double red[CG_BLOCK];
-    const double alpha = C.scal[S_ALPHA];
+// alpha = rz_k / (p . q) from the product's partials (nb of them) and slot
+// par; x += alpha p, r -= alpha q, z = r / d; partials of r . z and r . r.
+__global__ __launch_bounds__(CG_BLOCK) void k_cg_update(const CgArgs C, const double* p, int par, int nb) {
+    __shared__ double red[4];
+    const double pq = cg_total(C.part_pq, nb, red);
+    const bool ok = pq > 0.0 && isfinite(pq);
+    const double alpha = ok ? C.scal[S_RZ0 + par] / pq : 0.0;
+    if (!ok && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<int*>(C.scal + S_FLAG), 2);
     double rz = 0.0, rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * CG_BLOCK + threadIdx.x; i < C.n; i += (int64_t)gridDim.x * CG_BLOCK) {
         C.x[i] = fma(alpha, p[i], C.x[i]);
@@ -267,51 +288,35 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_update(const CgArgs C, const do
         rr += ri * ri;
     }
     const double v[2] = {rz, rr};
-    cg_partials<2>(C, v, red);
+    cg_partials<2>(C.part, v, red);
 }
 
-// The scalars from the partials of the kernel before (one workgroup).
-enum { CG_AFTER_RESIDUAL = 0, CG_AFTER_FINAL, CG_AFTER_PRODUCT, CG_AFTER_UPDATE };
+// Scalars for the host (one workgroup): after the first residual r.z (in both
+// slots: p_old is zero then, so the first beta only has to be finite), r.r and
+// b.b; after the final residual or a run of iterations, r.r.
+enum { CG_AFTER_RESIDUAL = 0, CG_AFTER_ITERATIONS };
 template <int STAGE>
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_scalars(const CgArgs C, int nb) {
-    __shared__ double red[CG_BLOCK];
+    __shared__ double red[4];
     if constexpr (STAGE == CG_AFTER_RESIDUAL) {
-        const double trz = cg_total(C, 0, nb, red);
-        const double trr = cg_total(C, 1, nb, red);
-        const double tbb = cg_total(C, 2, nb, red);
+        const double trz = cg_total(C.part, nb, red);
+        const double trr = cg_total(C.part + CG_GRID, nb, red);
+        const double tbb = cg_total(C.part + 2 * CG_GRID, nb, red);
         if (threadIdx.x == 0) {
-            C.scal[S_RZ] = trz;
+            C.scal[S_RZ0] = trz;
+            C.scal[S_RZ1] = trz;
             C.scal[S_RR] = trr;
             C.scal[S_BB] = tbb;
-            C.scal[S_BETA] = 0.0;
-        }
-    } else if constexpr (STAGE == CG_AFTER_FINAL) {
-        const double trr = cg_total(C, 1, nb, red);
-        if (threadIdx.x == 0) C.scal[S_RR] = trr;
-    } else if constexpr (STAGE == CG_AFTER_PRODUCT) {
-        const double tpq = cg_total(C, 0, nb, red);
-        if (threadIdx.x == 0) {
-            C.scal[S_PQ] = tpq;
-            if (!(tpq > 0.0) || !isfinite(tpq)) {
-                C.scal[S_ALPHA] = 0.0;
-                atomicOr(reinterpret_cast<int*>(C.scal + S_FLAG), 2);
-            } else {
-                C.scal[S_ALPHA] = C.scal[S_RZ] / tpq;
-            }
         }
     } else {
-        const double trz = cg_total(C, 0, nb, red);
-        const double trr = cg_total(C, 1, nb, red);
-        if (threadIdx.x == 0) {
-            const double old = C.scal[S_RZ];
-            C.scal[S_BETA] = old != 0.0 ? trz / old : 0.0;
-            C.scal[S_RZ] = trz;
-            C.scal[S_RR] = trr;
-        }
+        const double trr = cg_total(C.part + CG_GRID, nb, red);
+        if (threadIdx.x == 0) C.scal[S_RR] = trr;
     }
 }
 
-// Launch helpers (G selected at run time).
+// Launch helpers (G selected at run time). The residual runs on the
+// elementwise grid, so that its partials and the update's come in the same
+// number (the product adds them).
 struct CgLaunch {
     CgArgs C;
     int G;
@@ -319,7 +324,7 @@ struct CgLaunch {
     hipStream_t s;
 
     void residual(bool final_, double* p_old) const {
-        const dim3 g(grid_rows), b(CG_BLOCK);
+        const dim3 g(grid_elem), b(CG_BLOCK);
         if (G == 4) {
             if (final_) hipLaunchKernelGGL((k_cg_residual<4, true>), g, b, 0, s, C, p_old);
             else hipLaunchKernelGGL((k_cg_residual<4, false>), g, b, 0, s, C, p_old);
@@ -330,17 +335,21 @@ struct CgLaunch {
             if (final_) hipLaunchKernelGGL((k_cg_residual<16, true>), g, b, 0, s, C, p_old);
             else hipLaunchKernelGGL((k_cg_residual<16, false>), g, b, 0, s, C, p_old);
         }
-        if (final_) hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_FINAL>, dim3(1), b, 0, s, C, (int)grid_rows);
-        else hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_RESIDUAL>, dim3(1), b, 0, s, C, (int)grid_rows);
+        if (final_) hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_ITERATIONS>, dim3(1), b, 0, s, C, (int)grid_elem);
+        else hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_RESIDUAL>, dim3(1), b, 0, s, C, (int)grid_elem);
     }
-    void iteration(const double* p_old, double* p_new) const {
+    // iteration k, par = k mod 2
+    void iteration(const double* p_old, double* p_new, int par) const {
         const dim3 g(grid_rows), b(CG_BLOCK);
-        if (G == 4) hipLaunchKernelGGL(k_cg_product<4>, g, b, 0, s, C, p_old, p_new);
-        else if (G == 8) hipLaunchKernelGGL(k_cg_product<8>, g, b, 0, s, C, p_old, p_new);
-        else hipLaunchKernelGGL(k_cg_product<16>, g, b, 0, s, C, p_old, p_new);
-        hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_PRODUCT>, dim3(1), b, 0, s, C, (int)grid_rows);
-        hipLaunchKernelGGL(k_cg_update, dim3(grid_elem), b, 0, s, C, p_new);
-        hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_UPDATE>, dim3(1), b, 0, s, C, (int)grid_elem);
+        const int nb = (int)grid_elem;
+        if (G == 4) hipLaunchKernelGGL(k_cg_product<4>, g, b, 0, s, C, p_old, p_new, par, nb);
+        else if (G == 8) hipLaunchKernelGGL(k_cg_product<8>, g, b, 0, s, C, p_old, p_new, par, nb);
+        else hipLaunchKernelGGL(k_cg_product<16>, g, b, 0, s, C, p_old, p_new, par, nb);
+        hipLaunchKernelGGL(k_cg_update, dim3(grid_elem), b, 0, s, C, p_new, par, (int)grid_rows);
+    }
+    // r.r of the last iteration, for the host's convergence test
+    void residual_norm() const {
+        hipLaunchKernelGGL(k_cg_scalars<CG_AFTER_ITERATIONS>, dim3(1), dim3(CG_BLOCK), 0, s, C, (int)grid_elem);
     }
 };
 
@@ -360,7 +369,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     const int64_t n = n_rows;
     // workspace: r, z, q, p (two), 1/diag, partials, scalars
     const size_t vec = (size_t)n * sizeof(double);
-    const size_t bytes = 6 * vec + 3 * CG_GRID * sizeof(double) + S_N * sizeof(double) + 256;
+    const size_t bytes = 6 * vec + 4 * CG_GRID * sizeof(double) + S_N * sizeof(double) + 256;
     // The solve runs on a stream of its own (HIP graphs cannot be captured on
     // the null stream), ordered after the caller's work and before anything
     // the caller queues next.
@@ -402,7 +411,8 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     double* p1 = p0 + n;
     C.dinv = p1 + n;
     C.part = C.dinv + n;
-    C.scal = C.part + 3 * CG_GRID;
+    C.part_pq = C.part + 3 * CG_GRID;
+    C.scal = C.part_pq + CG_GRID;
     FEM_HIP(hipMemsetAsync(C.scal, 0, S_N * sizeof(double), s));
     // lanes per row from the mean row length
     int64_t nnz = 0;
@@ -432,17 +442,21 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
         if (steps == CG_CHECK) {
             // CG_CHECK iterations (an even number, so p ends in p0 again) as one graph
             if (!R.exec) {
+                // it is a multiple of CG_CHECK here (an even number), so
+                // iteration it + k has parity k mod 2
                 FEM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < CG_CHECK; ++k) L.iteration(k % 2 ? p1 : p0, k % 2 ? p0 : p1);
+                for (int k = 0; k < CG_CHECK; ++k) L.iteration(k % 2 ? p1 : p0, k % 2 ? p0 : p1, k % 2);
+                L.residual_norm();
                 FEM_HIP(hipStreamEndCapture(s, &R.graph));
                 FEM_HIP(hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0));
             }
             FEM_HIP(hipGraphLaunch(R.exec, s));
         } else {
             for (int64_t k = 0; k < steps; ++k) {
-                L.iteration(p0, p1);
+                L.iteration(p0, p1, (int)((it + k) % 2));
                 std::swap(p0, p1);
             }
+            L.residual_norm();
         }
         FEM_HIP(hipGetLastError());
         it += steps;
