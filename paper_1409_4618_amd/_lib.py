@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfem.so")
+# FEM_CHECK=1 selects the checked build (bounds checks in every kernel; same
+# results, slower); the default is the production library.
+LIB_PATH = os.path.join(HERE, "libfem_check.so" if os.environ.get("FEM_CHECK") == "1" else "libfem.so")
 
 c_int64_p = ctypes.POINTER(ctypes.c_int64)
 c_void_pp = ctypes.POINTER(ctypes.c_void_p)

@@ -38,7 +38,26 @@ struct BwdArgs {
     const uint16_t* inc;       // workgroup-local incidences by workgroup, node, element
     int64_t T;
     int* err_word;
+    // sizes, for the checked build's bounds checks
+    int64_t V;        // nodes
+    int64_t n_dofs;   // rows of the pattern (entries of u)
+    int64_t nnz;      // entries of gK, gM
+    int64_t n_pairs;  // (node, workgroup) pairs of the node map
 };
+
+// Checked build: node ids of an element within [0, V) (an id out of range is
+// flagged and replaced by 0, so the gathers stay in bounds).
+template <int NV>
+__device__ __forceinline__ void check_gids(const BwdArgs& A, int gid[NV]) {
+#if FEM_CHECK
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (!fem_in_range(gid[v], A.V, A.err_word)) gid[v] = 0;
+#else
+    (void)A;
+    (void)gid;
+#endif
+}
 
 // Weight modes of the adjoint: separate gK and gM arrays, one array for both
 // (L = u^T (K + M) u with its weights materialised), or the quadratic form
@@ -68,7 +87,8 @@ __device__ __forceinline__ void gather_row(const BwdArgs& A, const SlotView& sv,
     const double* pM = A.gM ? A.gM : A.gK;
 #pragma unroll
     for (int l = 0; l < NLOC; ++l) {
-        const int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
+        int64_t pos = base + (int64_t)((cp >> (8 * l)) & 0xFFu);
+        if (!fem_in_range(pos, A.nnz, A.err_word)) pos = 0;
         if constexpr (MODE == BWD_SAME) {
             wk[l] = wm[l] = pK[pos];
         } else {
@@ -98,7 +118,11 @@ __device__ __forceinline__ void load_u(const BwdArgs& A, int64_t e, double ue[NL
     for (int l = 0; l < NLOC; ++l) ue[l] = 0.0;
     if constexpr (MODE == BWD_QUADRATIC) {
 #pragma unroll
-        for (int l = 0; l < NLOC; ++l) ue[l] = A.u[A.elems2dofs[e * NLOC + l]];
+        for (int l = 0; l < NLOC; ++l) {
+            int64_t d = A.elems2dofs[e * NLOC + l];
+            if (!fem_in_range(d, A.n_dofs, A.err_word)) d = 0;
+            ue[l] = A.u[d];
+        }
     }
 }
 
@@ -133,6 +157,7 @@ __device__ double2 bwd_ned3(const BwdArgs& A, int64_t e, const SlotView& sv, dou
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
     gid[0] = q4.x; gid[1] = q4.y; gid[2] = q4.z; gid[3] = q4.w;
+    check_gids<4>(A, gid);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
@@ -310,6 +335,7 @@ __device__ double2 bwd_rt3(const BwdArgs& A, int64_t e, const SlotView& sv, doub
     V3 x[4];
     const int4 q4 = reinterpret_cast<const int4*>(A.elems)[e];
     gid[0] = q4.x; gid[1] = q4.y; gid[2] = q4.z; gid[3] = q4.w;
+    check_gids<4>(A, gid);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         x[v] = {A.nodes[(int64_t)gid[v] * 3], A.nodes[(int64_t)gid[v] * 3 + 1], A.nodes[(int64_t)gid[v] * 3 + 2]};
@@ -408,10 +434,10 @@ __device__ double2 bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, doub
     int gid[3];
     V2 x[3];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        gid[v] = A.elems[e * 3 + v];
-        x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
-    }
+    for (int v = 0; v < 3; ++v) gid[v] = A.elems[e * 3 + v];
+    check_gids<3>(A, gid);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) x[v] = {A.nodes[(int64_t)gid[v] * 2], A.nodes[(int64_t)gid[v] * 2 + 1]};
     double ue[3];
     load_u<3, MODE>(A, e, ue);
     const Geo2 g = geo2(x);
@@ -610,13 +636,19 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     // vertex, in ascending element order; incidence (lane, v) sits at
     // sh[(v * DIM + c) * BWD_BLOCK + lane]
     for (int j = (int)threadIdx.x; j < np; j += BWD_BLOCK) {
-        const int i0 = s_pst[j];
-        const int i1 = j + 1 < np ? s_pst[j + 1] : n_inc;
+        int i0 = s_pst[j];
+        int i1 = j + 1 < np ? s_pst[j + 1] : n_inc;
+#if FEM_CHECK
+        if (!fem_in_range(i0, n_inc + 1, A.err_word) || !fem_in_range(i1, n_inc + 1, A.err_word) ||
+            !fem_in_range(pb0 + j, A.n_pairs, A.err_word))
+            continue;
+#endif
         double acc[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
         for (int i = i0; i < i1; ++i) {
             const int slot = s_inc[i];
+            if (!fem_in_range(slot, n_inc, A.err_word)) continue;
             const int lane = slot / NV;
             const double* q = sh + lds_at(lane, slot - lane * NV, DIM);
 #pragma unroll
@@ -631,7 +663,8 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
 // workgroup order (npair lists them by node).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, const int32_t* npair,
-                                                      const double* partials, int64_t V, double* gnodes) {
+                                                      const double* partials, int64_t V, double* gnodes,
+                                                      int64_t n_pairs, int* err) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     double acc[DIM];
@@ -640,7 +673,9 @@ __global__ __launch_bounds__(256) void k_node_reduce(const int32_t* node_ptr, co
     const int64_t j1 = node_ptr[v + 1];
 #pragma unroll 4
     for (int64_t j = node_ptr[v]; j < j1; ++j) {
+        if (!fem_in_range(j, n_pairs, err)) break;
         const int64_t q = npair[j];
+        if (!fem_in_range(q, n_pairs, err)) continue;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] += partials[q * DIM + c];
     }
@@ -709,6 +744,10 @@ fem_status launch_quadratic_value(fem_mesh m, DofSet& ds, fem_kind kind, const d
     A.b = b;
     A.T = m->T;
     A.err_word = m->err_word;
+    A.V = m->V;
+    A.n_dofs = ds.pat.n_rows;
+    A.nnz = ds.pat.nnz;
+    A.n_pairs = m->bwd_pairs;
     const int64_t nb = quadratic_value_partials(m->T);
     if (nb > 0) {
         if (kc == 2) hipLaunchKernelGGL(k_quadratic_value<2>, dim3((unsigned)nb), dim3(BWD_BLOCK), 0, s, A, partials);
@@ -783,6 +822,10 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.inc = m->bwd_inc;
     A.T = m->T;
     A.err_word = m->err_word;
+    A.V = m->V;
+    A.n_dofs = ds.pat.n_rows;
+    A.nnz = ds.pat.nnz;
+    A.n_pairs = m->bwd_pairs;
     const unsigned grid = (unsigned)(((m->T + BWD_BLOCK - 1) / BWD_BLOCK + 7) / 8 * 8);
     if (m->T > 0) {
         if (u) launch_bwd_mode<BWD_QUADRATIC>(kc, A, grid, s);
@@ -794,10 +837,10 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
         const unsigned gv = (unsigned)((m->V + 255) / 256);
         if (m->dim == 3)
             hipLaunchKernelGGL(k_node_reduce<3>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->bwd_npair,
-                               m->elem_partials, m->V, gnodes);
+                               m->elem_partials, m->V, gnodes, m->bwd_pairs, m->err_word);
         else
             hipLaunchKernelGGL(k_node_reduce<2>, dim3(gv), dim3(256), 0, s, m->node_ptr, m->bwd_npair,
-                               m->elem_partials, m->V, gnodes);
+                               m->elem_partials, m->V, gnodes, m->bwd_pairs, m->err_word);
         FEM_HIP(hipGetLastError());
     }
     return FEM_OK;

@@ -183,6 +183,9 @@ static fem_status fill_meshdev(fem_mesh m, fem_kind kind, const double* nodes, c
     md->n_tiles = (ds.pat.n_rows + R - 1) / R;
     md->kind_code = kind_code(m->dim, kind);
     md->err_word = m->err_word;
+    md->T = m->T;
+    md->V = m->V;
+    md->nnz = ds.pat.nnz;
     return FEM_OK;
 }
 
@@ -264,6 +267,8 @@ fem_status fem_status_query(fem_mesh m) {
     FEM_HIP(hipStreamSynchronize(m->last_stream));
     FEM_HIP(hipMemcpy(&err, m->err_word, sizeof(int), hipMemcpyDeviceToHost));
     FEM_HIP(hipMemset(m->err_word, 0, sizeof(int)));
+    if (err & ERR_BOUNDS)
+        return fail(FEM_ERANGE, "checked build: a kernel met a map index outside the array it indexes");
     if (err & ERR_NONFINITE) return fail(FEM_ENONFINITE, "a Jacobian determinant was not finite");
     if (err & ERR_DEGENERATE) return fail(FEM_EDEGENERATE, "an element had a zero or non-finite Jacobian determinant");
     return FEM_OK;

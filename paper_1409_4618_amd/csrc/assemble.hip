@@ -113,7 +113,13 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
     const int64_t r0 = tile * R;
     const int64_t r1 = (r0 + R < md.n_rows) ? r0 + R : md.n_rows;
     const int64_t p0 = md.rowptr[r0];
-    const int nt = (int)(md.rowptr[r1] - p0);
+    int nt = (int)(md.rowptr[r1] - p0);
+#if FEM_CHECK
+    if (p0 < 0 || nt < 0 || p0 + nt > md.nnz) {
+        atomicOr(md.err_word, ERR_BOUNDS);
+        nt = 0;
+    }
+#endif
     for (int i = tid; i < nt; i += NT) sKM[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const int64_t r = r0 + lrow;
@@ -130,9 +136,21 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
             for (int u = 0; u < U; ++u) {
                 const int j = jb + g + G * u;
                 live[u] = j < j1;
-                const int jj = live[u] ? j : j1 - 1;
+                int jj = live[u] ? j : j1 - 1;
+#if FEM_CHECK
+                if (!fem_in_range(jj, md.T * NLOC, md.err_word)) {
+                    live[u] = false;
+                    jj = 0;
+                }
+#endif
                 slot[u] = md.rs_slot[jj];
                 cp[u] = load_colpos<NLOC>(md.colpos, jj);
+#if FEM_CHECK
+                if (!fem_in_range(slot[u], md.T * NLOC, md.err_word)) {
+                    live[u] = false;
+                    slot[u] = 0;
+                }
+#endif
             }
             SlotData<KC> sd[U];
             double ca[U], cb[U];
@@ -149,6 +167,13 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
 #pragma unroll
                     for (int v = 0; v < NV; ++v) sd[u].gid[v] = md.elems[e * NV + v];
                 }
+#if FEM_CHECK
+                for (int v = 0; v < NV; ++v)
+                    if (!fem_in_range(sd[u].gid[v], md.V, md.err_word)) {
+                        live[u] = false;
+                        sd[u].gid[v] = 0;
+                    }
+#endif
                 ca[u] = md.a ? md.a[e] : 1.0;
                 cb[u] = md.b ? md.b[e] : 1.0;
             }
@@ -174,6 +199,7 @@ __device__ __forceinline__ void fwd_tile(const MeshDev& md, int64_t tile, double
 #pragma unroll
                         for (int l = 0; l < NLOC; ++l) {
                             const int pos = rb + (int)((cp[u] >> (8 * l)) & 0xFFu);
+                            if (!fem_in_range(pos, nt, md.err_word)) continue;
                             const double2 o = sKM[pos];
                             sKM[pos] = make_double2(o.x + Kr[l], o.y + Mr[l]);
                         }
@@ -510,10 +536,17 @@ __host__ __device__ constexpr bool ned3_opposite(int k, int l) {
 // (bit k of mask). The slot record cp[k] gives the row's column offsets, its
 // tile-local row (LDS base of the row's values) and, for the 3D Nedelec
 // diagonal, the slot's rank in the row (index in the tile's diagonal buffer).
+// TB: the tile's sizes for the checked build (rows, values, diagonal slots).
+struct TileBounds {
+    int nrows, nvals, nslots;
+    int* err;
+};
+
 template <int KC, bool MASS>
 __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, uint32_t mask,
                                             const uint64_t cp[KT<KC>::NLOC], const int* rowbase,
-                                            const int* rowslot, double* out, double* sdiag) {
+                                            const int* rowslot, double* out, double* sdiag,
+                                            const TileBounds& tb) {
     constexpr int NLOC = KT<KC>::NLOC;
     static_for<0, NLOC>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
@@ -522,17 +555,29 @@ __device__ __forceinline__ void ema_scatter(typename EmaPass<KC, MASS>::T& st, u
             const typename EmaPass<KC, MASS>::T& sk = st;
             const uint64_t c = cp[k];
             const int lr = rec_row<KC>(c);
+#if FEM_CHECK
+            if (!fem_in_range(lr, tb.nrows, tb.err)) return;
+#endif
             const int base = rowbase[lr];
             const double r = ema_row<KC, MASS, k>(sk);
             const double d = ema_entry<KC, MASS, k, k>(sk, r);
             if constexpr (KC == 2) {
-                sdiag[rowslot[lr] + (int)(c >> 56)] = d;
+#if FEM_CHECK
+                if (fem_in_range(rowslot[lr] + (int)(c >> 56), tb.nslots, tb.err))
+#endif
+                    sdiag[rowslot[lr] + (int)(c >> 56)] = d;
             } else {
-                atomicAdd(&out[base + rec_col<KC>(c, k)], d);
+#if FEM_CHECK
+                if (fem_in_range(base + rec_col<KC>(c, k), tb.nvals, tb.err))
+#endif
+                    atomicAdd(&out[base + rec_col<KC>(c, k)], d);
             }
             static_for<0, NLOC>([&](auto ll) {
                 constexpr int l = decltype(ll)::value;
                 if constexpr (l != k) {
+#if FEM_CHECK
+                    if (!fem_in_range(base + rec_col<KC>(c, l), tb.nvals, tb.err)) return;
+#endif
                     double* o = &out[base + rec_col<KC>(c, l)];
                     const double v = ema_entry<KC, MASS, k, l>(sk, r);
                     // Entries whose two dofs determine the element (3D
@@ -609,6 +654,16 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
             gid[2] = q.z;
         }
     }
+#if FEM_CHECK
+    if (have) {
+        bool ok = fem_in_range(e, md.T, md.err_word);
+        for (int v = 0; v < NV; ++v) ok = ok && fem_in_range(gid[v], md.V, md.err_word);
+        if (!ok) {
+            e = 0;
+            for (int v = 0; v < NV; ++v) gid[v] = 0;
+        }
+    }
+#endif
     // record offset: the wavefront's base (tile header word 7 + wavefront)
     // plus the exclusive prefix of the dof counts within the wavefront (one
     // ballot per bit of a count <= 6, each counted below the lane at once)
@@ -628,10 +683,24 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         for (int k = 0; k < NLOC; ++k)
             if ((mask >> k) & 1u) {
                 const int64_t j = roff + __popc(mask & ((1u << k) - 1u));
+#if FEM_CHECK
+                if (!fem_in_range(j, md.T * NLOC, md.err_word)) continue;
+#endif
                 if constexpr (KC == 2) cp[k] = reinterpret_cast<const uint64_t*>(md.ema_rec)[j];
                 else cp[k] = reinterpret_cast<const uint32_t*>(md.ema_rec)[j];
             }
     }
+#if FEM_CHECK
+    // a tile's rows, values and slots within the pattern
+    const bool tile_ok = fem_in_range(r0 + nrows - 1, md.n_rows, md.err_word) &&
+                         fem_in_range(p0 + nt - 1, md.nnz, md.err_word) && nt <= md.ema_pmax && nrows <= R &&
+                         (KC != 2 || nslots <= md.ema_max_slots);
+    if (!tile_ok) {
+        atomicOr(md.err_word, ERR_BOUNDS);
+        return;  // uniform: the whole workgroup leaves before its first barrier
+    }
+#endif
+    const TileBounds tb{nrows, nt, nslots, md.err_word};
     // phase 0: clear the values, row bases (and row slot starts)
     for (int i = tid; i < nt; i += NT) out[i] = 0.0;
     for (int lr = tid; lr < nrows; lr += NT) {
@@ -657,7 +726,11 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if constexpr (KC == 2) {
 #pragma unroll
             for (int k = 0; k < NLOC; ++k)
+#if FEM_CHECK
+                if (((mask >> k) & 1u) && fem_in_range(rec_row<KC>(cp[k]), nrows, md.err_word))
+#else
                 if ((mask >> k) & 1u)
+#endif
                     rowdiag[rec_row<KC>(cp[k])] = rec_col<KC>(cp[k], k);
         }
         st = ema_elem<KC>(gid, x, ca, cb);
@@ -672,7 +745,7 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
         if (dst) {
             if (have) {
                 typename EmaPass<KC, MASS>::T ps = ema_pass_state<KC, MASS>(st);
-                ema_scatter<KC, MASS>(ps, mask, cp, rowbase, rowslot, out, sdiag);
+                ema_scatter<KC, MASS>(ps, mask, cp, rowbase, rowslot, out, sdiag, tb);
             }
             __syncthreads();
             if constexpr (KC == 2) {
@@ -680,8 +753,16 @@ __device__ __forceinline__ void tile_ema(const MeshDev& md, int64_t tile, char* 
                 for (int lr = tid; lr < nrows; lr += NT) {
                     double acc = 0.0;
                     const int j1 = rowslot[lr + 1];
-                    for (int j = rowslot[lr]; j < j1; ++j) acc += sdiag[j];
-                    out[rowbase[lr] + rowdiag[lr]] = acc;
+                    for (int j = rowslot[lr]; j < j1; ++j) {
+#if FEM_CHECK
+                        if (!fem_in_range(j, nslots, md.err_word)) break;
+#endif
+                        acc += sdiag[j];
+                    }
+#if FEM_CHECK
+                    if (fem_in_range(rowbase[lr] + rowdiag[lr], nt, md.err_word))
+#endif
+                        out[rowbase[lr] + rowdiag[lr]] = acc;
                 }
                 __syncthreads();
             }

@@ -24,7 +24,33 @@ fem_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // device error word bits
-enum : int { ERR_DEGENERATE = 1, ERR_NONFINITE = 2, ERR_RANGE = 4, ERR_OVERFLOW = 8 };
+enum : int { ERR_DEGENERATE = 1, ERR_NONFINITE = 2, ERR_RANGE = 4, ERR_OVERFLOW = 8, ERR_BOUNDS = 16 };
+
+// Checked build (compiled with -DFEM_CHECK=1 into libfem_check.so): before a
+// kernel reads or writes through an index taken from a map (element and node
+// ids, slot records, row tables, dof lists, CSR positions, tile-local LDS
+// offsets), it compares the index with the size of what it indexes. An index
+// out of range sets ERR_BOUNDS in the error word (fem_status_query reports
+// FEM_ERANGE) and the access is skipped, so the kernel still runs to its end.
+// In the default build the check is the constant true and compiles away.
+#ifndef FEM_CHECK
+#define FEM_CHECK 0
+#endif
+#if defined(__HIPCC__)
+__device__ __forceinline__ bool fem_in_range(int64_t i, int64_t n, int* err) {
+#if FEM_CHECK
+    if (i < 0 || i >= n) {
+        atomicOr(err, ERR_BOUNDS);
+        return false;
+    }
+#else
+    (void)i;
+    (void)n;
+    (void)err;
+#endif
+    return true;
+}
+#endif
 
 // ---------------------------------------------------------------------------
 // device buffers owned by a handle
@@ -225,6 +251,10 @@ struct MeshDev {
     int32_t ema_pmax;
     int32_t ema_max_slots;
     int32_t ema_pad;
+    // sizes, for the checked build's bounds checks
+    int64_t T;      // elements
+    int64_t V;      // nodes
+    int64_t nnz;    // values of K and M
 };
 
 int kind_code(int dim, fem_kind kind);

@@ -210,15 +210,20 @@ __global__ __launch_bounds__(INT_BLOCK) void k_load_local_ned(const int32_t* __r
 }
 
 // f[i] = sum of the local values of dof i's slots, in ascending element order
+// (n_slots, err: the checked build's bounds of the slot indices)
 __global__ __launch_bounds__(INT_BLOCK) void k_dof_sum(const int32_t* __restrict__ rs_ptr,
                                                         const int32_t* __restrict__ rs_slot,
                                                         const double* __restrict__ loc, int64_t n,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, int64_t n_slots, int* err) {
     const int64_t i = (int64_t)blockIdx.x * INT_BLOCK + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
     const int j1 = rs_ptr[i + 1];
-    for (int j = rs_ptr[i]; j < j1; ++j) acc += loc[rs_slot[j]];
+    for (int j = rs_ptr[i]; j < j1; ++j) {
+        if (!fem_in_range(j, n_slots, err)) break;
+        const int q = rs_slot[j];
+        if (fem_in_range(q, n_slots, err)) acc += loc[q];
+    }
     out[i] = acc;
 }
 
@@ -523,7 +528,7 @@ fem_status fem_load_vector(fem_mesh m, fem_kind kind, const double* nodes, fem_f
                            q, F, m->slot_vals, m->err_word);
     FEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_dof_sum, dim3(int_grid(ds.n)), dim3(INT_BLOCK), 0, s, ds.rs_ptr, ds.rs_slot, m->slot_vals,
-                       ds.n, f);
+                       ds.n, f, m->T * ds.nloc, m->err_word);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }
@@ -578,7 +583,7 @@ fem_status fem_rt_majorant_rhs(fem_mesh m, const double* nodes, const double* v,
                            c_div, c_grad, m->slot_vals);
     FEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_dof_sum, dim3(int_grid(ds.n)), dim3(INT_BLOCK), 0, s, ds.rs_ptr, ds.rs_slot, m->slot_vals,
-                       ds.n, rhs);
+                       ds.n, rhs, m->T * ds.nloc, m->err_word);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }

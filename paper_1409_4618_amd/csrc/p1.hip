@@ -180,6 +180,30 @@ __device__ __forceinline__ int64_t find_col(const int64_t* rowptr, const int32_t
     return lo;
 }
 
+// Sizes for the checked build: slots of the element lists, nonzeros, error word.
+struct P1Bounds {
+    int64_t n_slots, nnz;
+    int* err;
+};
+
+// Checked build: position pos holds column col (else flagged, and the caller
+// skips the store).
+__device__ __forceinline__ bool p1_pos_ok(const int32_t* colind, int64_t pos, int32_t col, const P1Bounds& b) {
+#if FEM_CHECK
+    if (!fem_in_range(pos, b.nnz, b.err)) return false;
+    if (colind[pos] != col) {
+        atomicOr(b.err, ERR_BOUNDS);
+        return false;
+    }
+#else
+    (void)colind;
+    (void)pos;
+    (void)col;
+    (void)b;
+#endif
+    return true;
+}
+
 // (c_a . c_b) / (d! |J|) of element e, times its coefficient
 template <int DIM>
 __device__ __forceinline__ double p1_entry(const int32_t* elems, const double* nodes, const double* a, int64_t e,
@@ -211,13 +235,15 @@ template <int DIM>
 __global__ __launch_bounds__(P1_TB) void k_p1_offdiag(const int32_t* elems, const double* nodes, const double* a,
                                                       const int32_t* edges2nodes, const int32_t* rs_ptr,
                                                       const int32_t* rs_slot, int64_t E, const int64_t* rowptr,
-                                                      const int32_t* colind, double* K) {
+                                                      const int32_t* colind, double* K, const P1Bounds bd) {
     constexpr int NE = DIM == 2 ? 3 : 6;
     const int64_t ed = (int64_t)blockIdx.x * P1_TB + threadIdx.x;
     if (ed >= E) return;
     double acc = 0.0;
     for (int j = rs_ptr[ed]; j < rs_ptr[ed + 1]; ++j) {
+        if (!fem_in_range(j, bd.n_slots, bd.err)) break;
         const int64_t slot = rs_slot[j];
+        if (!fem_in_range(slot, bd.n_slots, bd.err)) continue;
         const int64_t e = slot / NE;
         const int k = (int)(slot - e * NE);
         const int va = DIM == 2 ? nib(TRI_START, k) : nib(NED3_START, k);
@@ -225,25 +251,30 @@ __global__ __launch_bounds__(P1_TB) void k_p1_offdiag(const int32_t* elems, cons
         acc += p1_entry<DIM>(elems, nodes, a, e, va, vb);
     }
     const int32_t lo = edges2nodes[2 * ed], hi = edges2nodes[2 * ed + 1];
-    K[find_col(rowptr, colind, lo, hi)] = acc;
-    K[find_col(rowptr, colind, hi, lo)] = acc;
+    const int64_t p_lh = find_col(rowptr, colind, lo, hi), p_hl = find_col(rowptr, colind, hi, lo);
+    if (p1_pos_ok(colind, p_lh, hi, bd)) K[p_lh] = acc;
+    if (p1_pos_ok(colind, p_hl, lo, bd)) K[p_hl] = acc;
 }
 
 // diagonal entries: over the elements of each node
 template <int DIM>
 __global__ __launch_bounds__(P1_TB) void k_p1_diag(const int32_t* elems, const double* nodes, const double* a,
                                                    const int32_t* vs_ptr, const int32_t* vs_slot, int64_t V,
-                                                   const int64_t* rowptr, const int32_t* colind, double* K) {
+                                                   const int64_t* rowptr, const int32_t* colind, double* K,
+                                                   const P1Bounds bd) {
     const int64_t i = (int64_t)blockIdx.x * P1_TB + threadIdx.x;
     if (i >= V) return;
     double acc = 0.0;
     for (int j = vs_ptr[i]; j < vs_ptr[i + 1]; ++j) {
+        if (!fem_in_range(j, bd.n_slots, bd.err)) break;
         const int64_t slot = vs_slot[j];
+        if (!fem_in_range(slot, bd.n_slots, bd.err)) continue;
         const int64_t e = slot / (DIM + 1);
         const int v = (int)(slot - e * (DIM + 1));
         acc += p1_entry<DIM>(elems, nodes, a, e, v, v);
     }
-    K[find_col(rowptr, colind, i, (int32_t)i)] = acc;
+    const int64_t p = find_col(rowptr, colind, i, (int32_t)i);
+    if (p1_pos_ok(colind, p, (int32_t)i, bd)) K[p] = acc;
 }
 
 // ------------------------------------------------------------------ load
@@ -275,12 +306,17 @@ __global__ __launch_bounds__(INT_BLOCK) void k_p1_load_local(const int32_t* elem
     for (int v = 0; v <= DIM; ++v) loc[e * (DIM + 1) + v] = acc[v] * aJ;
 }
 
+// (n_slots, err: the checked build's bounds of the list entries and slots)
 __global__ __launch_bounds__(P1_TB) void k_list_sum(const int32_t* ptr, const int32_t* slot, const double* loc,
-                                                    int64_t n, double* out) {
+                                                    int64_t n, double* out, int64_t n_slots, int* err) {
     const int64_t i = (int64_t)blockIdx.x * P1_TB + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
-    for (int j = ptr[i]; j < ptr[i + 1]; ++j) acc += loc[slot[j]];
+    for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
+        if (!fem_in_range(j, n_slots, err)) break;
+        const int q = slot[j];
+        if (fem_in_range(q, n_slots, err)) acc += loc[q];
+    }
     out[i] = acc;
 }
 
@@ -360,16 +396,18 @@ fem_status fem_p1_assemble(fem_mesh m, const double* nodes, const double* a, dou
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
     const int64_t E = m->edges.n, V = m->V;
+    const P1Bounds be{m->T * m->edges.nloc, m->p1_nnz, m->err_word};
+    const P1Bounds bv{m->T * (m->dim + 1), m->p1_nnz, m->err_word};
     if (m->dim == 3) {
         hipLaunchKernelGGL(k_p1_offdiag<3>, dim3(p1_blocks(E)), dim3(P1_TB), 0, s, m->elems, nodes, a, m->edges2nodes,
-                           m->edges.rs_ptr, m->edges.rs_slot, E, m->p1_rowptr, m->p1_colind, K);
+                           m->edges.rs_ptr, m->edges.rs_slot, E, m->p1_rowptr, m->p1_colind, K, be);
         hipLaunchKernelGGL(k_p1_diag<3>, dim3(p1_blocks(V)), dim3(P1_TB), 0, s, m->elems, nodes, a, m->vs_ptr,
-                           m->vs_slot, V, m->p1_rowptr, m->p1_colind, K);
+                           m->vs_slot, V, m->p1_rowptr, m->p1_colind, K, bv);
     } else {
         hipLaunchKernelGGL(k_p1_offdiag<2>, dim3(p1_blocks(E)), dim3(P1_TB), 0, s, m->elems, nodes, a, m->edges2nodes,
-                           m->edges.rs_ptr, m->edges.rs_slot, E, m->p1_rowptr, m->p1_colind, K);
+                           m->edges.rs_ptr, m->edges.rs_slot, E, m->p1_rowptr, m->p1_colind, K, be);
         hipLaunchKernelGGL(k_p1_diag<2>, dim3(p1_blocks(V)), dim3(P1_TB), 0, s, m->elems, nodes, a, m->vs_ptr,
-                           m->vs_slot, V, m->p1_rowptr, m->p1_colind, K);
+                           m->vs_slot, V, m->p1_rowptr, m->p1_colind, K, bv);
     }
     FEM_HIP(hipGetLastError());
     return FEM_OK;
@@ -396,7 +434,7 @@ fem_status fem_p1_load(fem_mesh m, const double* nodes, fem_function fn, const d
         hipLaunchKernelGGL(k_p1_load_local<2>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, m->T, q, Fa,
                            m->slot_vals);
     hipLaunchKernelGGL(k_list_sum, dim3(p1_blocks(m->V)), dim3(P1_TB), 0, s, m->vs_ptr, m->vs_slot, m->slot_vals,
-                       m->V, F);
+                       m->V, F, m->T * (m->dim + 1), m->err_word);
     FEM_HIP(hipGetLastError());
     return FEM_OK;
 }

@@ -131,6 +131,7 @@ enum { S_RZ0 = 0, S_RZ1, S_RR, S_BB, S_FLAG, S_N };
 
 struct CgArgs {
     int64_t n;
+    int64_t nnz;  // for the checked build's bounds checks
     const int64_t* rowptr;
     const int32_t* colind;
     const double* A;
@@ -184,9 +185,14 @@ __device__ __forceinline__ double cg_row(const CgArgs& C, int64_t i, int j, cons
                                          double beta) {
     double sa = 0.0, sb = 0.0;
     if (i < C.n) {
-        const int64_t e1 = C.rowptr[i + 1];
+        int64_t e1 = C.rowptr[i + 1];
+#if FEM_CHECK
+        if (!fem_in_range(e1, C.nnz + 1, reinterpret_cast<int*>(C.scal + S_FLAG))) e1 = 0;
+#endif
         for (int64_t e = C.rowptr[i] + j; e < e1; e += G) {
-            const int32_t c = C.colind[e];
+            if (!fem_in_range(e, C.nnz, reinterpret_cast<int*>(C.scal + S_FLAG))) break;
+            int32_t c = C.colind[e];
+            if (!fem_in_range(c, C.n, reinterpret_cast<int*>(C.scal + S_FLAG))) c = 0;
             const double xv = FUSED ? fma(beta, p[c], x[c]) : x[c];
             sa += C.A[e] * xv;
             if (C.B) sb += C.B[e] * xv;
@@ -202,8 +208,10 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cg_diag(const CgArgs C) {
     const int64_t i = (int64_t)blockIdx.x * CG_BLOCK + threadIdx.x;
     if (i >= C.n) return;
     double d = 0.0;
-    for (int64_t e = C.rowptr[i]; e < C.rowptr[i + 1]; ++e)
+    for (int64_t e = C.rowptr[i]; e < C.rowptr[i + 1]; ++e) {
+        if (!fem_in_range(e, C.nnz, reinterpret_cast<int*>(C.scal + S_FLAG))) break;
         if (C.colind[e] == (int32_t)i) d = C.ca * C.A[e] + (C.B ? C.cb * C.B[e] : 0.0);
+    }
     if (!(d > 0.0) || !isfinite(d)) {
         atomicOr(reinterpret_cast<int*>(C.scal + S_FLAG), 1);
         d = 1.0;
@@ -418,6 +426,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     int64_t nnz = 0;
     FEM_HIP(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
+    C.nnz = nnz;
     CgLaunch L;
     L.C = C;
     L.G = nnz <= 8 * n ? 4 : nnz <= 16 * n ? 8 : 16;
@@ -432,6 +441,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     FEM_HIP(hipStreamSynchronize(s));
     const double bb = host[S_BB];
     int flag = (int)reinterpret_cast<const int*>(&host[S_FLAG])[0];
+    if (flag & ERR_BOUNDS) return fail(FEM_ERANGE, "fem_cg_solve (checked build): a column index outside [0, n_rows)");
     if (flag & 1) return fail(FEM_EINVAL, "fem_cg_solve: a diagonal entry is not positive");
     double rr = host[S_RR];
     int64_t it = 0;
@@ -464,6 +474,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
         FEM_HIP(hipStreamSynchronize(s));
         rr = host[S_RR];
         flag = (int)reinterpret_cast<const int*>(&host[S_FLAG])[0];
+        if (flag & ERR_BOUNDS) return fail(FEM_ERANGE, "fem_cg_solve (checked build): a column index outside [0, n_rows)");
         if (flag & 2) return fail(FEM_EHIP, "fem_cg_solve: breakdown (p . A p <= 0: the matrix is not positive definite)");
         converged = rr <= target || !std::isfinite(rr);
     }

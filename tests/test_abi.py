@@ -99,3 +99,14 @@ def test_missing_library_fails_loudly():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "is missing" in r.stdout
+
+
+def test_checked_build_exports_every_declared_symbol():
+    """libfem_check.so (the bounds-checked build) is built beside libfem.so and
+    exports the same entry points."""
+    from paper_1409_4618_amd import build
+    if not os.path.exists(build.LIB_CHECK):
+        build.build()
+    L = ctypes.CDLL(build.LIB_CHECK)
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
