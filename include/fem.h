@@ -76,7 +76,9 @@ typedef enum {
 typedef enum {
     FEM_OK = 0,
     FEM_EINVAL = 1,       /* bad argument: NULL pointer, dim not 2/3, kind/dim mismatch, ... */
-    FEM_ERANGE = 2,       /* an element references a node id outside [0, n_nodes)          */
+    FEM_ERANGE = 2,       /* an element references a node id outside [0, n_nodes); in the
+                             checked build (FEM_CHECK=1), also: a kernel met a map index
+                             outside the array it indexes                                   */
     FEM_EDEGENERATE = 3,  /* an element has det B_K == 0 (e.g. a repeated node)            */
     FEM_ENONFINITE = 4,   /* a node coordinate or a Jacobian determinant is not finite     */
     FEM_EOVERFLOW = 5,    /* a size exceeds an index limit (int32 ids, row length > 255)   */
