@@ -185,10 +185,12 @@ def cold_forward(p, s, steps, warmup, flush):
 
 def fwd_bwd_rate(p, steps, warmup):
     """Forward + backward through torch.autograd: K, M, L = assemble_quadratic
-    (fem_assemble and fem_quadratic_value) and L.backward() (the quadratic
-    adjoint, dL/da, dL/db, dL/dnodes), timed with HIP events around each half
-    of every step. Also reported: the adjoint kernels alone, and the adjoint
-    with materialised weights gK = gM = u_row u_col."""
+    (fem_assemble, then fem_quadratic_value_adjoint: L with dL/da, dL/db,
+    dL/dnodes from one pass, since the inputs need gradients) and L.backward()
+    (the upstream factor applied to those derivatives), timed with HIP events
+    around each half of every step. Also reported: the adjoint kernels alone
+    (fem_assemble_backward_quadratic), and the adjoint with materialised
+    weights gK = gM = u_row u_col."""
     import torch
     import paper_1409_4618_amd as fem
     s = setup_mesh(p)
@@ -248,7 +250,8 @@ def fwd_bwd_rate(p, steps, warmup):
     ms_bg = timed(bwd_general, steps, warmup)
     s["mesh"].status()
     out = dict(workload=f"kuhn96_ned3d: {p.T} tets, L = u^T(K(a)+M(b))u through torch.autograd: "
-                        "K, M, L = fem.assemble_quadratic(...), L.backward() (grads wrt a, b, nodes); "
+                        "K, M, L = fem.assemble_quadratic(...) (assembly, then L and its adjoint in one pass), "
+                        "L.backward() (grads wrt a, b, nodes); "
                         "bwd_kernel_ms: the adjoint kernels alone; bwd_general_ms: the adjoint with "
                         "materialised weights gK = gM = u_row u_col",
                fwd_ms=f_ms, bwd_ms=b_ms, fwd_bwd_ms=fb_ms, fwd_bwd_wall_ms=wall_ms,

@@ -188,6 +188,21 @@ fem_status fem_quadratic_value(fem_mesh mesh, fem_kind kind, const double* nodes
                                const double* a, const double* b, const double* u,
                                double* L, void* stream);
 
+/* L = u^T (K(a) + M(b)) u and its adjoint (dL/da, dL/db, dL/dnodes) in one
+ * pass: fem_quadratic_value and fem_assemble_backward_quadratic fused, for a
+ * forward pass whose result will be differentiated (the derivatives are then
+ * ready before the backward pass asks for them; the backward only scales them
+ * by the upstream factor). Not part of the paper. Arguments as in those two
+ * calls; ga, gb, gnodes may be NULL (all three NULL: fem_quadratic_value).
+ * L is summed in the same element order as fem_quadratic_value's; the two may
+ * differ in the last bits (the element terms come from another kernel).
+ * Uses the handle's scratch of fem_quadratic_value. Asynchronous.
+ * FEM_EINVAL if nodes, u or L is NULL; FEM_ENOTREADY before fem_pattern.    */
+fem_status fem_quadratic_value_adjoint(fem_mesh mesh, fem_kind kind, const double* nodes,
+                                       const double* a, const double* b, const double* u,
+                                       double* L, double* ga, double* gb, double* gnodes,
+                                       void* stream);
+
 /* Allocation-free variant of fem_quadratic_value, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc. Same arguments, kernels and result

@@ -20,7 +20,8 @@ from ._lib import (FEM_FN_BUBBLE_F, FEM_FN_BUBBLE_GRAD_U, FEM_FN_BUBBLE_U, FEM_F
                    FEM_FN_EDDY_F, FEM_FN_POLYNOMIAL, FEM_NEDELEC, FEM_RAVIART_THOMAS, FemError, check, hip, lib)
 
 __all__ = ["Mesh", "Batch", "assemble", "assemble_backward", "assemble_backward_quadratic", "FemAssemble", "FemError",
-           "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_form", "assemble_quadratic", "csr_matvec",
+           "kind_code", "NED", "RT", "quadratic_value", "quadratic_value_noalloc", "quadratic_value_adjoint",
+           "quadratic_form", "assemble_quadratic", "csr_matvec",
            "norm_L2", "load_vector", "field_error", "cg_solve", "default_quad_m",
            "FEM_FN_POLYNOMIAL", "FEM_FN_EDDY_E", "FEM_FN_EDDY_CURL_E", "FEM_FN_EDDY_F", "FEM_FN_BUBBLE_U",
            "FEM_FN_BUBBLE_GRAD_U", "FEM_FN_BUBBLE_F", "p1_pattern", "p1_assemble", "p1_load", "p1_dirichlet",
@@ -463,6 +464,25 @@ def assemble_backward_quadratic(mesh: Mesh, kind, nodes, a, b, u, need_a=True, n
     return gn, ga, gb
 
 
+def quadratic_value_adjoint(mesh: Mesh, kind, nodes, a, b, u, need_a=True, need_b=True, need_nodes=True):
+    """(L, dL/dnodes, dL/da, dL/db) of L = u^T (K(a) + M(b)) u from one pass
+    (fem_quadratic_value_adjoint): the forward value with its adjoint ready for
+    a backward pass."""
+    torch = _torch()
+    n_rows, _ = mesh.pattern_info(kind)
+    _check_inputs(mesh, nodes, a, b)
+    _check_dev(u, torch.float64, "u", (n_rows,))
+    dev = nodes.device
+    L = torch.empty((), dtype=torch.float64, device=dev)
+    ga = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_a else None
+    gb = torch.empty(mesh.n_elems, dtype=torch.float64, device=dev) if need_b else None
+    gn = torch.empty_like(nodes) if need_nodes else None
+    check(lib().fem_quadratic_value_adjoint(mesh.handle, kind_code(kind), _ptr(nodes), _ptr(a), _ptr(b), _ptr(u),
+                                            _ptr(L), _ptr(ga), _ptr(gb), _ptr(gn), _stream_ptr()),
+          "fem_quadratic_value_adjoint")
+    return L, gn, ga, gb
+
+
 def _autograd_function():
     torch = _torch()
 
@@ -497,17 +517,35 @@ def _autograd_function():
     return FemAssemble
 
 
+def _quadratic_forward(ctx, nodes, a, b, u, mesh, kind):
+    """L, and when nodes, a or b need a gradient, their derivatives from the
+    same pass (fem_quadratic_value_adjoint), kept for the backward."""
+    need_x, need_a, need_b = ctx.needs_input_grad[:3]
+    ctx.adj = None
+    if need_x or need_a or need_b:
+        L, gn, ga, gb = quadratic_value_adjoint(mesh, kind, nodes, a, b, u, need_a=need_a, need_b=need_b,
+                                                need_nodes=need_x)
+        ctx.adj = (gn, ga, gb)
+    else:
+        L = quadratic_value(mesh, kind, nodes, a, b, u)
+    return L
+
+
 def _quadratic_backward(ctx, gL):
     """Gradients of L = u^T (K(a) + M(b)) u, scaled by the upstream gL: the
-    quadratic adjoint for nodes, a and b, and 2 (K + M) u for u (K and M from
-    the forward when it kept them, else assembled here)."""
+    quadratic adjoint for nodes, a and b (computed by the forward pass), and
+    2 (K + M) u for u (K and M from the forward when it kept them, else
+    assembled here)."""
     nodes, a, b, u = ctx.saved_tensors[:4]
     mesh, kind = ctx.mesh, ctx.kind
-    need_x, need_a, need_b, need_u = ctx.needs_input_grad[:4]
+    need_u = ctx.needs_input_grad[3]
     gn = ga = gb = gu = None
-    if need_x or need_a or need_b:
-        gn, ga, gb = assemble_backward_quadratic(mesh, kind, nodes, a, b, u, need_a=need_a, need_b=need_b,
-                                                 need_nodes=need_x)
+    if ctx.adj is not None:
+        # out of place (a graph kept with retain_graph=True may be differentiated
+        # again), all three in one multi-tensor launch
+        have = [g for g in ctx.adj if g is not None]
+        scaled = iter(_torch()._foreach_mul(have, gL)) if have else iter(())
+        gn, ga, gb = (None if g is None else next(scaled) for g in ctx.adj)
     if need_u:
         if len(ctx.saved_tensors) > 4:
             K, M = ctx.saved_tensors[4:6]
@@ -517,7 +555,8 @@ def _quadratic_backward(ctx, gL):
         gu = csr_matvec(rowptr, colind, K, u, B=M, alpha=2.0, beta=2.0)
     # chain rule: the adjoint kernels compute dL/d(.); the upstream factor
     # (1 for L.backward()) multiplies them
-    gn, ga, gb, gu = (None if g is None else g.mul_(gL) for g in (gn, ga, gb, gu))
+    if gu is not None:
+        gu.mul_(gL)
     return gn, ga, gb, gu
 
 
@@ -530,7 +569,7 @@ def _quadratic_functions():
 
         @staticmethod
         def forward(ctx, nodes, a, b, u, mesh, kind):
-            L = quadratic_value(mesh, kind, nodes, a, b, u)
+            L = _quadratic_forward(ctx, nodes, a, b, u, mesh, kind)
             ctx.mesh = mesh
             ctx.kind = kind
             ctx.save_for_backward(nodes, a, b, u)
@@ -548,7 +587,7 @@ def _quadratic_functions():
         @staticmethod
         def forward(ctx, nodes, a, b, u, mesh, kind):
             K, M = _assemble_values(mesh, kind, nodes, a, b)
-            L = quadratic_value(mesh, kind, nodes, a, b, u)
+            L = _quadratic_forward(ctx, nodes, a, b, u, mesh, kind)
             ctx.mesh = mesh
             ctx.kind = kind
             ctx.mark_non_differentiable(K, M)

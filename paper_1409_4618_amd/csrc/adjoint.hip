@@ -32,6 +32,7 @@ struct BwdArgs {
     const int32_t* elems2dofs; // quadratic form: [T*nloc] global dof of each slot
     double* ga;
     double* gb;
+    double* lpart;             // quadratic form: [workgroups] partials of L (NULL: no value)
     double* partials;          // [pairs][dim] vertex-derivative partial per (node, workgroup)
     const int32_t* bptr;       // [workgroups+1] pairs of each workgroup (workgroup-major)
     const uint16_t* pst;       // [pairs] first incidence of each pair, workgroup-local
@@ -555,6 +556,24 @@ __device__ double2 bwd_tri(const BwdArgs& A, int64_t e, const SlotView& sv, doub
     return gab;
 }
 
+// L_e = a_e dL/da_e + b_e dL/db_e (L is linear in the coefficients), and the
+// workgroup's sum of it by a fixed tree in LDS (red: BWD_BLOCK doubles), the
+// same in k_backward and k_quadratic_value.
+__device__ __forceinline__ double elem_value(const BwdArgs& A, int64_t e, double2 g) {
+    const double2 cab = load_coeffs(A, e);
+    return cab.x * g.x + cab.y * g.y;
+}
+__device__ __forceinline__ double wg_tree_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = BWD_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
 template <int KC, int MODE>
 __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     constexpr int NV = KT<KC>::NV, DIM = KT<KC>::DIM, NLOC = KT<KC>::NLOC;
@@ -623,10 +642,18 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_backward(const BwdArgs A) {
     }
     const SlotView sv = SLOTS ? SlotView{s_base + (int)threadIdx.x * NLOC, s_cp + (int)threadIdx.x * NLOC}
                               : SlotView{A.slot_base + e * NLOC, A.slot_cp + e * NLOC};
+    double2 gab = make_double2(0.0, 0.0);
     if (live) {
-        if constexpr (KC == 2) bwd_ned3<MODE>(A, e, sv, sh);
-        else if constexpr (KC == 1) bwd_rt3<MODE>(A, e, sv, sh);
-        else bwd_tri<MODE>(A, e, sv, sh);
+        if constexpr (KC == 2) gab = bwd_ned3<MODE>(A, e, sv, sh);
+        else if constexpr (KC == 1) gab = bwd_rt3<MODE>(A, e, sv, sh);
+        else gab = bwd_tri<MODE>(A, e, sv, sh);
+    }
+    if constexpr (MODE == BWD_QUADRATIC) {
+        if (A.lpart) {  // uniform: the value of L as well (partials in element order)
+            __shared__ double red[BWD_BLOCK];
+            const double s = wg_tree_sum(live ? elem_value(A, e, gab) : 0.0, red);
+            if (threadIdx.x == 0) A.lpart[blk] = s;
+        }
     }
     if (!A.partials) return;  // uniform
     // the node map's loads into LDS are complete in every wavefront
@@ -700,17 +727,10 @@ __global__ __launch_bounds__(BWD_BLOCK) void k_quadratic_value(const BwdArgs A, 
         if constexpr (KC == 2) g = bwd_ned3<BWD_QUADRATIC>(A, e, sv, nullptr);
         else if constexpr (KC == 1) g = bwd_rt3<BWD_QUADRATIC>(A, e, sv, nullptr);
         else g = bwd_tri<BWD_QUADRATIC>(A, e, sv, nullptr);
-        const double2 cab = load_coeffs(A, e);
-        v = cab.x * g.x + cab.y * g.y;
+        v = elem_value(A, e, g);
     }
-    red[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int w = BWD_BLOCK / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    const double s = wg_tree_sum(v, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // out[0] = sum of n partials: lane t adds t, t + 256, ... in order, then a
@@ -790,8 +810,12 @@ static void launch_bwd_mode(int kc, const BwdArgs& A, unsigned grid, hipStream_t
 
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                            const double* a, const double* b, const double* gK, const double* gM,
-                           const double* u, double* ga, double* gb, double* gnodes, hipStream_t s) {
+                           const double* u, double* ga, double* gb, double* gnodes, double* L,
+                           hipStream_t s) {
     const int kc = kind_code(m->dim, kind);
+    if (L && !u) return fail(FEM_EINVAL, "the value of L comes with the quadratic-form adjoint only");
+    if (L && !m->qv_partials)
+        FEM_HIP(dmalloc(m, &m->qv_partials, std::max<int64_t>(1, quadratic_value_partials(m->T))));
     if (!u && !gK && !gM) {  // L = 0: every derivative is zero
         if (fem_status st = zero_f64(ga, m->T, s)) return st;
         if (fem_status st = zero_f64(gb, m->T, s)) return st;
@@ -816,6 +840,7 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
     A.slot_cp = ds.slot_cp;
     A.ga = ga;
     A.gb = gb;
+    A.lpart = L ? m->qv_partials : nullptr;
     A.partials = gnodes ? m->elem_partials : nullptr;
     A.bptr = m->bwd_bptr;
     A.pst = m->bwd_pst;
@@ -833,6 +858,8 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
         else launch_bwd_mode<BWD_SEPARATE>(kc, A, grid, s);
         FEM_HIP(hipGetLastError());
     }
+    if (L)
+        if (fem_status st = launch_sum_partials(m->qv_partials, quadratic_value_partials(m->T), L, s)) return st;
     if (gnodes && m->V > 0) {
         const unsigned gv = (unsigned)((m->V + 255) / 256);
         if (m->dim == 3)

@@ -229,7 +229,7 @@ fem_status fem_assemble_backward(fem_mesh m, fem_kind kind, const double* nodes,
     if (!ga && !gb && !gnodes) return FEM_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
-    return launch_backward(m, ds, kind, nodes, a, b, gK, gM, nullptr, ga, gb, gnodes, s);
+    return launch_backward(m, ds, kind, nodes, a, b, gK, gM, nullptr, ga, gb, gnodes, nullptr, s);
 }
 
 fem_status fem_assemble_backward_quadratic(fem_mesh m, fem_kind kind, const double* nodes,
@@ -244,7 +244,22 @@ fem_status fem_assemble_backward_quadratic(fem_mesh m, fem_kind kind, const doub
     if (!ga && !gb && !gnodes) return FEM_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
-    return launch_backward(m, ds, kind, nodes, a, b, nullptr, nullptr, u, ga, gb, gnodes, s);
+    return launch_backward(m, ds, kind, nodes, a, b, nullptr, nullptr, u, ga, gb, gnodes, nullptr, s);
+}
+
+fem_status fem_quadratic_value_adjoint(fem_mesh m, fem_kind kind, const double* nodes, const double* a,
+                                       const double* b, const double* u, double* L, double* ga, double* gb,
+                                       double* gnodes, void* stream) {
+    if (!m) return fail(FEM_EINVAL, "fem_quadratic_value_adjoint: mesh is NULL");
+    if (kind != FEM_NEDELEC && kind != FEM_RAVIART_THOMAS)
+        return fail(FEM_EINVAL, "fem_quadratic_value_adjoint: bad kind");
+    if (!nodes || !u || !L) return fail(FEM_EINVAL, "fem_quadratic_value_adjoint: nodes, u or L is NULL");
+    DofSet& ds = dofset(m, kind);
+    if (!ds.pat.built) return fail(FEM_ENOTREADY, "pattern not built: call fem_pattern first");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    m->last_stream = s;
+    if (!ga && !gb && !gnodes) return fem_quadratic_value(m, kind, nodes, a, b, u, L, stream);
+    return launch_backward(m, ds, kind, nodes, a, b, nullptr, nullptr, u, ga, gb, gnodes, L, s);
 }
 
 fem_status fem_quadratic_value(fem_mesh m, fem_kind kind, const double* nodes, const double* a,

@@ -262,10 +262,12 @@ int rows_index(int rows_per_tile);  // 32 -> 0, 64 -> 1, 128 -> 2, 256 -> 3
 fem_status launch_forward(const MeshDev& md, int rows_per_tile, int pmax, hipStream_t s);
 // Adjoint. Weights: gK, gM (either may be NULL = 0), or, when u is not NULL,
 // the quadratic form L = u^T (K(a) + M(b)) u (weights u_I u_J, gK/gM unused).
+// L (device, may be NULL; quadratic form only): the value of L as well, from
+// the same pass.
 fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* nodes,
                            const double* a, const double* b, const double* gK,
                            const double* gM, const double* u, double* ga, double* gb,
-                           double* gnodes, hipStream_t s);
+                           double* gnodes, double* L, hipStream_t s);
 // Value of L = u^T (K(a) + M(b)) u into out[0] (device), through
 // quadratic_value_partials(T) device doubles of scratch.
 int64_t quadratic_value_partials(int64_t n_elems);
