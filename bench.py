@@ -432,62 +432,81 @@ def cpu_baseline(p, target_seconds=12.0, workers=None):
 # (K_RT, M_RT, K_Ned, M_Ned). Context for the level curves, not a target.
 PAPER_3D_S = {1: (0.02, 0.09, 0.05, 0.09), 2: (0.14, 0.39, 0.30, 0.79), 3: (0.82, 2.18, 1.92, 4.53),
               4: (7.15, 15.35, 15.44, 33.43), 5: (59.37, 125.71, 129.91, 282.14),
-              6: (503.89, 1054.49, 1125.08, 2291.50)}
+              6: (503.89, 1054.49, 1125.08, 2291.50), 7: (4437.84, 8717.70, 10232.01, 20028.06)}
 PAPER_2D_S = {5: (0.03, 0.06, 0.03, 0.03), 6: (0.11, 0.51, 0.11, 0.47), 7: (0.41, 1.08, 0.40, 1.02),
               8: (1.70, 3.59, 1.82, 3.65), 9: (7.49, 12.82, 7.49, 12.94), 10: (30.89, 52.09, 30.83, 54.86),
-              11: (132.95, 216.64, 132.56, 230.44), 12: (597.37, 919.36, 583.86, 931.79)}
+              11: (132.95, 216.64, 132.56, 230.44), 12: (597.37, 919.36, 583.86, 931.79),
+              13: (2620.11, 3969.16, 2840.51, 4121.33)}
 
 
-def level_curves(steps, warmup, max_level_2d=12):
+def level_curves(steps, warmup, max_level_3d=7, max_level_2d=13):
     """The paper's timing tables re-run on the GPU: unit coefficients and
     unperturbed meshes (the paper's timing setting), the 3D unit cube at levels
-    1-6 (n = 3 2^level cubes per side, 6 tets each) and the 2D L-shape at levels
-    5-12 (m = 2^level cells per half side), both kinds. Per level and kind: K + M
-    together, K alone and M alone (the paper's columns), warm median of `steps`
-    launches each, M elements/s, the fraction of 8 TB/s (K + M), the growth
-    from the previous level (the paper prints it: 4 in 2D, 8 in 3D is optimal),
-    the paper's seconds beside them, and the CPU oracle (numeric phase, one
-    thread) at the small levels. The paper's 2D levels 13-14 and 3D level 7 have
-    2^31 or more nonzeros, beyond the library's int32 column indices."""
+    1-7 (n = 3 2^level cubes per side, 6 tets each; level 7 has 340 M tets and
+    6.5 G Nedelec nonzeros per matrix) and the 2D L-shape at levels 5-13 (m =
+    2^level cells per half side; level 13 has 3.02 G nonzeros per matrix), both
+    kinds, each on a topology handle of its own (so that one kind's pattern and
+    tiles are resident at a time). The meshes are laid out on the device. Per
+    level and kind: K + M together, K alone and M alone (the paper's columns),
+    warm median of `steps` launches each, M elements/s, the fraction of 8 TB/s
+    (K + M), the growth from the previous level (the paper prints it: 4 in 2D,
+    8 in 3D is optimal), the paper's seconds beside them, and the CPU oracle
+    (numeric phase, one thread) at the small levels. The paper's 2D level 14
+    has 4.8 G element-edge slots (T times the edges per element), beyond the
+    library's int32 slot indices. A level that fails (out of device memory) is
+    recorded with its error and the curve goes on."""
     import torch
     import meshgen as mg
     import oracle
     import paper_1409_4618_amd as fem
     from threadpoolctl import threadpool_limits
+    d = torch.device("cuda:0")
     out = []
     prev = {}
-    cases = ([("cube", L, 3 * 2 ** L) for L in range(1, 7)] +
+    cases = ([("cube", L, 3 * 2 ** L) for L in range(1, max_level_3d + 1)] +
              [("lshape", L, 2 ** L) for L in range(5, max_level_2d + 1)])
     for dom, L, n in cases:
-        nodes, elems = mg.kuhn_box(n) if dom == "cube" else mg.l_shape(n)
-        dim = elems.shape[1] - 1
+        tn, te = mg.kuhn_box_torch(n, d) if dom == "cube" else mg.l_shape_torch(n, d)
+        T, dim = int(te.shape[0]), int(te.shape[1]) - 1
         paper = (PAPER_3D_S if dim == 3 else PAPER_2D_S)[L]
-        for kind in ("rt", "ned"):
-            p = mg.Problem(f"{dom}{L}_{kind}", kind, nodes, elems)
-            s = setup_mesh(p)
-            st, wu = max(5, steps // 10), max(2, warmup // 10)
-            f = forward_rate(p, s, st, wu)
-            k_ms = timed(lambda: fem.assemble_into(s["mesh"], kind, s["nodes"], None, None, s["K"], None), st, wu)
-            m_ms = timed(lambda: fem.assemble_into(s["mesh"], kind, s["nodes"], None, None, None, s["M"]), st, wu)
-            s["mesh"].status()
-            pk, pm = (paper[0], paper[1]) if kind == "rt" else (paper[2], paper[3])
-            row = {"domain": dom, "level": L, "kind": kind, "elements": int(elems.shape[0]), "rows": s["n_rows"],
-                   "nnz": s["nnz"], "ms": round(f["ms"], 5), "k_ms": round(k_ms, 5), "m_ms": round(m_ms, 5),
-                   "mel_s": round(f["mtets"], 1), "frac": round(f["frac"], 4),
-                   "paper_k_s": pk, "paper_m_s": pm, "paper_mel_s": round(elems.shape[0] / (pk + pm) / 1e6, 4)}
-            if (dom, kind) in prev:
-                row["growth"] = round(f["ms"] / prev[(dom, kind)], 2)
-            prev[(dom, kind)] = f["ms"]
-            if elems.shape[0] <= 100000:
-                with threadpool_limits(limits=1):
-                    t0 = time.perf_counter()
-                    oracle.assemble(nodes, elems, kind)
-                    row["oracle_1thread_mel_s"] = round(elems.shape[0] / (time.perf_counter() - t0) / 1e6, 4)
-            out.append(row)
-            del s
-            torch.cuda.empty_cache()
-        log(f"bench:   {dom} level {L}: {out[-1]['mel_s']} M el/s (ned), {out[-2]['mel_s']} (rt)")
-        del nodes, elems
+        mesh = s = None
+        try:
+            for kind in ("rt", "ned"):
+                mesh = s = None
+                torch.cuda.empty_cache()
+                mesh = fem.Mesh(tn, te)
+                p = mg.Problem(f"{dom}{L}_{kind}", kind, tn, te)
+                n_rows, nnz = mesh.pattern_info(kind)
+                s = dict(mesh=mesh, nodes=tn, elems=te, a=None, b=None, nnz=nnz, n_rows=n_rows,
+                         K=torch.empty(nnz, dtype=torch.float64, device=d),
+                         M=torch.empty(nnz, dtype=torch.float64, device=d))
+                st, wu = max(5, steps // 10), max(2, warmup // 10)
+                f = forward_rate(p, s, st, wu)
+                k_ms = timed(lambda: fem.assemble_into(mesh, kind, tn, None, None, s["K"], None), st, wu)
+                m_ms = timed(lambda: fem.assemble_into(mesh, kind, tn, None, None, None, s["M"]), st, wu)
+                mesh.status()
+                pk, pm = (paper[0], paper[1]) if kind == "rt" else (paper[2], paper[3])
+                row = {"domain": dom, "level": L, "kind": kind, "elements": T, "rows": n_rows, "nnz": nnz,
+                       "ms": round(f["ms"], 5), "k_ms": round(k_ms, 5), "m_ms": round(m_ms, 5),
+                       "mel_s": round(f["mtets"], 1), "frac": round(f["frac"], 4),
+                       "paper_k_s": pk, "paper_m_s": pm, "paper_mel_s": round(T / (pk + pm) / 1e6, 4)}
+                if (dom, kind) in prev:
+                    row["growth"] = round(f["ms"] / prev[(dom, kind)], 2)
+                prev[(dom, kind)] = f["ms"]
+                if T <= 100000:
+                    nodes, elems = tn.cpu().numpy(), te.cpu().numpy()
+                    with threadpool_limits(limits=1):
+                        t0 = time.perf_counter()
+                        oracle.assemble(nodes, elems, kind)
+                        row["oracle_1thread_mel_s"] = round(T / (time.perf_counter() - t0) / 1e6, 4)
+                out.append(row)
+            log(f"bench:   {dom} level {L}: {out[-1]['mel_s']} M el/s (ned), {out[-2]['mel_s']} (rt)")
+        except (RuntimeError, fem.FemError) as e:
+            out.append({"domain": dom, "level": L, "elements": T, "error": str(e)[:200]})
+            log(f"bench:   {dom} level {L}: not run ({str(e)[:120]})")
+        mesh = s = None
+        del tn, te
+        torch.cuda.empty_cache()
     return out
 
 

@@ -96,7 +96,7 @@ typedef enum {
  * validates the mesh (node ids in range, finite coordinates, det B_K != 0).
  * Synchronises `stream` (to learn the number of edges / faces).
  * On success *out owns the topology; release it with fem_mesh_destroy.
- * Limits: n_elems * (edges per element) < 2^31, n_nodes < 2^31.             */
+ * Limits: n_elems * (edges per element) < 2^31, n_nodes * dim < 2^31.       */
 fem_status fem_topology(const double* nodes, int64_t n_nodes, int dim,
                         const int32_t* elems, int64_t n_elems,
                         void* stream, fem_mesh* out);
@@ -122,9 +122,10 @@ fem_status fem_mesh_topology(fem_mesh mesh, const int32_t** edges2nodes,
  * edges (Nedelec, 2D RT) or faces (3D RT). Outputs may be NULL.
  * The element pairs are sorted in chunks of whole rows (at most 2^29 pairs
  * each; the environment variable FEM_PAIR_CHUNK sets another bound), so
- * n_elems * n_local^2 may exceed 2^31 (3D Nedelec on a 60 M-tet mesh).
- * FEM_EOVERFLOW if a row has more than 255 entries or nnz >= 2^31; a refused
- * build keeps nothing, and the other kind's pattern can still be built.      */
+ * n_elems * n_local^2 may exceed 2^31 (3D Nedelec on a 60 M-tet mesh), and
+ * so may nnz (rowptr is i64; colind holds column numbers, which are below
+ * n_rows). FEM_EOVERFLOW if a row has more than 255 entries; a refused build
+ * keeps nothing, and the other kind's pattern can still be built.            */
 fem_status fem_pattern(fem_mesh mesh, fem_kind kind, void* stream,
                        int64_t* n_rows, int64_t* nnz,
                        const int64_t** rowptr, const int32_t** colind);
@@ -149,7 +150,10 @@ fem_status fem_assemble(fem_mesh mesh, fem_kind kind, const double* nodes,
  *   ga, gb  dev f64 [n_elems] outputs dL/da, dL/db (NULL to skip)
  *   gnodes  dev f64 [n_nodes][dim] output dL/dnodes (NULL to skip); overwritten,
  *           nodes in no element get 0.
- * Uses library-owned scratch inside the handle (allocated on first use).    */
+ * Uses library-owned scratch inside the handle (allocated on first use).
+ * FEM_EOVERFLOW if nnz >= 2^31 (its per-slot row starts are 32-bit); the
+ * quadratic form (fem_assemble_backward_quadratic) reads no nnz-sized array
+ * and has no such limit.                                                     */
 fem_status fem_assemble_backward(fem_mesh mesh, fem_kind kind, const double* nodes,
                                  const double* a, const double* b,
                                  const double* gK, const double* gM,

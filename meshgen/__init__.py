@@ -86,6 +86,33 @@ def kuhn_box(nx: int, ny: Optional[int] = None, nz: Optional[int] = None,
     return nodes, elems
 
 
+def kuhn_box_torch(n: int, device):
+    """The mesh of ``kuhn_box(n)`` (unit cube, n cubes per side), laid out with
+    torch on ``device`` (the same node coordinates, taken from the same
+    ``numpy.linspace`` values, and the same element lists), for sizes whose
+    host-side layout would be slow: float64 nodes [V, 3] and int32 elems
+    [T, 4] tensors."""
+    import torch
+    xs = torch.tensor(np.linspace(0.0, 1.0, n + 1), dtype=torch.float64, device=device)
+    g = torch.arange(n + 1, device=device)
+    k, j, i = torch.meshgrid(g, g, g, indexing="ij")  # i fastest
+    nodes = torch.stack([xs[i.reshape(-1)], xs[j.reshape(-1)], xs[k.reshape(-1)]], dim=1)
+    del i, j, k
+    c = torch.arange(n, device=device, dtype=torch.int32)
+    k, j, i = torch.meshgrid(c, c, c, indexing="ij")
+    stride = (1, n + 1, (n + 1) * (n + 1))
+    v0 = (i + stride[1] * j + stride[2] * k).reshape(-1)
+    del i, j, k
+    tets = []
+    for p in KUHN_PERMS:
+        n1 = v0 + stride[p[0]]
+        n2 = n1 + stride[p[1]]
+        tets.append(torch.stack([v0, n1, n2, n2 + stride[p[2]]], dim=1))
+        del n1, n2
+    elems = torch.stack(tets, dim=1).reshape(-1, 4)
+    return nodes, elems
+
+
 def l_shape(m: int):
     """Triangle mesh of (0,1)^2 minus [1/2,1)^2 with ``m`` cells per half side."""
     n = 2 * m
@@ -110,6 +137,29 @@ def l_shape(m: int):
     t2 = np.stack([v00, v11, v01], axis=1)
     elems = np.stack([t1, t2], axis=1).reshape(-1, 3).astype(np.int32)
     return nodes.astype(np.float64), elems
+
+
+def l_shape_torch(m: int, device):
+    """The mesh of ``l_shape(m)``, laid out with torch on ``device`` (the same
+    node order and element lists), for sizes whose host-side layout would be
+    slow: float64 nodes [V, 2] and int32 elems [T, 3] tensors."""
+    import torch
+    n = 2 * m
+    g = torch.arange(n + 1, device=device)
+    j, i = torch.meshgrid(g, g, indexing="ij")  # node (i, j) at grid index i + (n+1) j
+    keep = (~((i > m) & (j > m))).reshape(-1)
+    new_id = torch.cumsum(keep.to(torch.int64), 0) - 1
+    h = 1.0 / n
+    nodes = torch.stack([i.reshape(-1)[keep], j.reshape(-1)[keep]], dim=1).to(torch.float64) * h
+    del i, j
+    c = torch.arange(n, device=device)
+    cj, ci = torch.meshgrid(c, c, indexing="ij")
+    cell_keep = (~((ci >= m) & (cj >= m))).reshape(-1)
+    g00 = (ci.reshape(-1) + (n + 1) * cj.reshape(-1))[cell_keep]
+    del ci, cj, cell_keep
+    v00, v10, v01, v11 = (new_id[g00 + d].to(torch.int32) for d in (0, 1, n + 1, n + 2))
+    elems = torch.stack([v00, v10, v11, v00, v11, v01], dim=1).reshape(-1, 3)
+    return nodes, elems
 
 
 def boundary_mask(nodes: np.ndarray, lo=None, hi=None, tol: float = 1e-12) -> np.ndarray:

@@ -119,22 +119,25 @@ class Mesh:
             except Exception:
                 pass
 
-    def topology(self):
-        """Copies of the topology arrays as device tensors (dict)."""
+    def topology(self, names=None):
+        """Copies of the topology arrays as device tensors (dict): all of them, or
+        those in ``names``."""
         torch = _torch()
         ptrs = [ctypes.c_void_p() for _ in range(6)]
         check(lib().fem_mesh_topology(self._h, *[ctypes.byref(p) for p in ptrs]), "fem_mesh_topology")
         ne = 6 if self.dim == 3 else 3
-        out = {
-            "edges2nodes": _copy_from_device(ptrs[0].value, 2 * self.n_edges, torch.int32).view(-1, 2),
-            "elems2edges": _copy_from_device(ptrs[1].value, ne * self.n_elems, torch.int32).view(-1, ne),
-            "signs_e": _copy_from_device(ptrs[2].value, ne * self.n_elems, torch.int8).view(-1, ne),
-        }
+        layout = {"edges2nodes": (0, 2, self.n_edges, torch.int32), "elems2edges": (1, ne, self.n_elems, torch.int32),
+                  "signs_e": (2, ne, self.n_elems, torch.int8)}
         if self.dim == 3:
-            out["faces2nodes"] = _copy_from_device(ptrs[3].value, 3 * self.n_faces, torch.int32).view(-1, 3)
-            out["elems2faces"] = _copy_from_device(ptrs[4].value, 4 * self.n_elems, torch.int32).view(-1, 4)
-            out["signs_f"] = _copy_from_device(ptrs[5].value, 4 * self.n_elems, torch.int8).view(-1, 4)
-        return out
+            layout.update({"faces2nodes": (3, 3, self.n_faces, torch.int32),
+                           "elems2faces": (4, 4, self.n_elems, torch.int32),
+                           "signs_f": (5, 4, self.n_elems, torch.int8)})
+        if names is not None:
+            unknown = set(names) - set(layout)
+            if unknown:
+                raise ValueError(f"unknown topology arrays: {sorted(unknown)}")
+            layout = {k: layout[k] for k in names}
+        return {k: _copy_from_device(ptrs[i].value, w * n, dt).view(-1, w) for k, (i, w, n, dt) in layout.items()}
 
     def pattern_info(self, kind):
         """(n_rows, nnz) of the CSR pattern of ``kind`` (built on first use)."""

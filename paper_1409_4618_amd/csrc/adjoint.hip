@@ -821,12 +821,12 @@ fem_status launch_backward(fem_mesh m, DofSet& ds, fem_kind kind, const double* 
         if (fem_status st = zero_f64(gb, m->T, s)) return st;
         return zero_f64(gnodes, m->V * m->dim, s);
     }
+    if (!u)
+        if (fem_status st = build_slot_map(m, ds, s)) return st;
     if (gnodes) {
         if (fem_status st = build_node_map(m, s)) return st;
         if (!m->elem_partials) FEM_HIP(dmalloc(m, &m->elem_partials, std::max<int64_t>(m->bwd_pairs, 1) * m->dim));
     }
-    if (!u)
-        if (fem_status st = build_slot_map(m, ds, s)) return st;
     BwdArgs A;
     A.u = u;
     A.elems2dofs = ds.elems2dofs;

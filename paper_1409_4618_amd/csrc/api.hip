@@ -99,7 +99,7 @@ fem_status fem_topology(const double* nodes, int64_t n_nodes, int dim, const int
     if (n_nodes <= 0 || n_elems <= 0) return fail(FEM_EINVAL, "fem_topology: empty mesh");
     if (!nodes || !elems) return fail(FEM_EINVAL, "fem_topology: nodes or elems is NULL");
     const int ne = dim == 3 ? 6 : 3;
-    if (n_nodes >= (int64_t(1) << 31) || n_elems * ne >= (int64_t(1) << 31) ||
+    if (n_nodes * dim >= (int64_t(1) << 31) || n_elems * ne >= (int64_t(1) << 31) ||
         n_elems * (dim + 1) >= (int64_t(1) << 31))
         return fail(FEM_EOVERFLOW, "fem_topology: mesh exceeds the int32 index limits");
     fem_mesh m = new fem_mesh_s();

@@ -119,7 +119,7 @@ struct DofSet {
     Pattern pat;
     // adjoint gather map, element-major: for slot e*nloc + k, the CSR position
     // of its row's first entry and its column-offset record (built on first use)
-    int32_t* slot_base = nullptr;  // [T*nloc] (< 2^31: nnz < 2^31 is checked when the pattern is built)
+    int32_t* slot_base = nullptr;  // [T*nloc] (built only for nnz < 2^31)
     uint64_t* slot_cp = nullptr;   // [T*nloc]
     bool slot_map_built = false;   // set once every step of the build has succeeded
 };

@@ -26,6 +26,10 @@ namespace fem {
 
 constexpr int TB = 256;
 
+// Workgroups for one thread per item. A dispatch counts its work-items in 32
+// bits, so n must stay below 2^32 - t: every launch here is over at most
+// T * (edges or faces per element), n_nodes * dim, the rows, the tiles or one
+// pair chunk, all below 2^31 by the limits fem_topology and fem_pattern check.
 static inline unsigned nblk(int64_t n, int t = TB) { return (unsigned)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------- validation
@@ -278,13 +282,14 @@ struct TmpBufs {
         if ((e = hipMalloc((void**)&scan, n * sizeof(uint32_t))) != hipSuccess) return e;
         return hipSuccess;
     }
-    ~TmpBufs() {
-        if (keys) (void)hipFree(keys);
-        if (keys_tmp) (void)hipFree(keys_tmp);
-        if (vals) (void)hipFree(vals);
-        if (vals_tmp) (void)hipFree(vals_tmp);
-        if (scan) (void)hipFree(scan);
+    // (callers synchronise the stream that used the buffers first)
+    void release() {
+        for (void** q : {(void**)&keys, (void**)&keys_tmp, (void**)&vals, (void**)&vals_tmp, (void**)&scan}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
+        }
     }
+    ~TmpBufs() { release(); }
 };
 
 // ---------------------------------------------------------------- topology
@@ -428,20 +433,24 @@ __global__ void k_pair_keys(const int32_t* rs_slot, int64_t n, const int32_t* el
 }
 
 // After the exclusive scan of the head flags: the CSR position of each sorted
-// pair is base + (its unique rank); heads write the column and, at a row's
-// first entry, the row start. map[pair] = CSR position (chunk-local pairs).
+// pair is base + (its unique rank within the chunk); heads write the column
+// at that rank in the chunk's column buffer and, at a row's first entry, the
+// row start. map[pair] = the unique rank (chunk-local pairs; below 2^31
+// because a chunk has fewer pairs), so the total number of nonzeros is not
+// bounded by the map's width.
 __global__ void k_pair_unique(const uint64_t* keys, const uint32_t* sorted_pairs,
                               const uint32_t* scan, int64_t n, int64_t N, int64_t base,
-                              int32_t* colind, int64_t* rowptr, int32_t* map) {
+                              int32_t* cols, int64_t* rowptr, uint32_t* map) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
     const bool head = (i == 0 || k != keys[i - 1]);
-    const int64_t id = base + (int64_t)(scan[i] + (head ? 1u : 0u) - 1u);
-    map[sorted_pairs[i]] = (int32_t)id;
+    const uint32_t local = scan[i] + (head ? 1u : 0u) - 1u;
+    const int64_t id = base + (int64_t)local;
+    map[sorted_pairs[i]] = local;
     if (head) {
         const uint64_t row = k / (uint64_t)N;
-        colind[id] = (int32_t)(k - row * (uint64_t)N);
+        cols[local] = (int32_t)(k - row * (uint64_t)N);
         if (i == 0 || keys[i - 1] / (uint64_t)N != row) rowptr[row] = id;
     }
 }
@@ -453,16 +462,17 @@ __global__ void k_slot_rank(const int32_t* rs_slot, int64_t n, int32_t* rank) {
 }
 
 // Column offsets of the slots j0 .. j0+n of the row-sorted list (the same
-// chunk as the pairs in map): byte l = CSR position of (row, dof l) minus the
-// row start.
-__global__ void k_colpos(const int32_t* rs_slot, int64_t n, const int32_t* elems2dofs, const int32_t* map,
-                         const int64_t* rowptr, int nloc, int cp, uint8_t* colpos, int* err) {
+// chunk as the pairs in map, whose first nonzero is chunk_base): byte l = CSR
+// position of (row, dof l) minus the row start.
+__global__ void k_colpos(const int32_t* rs_slot, int64_t n, const int32_t* elems2dofs, const uint32_t* map,
+                         int64_t chunk_base, const int64_t* rowptr, int nloc, int cp, uint8_t* colpos,
+                         int* err) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int64_t base = rowptr[elems2dofs[rs_slot[j]]];
     uint8_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int l = 0; l < nloc; ++l) {
-        const int64_t off = (int64_t)map[j * nloc + l] - base;
+        const int64_t off = chunk_base + (int64_t)map[j * nloc + l] - base;
         if (off < 0 || off > 255) atomicOr(err, ERR_OVERFLOW);
         out[l] = (uint8_t)off;
     }
@@ -504,6 +514,13 @@ __global__ __launch_bounds__(256) void k_row_stats(const int64_t* rowptr, int64_
         for (int q = 0; q < 4; ++q) atomicMax(&tile_pmax[q], red[1 + q][0]);
     }
 }
+
+// Frees a temporary device buffer when the builder returns, on any path.
+template <class T>
+struct FreeOnExit {
+    T** p;
+    ~FreeOnExit() { (void)hipFree(*p); }
+};
 
 fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     Pattern& p = ds.pat;
@@ -572,14 +589,20 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
     FEM_HIP(tb.alloc(std::max<int64_t>(max_pairs, 8)));
     const int bits = bit_length((uint64_t)N * (uint64_t)N - 1);
     FEM_HIP(alloc(&p.rowptr, N + 1));
-    int32_t* map = nullptr;     // CSR position of every pair of the current chunk
-    int32_t* staged = nullptr;  // several chunks: columns until the total is known
-    struct Free {
-        int32_t** p;
-        ~Free() { (void)hipFree(*p); }
-    } free_map{&map}, free_staged{&staged};
-    FEM_HIP(hipMalloc((void**)&map, (size_t)max_pairs * sizeof(int32_t)));
-    if (n_chunks > 1) FEM_HIP(hipMalloc((void**)&staged, (size_t)n_pairs * sizeof(int32_t)));
+    uint32_t* map = nullptr;  // chunk-local CSR position of every pair of the current chunk
+    FreeOnExit<uint32_t> free_map{&map};
+    // several chunks: each chunk's columns in a buffer of its own until the
+    // total is known (nnz words in all, not one per element pair)
+    struct Staged {
+        std::vector<std::pair<int32_t*, int64_t>> v;
+        ~Staged() {
+            for (auto& q : v) (void)hipFree(q.first);
+        }
+    } staged;
+    FEM_HIP(hipMalloc((void**)&map, (size_t)max_pairs * sizeof(uint32_t)));
+    int* stats = nullptr;  // row statistics: longest row, most values of a tile of 32 .. 256 rows
+    FreeOnExit<int> free_stats{&stats};
+    FEM_HIP(hipMalloc((void**)&stats, 5 * sizeof(int)));
     FEM_HIP(alloc(&p.colpos, n_slots * p.cp_stride));
     FEM_HIP(hipMemsetAsync(m->err_word, 0, sizeof(int), s));
     int64_t nnz = 0;
@@ -595,28 +618,46 @@ fem_status build_pattern(fem_mesh m, DofSet& ds, hipStream_t s) {
         FEM_HIP(scan_exclusive_u32(tb.scan, np, s));
         int64_t nc = 0;
         if (fem_status st = read_count(tb.scan, tb.keys, np, s, &nc)) return st;
-        if (nnz + nc >= (int64_t(1) << 31))
-            return fail(FEM_EOVERFLOW, "fem_pattern: more than 2^31 - 1 nonzeros");
-        if (n_chunks == 1) FEM_HIP(alloc(&p.colind, nc));
+        int32_t* cols = nullptr;
+        if (n_chunks == 1) {
+            FEM_HIP(alloc(&p.colind, nc));
+            cols = p.colind;
+        } else {
+            FEM_HIP(hipMalloc((void**)&cols, (size_t)std::max<int64_t>(nc, 1) * sizeof(int32_t)));
+            staged.v.push_back({cols, nc});
+        }
         hipLaunchKernelGGL(k_pair_unique, dim3(nblk(np)), dim3(TB), 0, s, tb.keys, tb.vals, tb.scan, np, N,
-                           nnz, n_chunks == 1 ? p.colind : staged, p.rowptr, map);
+                           nnz, cols, p.rowptr, map);
         hipLaunchKernelGGL(k_colpos, dim3(nblk(ns)), dim3(TB), 0, s, ds.rs_slot + j0, ns, ds.elems2dofs, map,
-                           p.rowptr, nloc, p.cp_stride, p.colpos + j0 * p.cp_stride, m->err_word);
+                           nnz, p.rowptr, nloc, p.cp_stride, p.colpos + j0 * p.cp_stride, m->err_word);
         FEM_HIP(hipGetLastError());
         nnz += nc;
     }
     p.nnz = nnz;
     if (n_chunks > 1) {
+        // the sort buffers and the map are done with: free them before the
+        // final column array, and each chunk's buffer once it is copied
+        FEM_HIP(hipStreamSynchronize(s));
+        tb.release();
+        (void)hipFree(map);
+        map = nullptr;
         FEM_HIP(alloc(&p.colind, nnz));
-        FEM_HIP(hipMemcpyAsync(p.colind, staged, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        int64_t at = 0;
+        for (auto& q : staged.v) {
+            FEM_HIP(hipMemcpyAsync(p.colind + at, q.first, (size_t)q.second * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+            FEM_HIP(hipStreamSynchronize(s));
+            (void)hipFree(q.first);
+            q.first = nullptr;
+            at += q.second;
+        }
+        staged.v.clear();
     }
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p.rowptr + N, nnz);
     FEM_HIP(hipGetLastError());
     FEM_HIP(alloc(&p.slot_rank, n_slots));
     hipLaunchKernelGGL(k_slot_rank, dim3(nblk(n_slots)), dim3(TB), 0, s, ds.rs_slot, n_slots, p.slot_rank);
     FEM_HIP(hipGetLastError());
-    // row statistics (reuse the scan buffer as 4 ints)
-    int* stats = reinterpret_cast<int*>(tb.scan);
     FEM_HIP(hipMemsetAsync(stats, 0, 5 * sizeof(int), s));
     hipLaunchKernelGGL(k_row_stats, dim3(nblk(N)), dim3(TB), 0, s, p.rowptr, N, stats, stats + 1);
     FEM_HIP(hipGetLastError());
@@ -679,6 +720,9 @@ struct Staged {
 
 fem_status build_slot_map(fem_mesh m, DofSet& ds, hipStream_t s) {
     if (ds.slot_map_built) return FEM_OK;
+    if (ds.pat.nnz >= (int64_t(1) << 31))
+        return fail(FEM_EOVERFLOW, "fem_assemble_backward: weights per nonzero need nnz < 2^31 "
+                                   "(the quadratic form has no such limit)");
     Staged st{m, {}};
     const int64_t n = m->T * ds.nloc;
     FEM_HIP(st.alloc(&ds.slot_base, n));
@@ -871,9 +915,11 @@ __global__ void k_ema_stats(const int64_t* rowptr, const int32_t* rs_ptr, int64_
     atomicMax(max_slots, rs_ptr[r1] - rs_ptr[r0]);
 }
 
-__global__ void k_fill_u16(uint16_t* p, int64_t n, uint16_t v) {
+// Every entry's eight in-tile slot words set to 0xFFFF (none in the tile),
+// one 16-byte entry per thread.
+__global__ void k_clear_joff(uint4* joff, int64_t n_ent) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i < n_ent) joff[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
 }
 
 // One attempt at tiles of R rows; allocations are plain (freed by the caller
@@ -902,8 +948,8 @@ static fem_status ema_attempt(fem_mesh m, DofSet& ds, int R, hipStream_t s, Patt
     hipLaunchKernelGGL(k_tile_unique, dim3(nblk(n_slots)), dim3(TB), 0, s, tb.keys, tb.scan, n_slots,
                        T, out.elems, out.eptr);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, out.eptr + n_tiles, (int32_t)n_ent);
-    hipLaunchKernelGGL(k_fill_u16, dim3(nblk(n_ent * 8)), dim3(TB), 0, s, out.joff, n_ent * 8,
-                       (uint16_t)0xFFFF);
+    hipLaunchKernelGGL(k_clear_joff, dim3(nblk(n_ent)), dim3(TB), 0, s, reinterpret_cast<uint4*>(out.joff),
+                       n_ent);
     FEM_HIP(hipGetLastError());
     int* stats = reinterpret_cast<int*>(tb.keys_tmp);  // [4]: max_elems, overflow, pmax, max_slots
     FEM_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(int), s));

@@ -59,6 +59,8 @@ def test_argument_errors_without_gpu(L):
                           ctypes.byref(out)) == 5
     assert L.fem_topology(ctypes.c_void_p(16), 10, 3, ctypes.c_void_p(16), 1 << 29, None,
                           ctypes.byref(out)) == 5
+    assert L.fem_topology(ctypes.c_void_p(16), 1 << 30, 3, ctypes.c_void_p(16), 10, None,
+                          ctypes.byref(out)) == 5  # n_nodes * dim >= 2^31
     # NULL handles
     assert L.fem_assemble(None, FEM_NEDELEC, None, None, None, None, None, None) == 1
     assert L.fem_assemble_backward(None, FEM_NEDELEC, *([None] * 9)) == 1

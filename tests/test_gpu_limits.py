@@ -15,11 +15,25 @@ Kuhn 216^3 (60,466,176 tets, 10,218,313 nodes), 3D Nedelec:
   K G = 0 for the discrete gradient and the constant-field identity
   u^T M(b) u = |c|^2 sum_K b_K |K| on the whole output.
 
-Kuhn 266^3 (112,926,576 tets): the Nedelec pattern would have more than
-2^31 - 1 nonzeros (E + 6F + 6T = 2,167,610,858 at that size), so fem_pattern
-refuses it with FEM_EOVERFLOW (status 5), keeps nothing of the attempt, and
-the handle stays usable: the Raviart-Thomas pattern of the same mesh
-(1.58 G nonzeros) still builds.
+Kuhn 266^3 (112,926,576 tets), 3D Nedelec: the pattern has
+E + 6F + 6T = 2,167,610,858 >= 2^31 nonzeros, so CSR positions pass the int32
+range (rowptr is int64; the pattern builder's pair map holds positions
+relative to its chunk). The assembled K and M (17.3 GB each) are
+deterministic and satisfy the identities above, checked in row chunks; the
+quadratic adjoint's dL/da and dL/db add up to u^T K u and u^T M u formed from
+those values, and fem_quadratic_value to their sum. The adjoint with weights
+per nonzero is refused with FEM_EOVERFLOW (status 5: its per-slot row starts
+are 32-bit) and the handle stays usable: the Raviart-Thomas pattern of the
+same mesh (F + 12 T = 1.58 G nonzeros) still builds.
+
+The 2D L-shape of the paper's timing table at level 13 (402,653,184
+triangles; more tile entries than one work-item each can address in a
+dispatch's 32-bit grid, so the tile builder clears them per entry): edge count
+as printed, 3.02 G nonzeros, deterministic, the same identities.
+
+The 3D cube of the paper's timing table at level 7 (Kuhn 384^3, 339,738,624
+tets; 6 T = 2.04 G element-edge slots, just below 2^31): face and edge counts
+as printed, 6.52 G Nedelec nonzeros, the same identities on the whole output.
 """
 import numpy as np
 import pytest
@@ -30,6 +44,19 @@ from oracle.reference import LOCAL_EDGES, LOCAL_FACES
 from gpu_util import say
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def release_device_memory():
+    """These meshes take most of the device: release what earlier tests left in
+    torch's cache (and unreferenced handles) before and after each."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
 
 
 def kuhn_on_device(n):
@@ -65,7 +92,8 @@ def test_kuhn216_beyond_2_31_element_pairs():
     check_identities(mesh, tn, K, M)
 
 
-def test_kuhn266_nedelec_pattern_is_refused():
+def test_kuhn266_nedelec_beyond_2_31_nonzeros():
+    import torch
     import paper_1409_4618_amd as fem
     from paper_1409_4618_amd import FemError
     n = 266
@@ -74,51 +102,181 @@ def test_kuhn266_nedelec_pattern_is_refused():
     assert E + 6 * F + 6 * T >= 2 ** 31 > F + 12 * T
     say(f"[gpu] index limit: Kuhn {n}^3, T={T}")
     mesh = fem.Mesh(tn, te)
+    say("    Nedelec pattern beyond 2^31 nonzeros")
+    N, nnz = mesh.pattern_info("ned")
+    assert N == E and nnz == E + 6 * F + 6 * T
+    K, M = fem.assemble(mesh, "ned", tn)
+    K2, M2 = fem.assemble(mesh, "ned", tn)
+    mesh.status()
+    assert torch.equal(K, K2) and torch.equal(M, M2)
+    del K2, M2
+    torch.cuda.empty_cache()
+    say("    whole-output identities")
+    rng = np.random.default_rng(11)
+    u = torch.tensor(rng.normal(size=N), device=tn.device)
+    uKu, uMu, scale = check_identities(mesh, tn, K, M, u)
+    say("    quadratic adjoint against the assembled values")
+    _, ga, gb = fem.assemble_backward_quadratic(mesh, "ned", tn, None, None, u, need_nodes=False)
+    mesh.status()
+    sa, sb = float(ga.sum()), float(gb.sum())
+    say(f"    sum dL/da vs u^T K u: {abs(sa - uKu) / scale[0]:.2e}; "
+        f"sum dL/db vs u^T M u: {abs(sb - uMu) / scale[1]:.2e}")
+    assert abs(sa - uKu) <= 1e-12 * scale[0] and abs(sb - uMu) <= 1e-12 * scale[1]
+    L = float(fem.quadratic_value(mesh, "ned", tn, None, None, u))
+    assert abs(L - (uKu + uMu)) <= 1e-12 * (scale[0] + scale[1])
+    del ga, gb
+    say("    weights per nonzero: refused, the handle stays usable")
     with pytest.raises(FemError) as ei:
-        mesh.pattern_info("ned")
+        fem.assemble_backward(mesh, "ned", tn, None, None, K, M)
     assert ei.value.status == 5
     mesh.status()
+    del K, M
+    torch.cuda.empty_cache()
     N, nnz = mesh.pattern_info("rt")
     assert N == F and nnz == F + 12 * T
 
 
-def check_identities(mesh, tn, K, M):
-    """Bitwise symmetry, K G = 0 and the constant-field identity (b = 1) on
-    the whole output (elementwise torch ops: no library gemv)."""
+def test_lshape_level13_beyond_2_31_nonzeros():
+    """The paper's 2D timing mesh at level 13 (402,653,184 triangles), laid out
+    on the device: its edge count is the paper's printed matrix size, the
+    Nedelec pattern has E + 6T = 3.02 G nonzeros, and K and M satisfy the
+    identities above on the whole output (the L-shape has area 3/4)."""
     import torch
+    import paper_1409_4618_amd as fem
+    tn, te = mg.l_shape_torch(2 ** 13, torch.device("cuda:0"))
+    T = te.shape[0]
+    assert T == 402_653_184
+    say(f"[gpu] index limit: L-shape level 13, T={T}")
+    mesh = fem.Mesh(tn, te)
+    N, nnz = mesh.pattern_info("ned")
+    assert N == 604_012_544 and nnz == N + 6 * T and nnz >= 2 ** 31
+    K, M = fem.assemble(mesh, "ned", tn)
+    K2, M2 = fem.assemble(mesh, "ned", tn)
+    mesh.status()
+    assert torch.equal(K, K2) and torch.equal(M, M2)
+    del K2, M2
+    torch.cuda.empty_cache()
+    say("    whole-output identities")
+    check_identities(mesh, tn, K, M, volume=0.75)
+
+
+def test_cube_level7_paper_sizes():
+    """The paper's largest 3D timing mesh (level 7: Kuhn 384^3, 339,738,624
+    tets), laid out on the device: the face and edge counts are the paper's
+    printed matrix sizes, the Nedelec pattern has E + 6F + 6T = 6.52 G
+    nonzeros, and K and M (52 GB each) satisfy the identities above on the
+    whole output (checked after the handle is released, for memory)."""
+    import torch
+    import paper_1409_4618_amd as fem
+    tn, te = mg.kuhn_box_torch(384, torch.device("cuda:0"))
+    V, T, E, F = mg.kuhn_counts(384)
+    assert te.shape[0] == T == 339_738_624
+    say(f"[gpu] index limit: cube level 7 (Kuhn 384^3), T={T}")
+    mesh = fem.Mesh(tn, te)
+    assert (mesh.n_faces, mesh.n_edges) == (680_361_984, 397_689_984) == (F, E)
+    N, nnz = mesh.pattern_info("ned")
+    assert N == E and nnz == E + 6 * F + 6 * T
+    structure = nedelec_structure(mesh, host=True)
+    torch.cuda.empty_cache()
+    K, M = fem.assemble(mesh, "ned", tn)
+    mesh.status()
+    del mesh, te
+    torch.cuda.empty_cache()
+    say("    whole-output identities")
+    check_identities(None, tn, K, M, structure=structure)
+
+
+def row_chunks(rowptr_h, chunk=1 << 27):
+    """Row ranges [r0, r1) of about ``chunk`` nonzeros each (at least one row)."""
+    n = rowptr_h.size - 1
+    out, r0 = [], 0
+    while r0 < n:
+        r1 = int(np.searchsorted(rowptr_h, rowptr_h[r0] + chunk, side="right")) - 1
+        r1 = min(max(r1, r0 + 1), n)
+        out.append((r0, r1))
+        r0 = r1
+    return out
+
+
+def transposed_positions(rowptr, colind, rows, cols):
+    """Position of (col, row) for each entry (row, col): the lower bound of row
+    among the sorted columns of row col, by bisection (elementwise torch ops)."""
+    import torch
+    nnz = colind.numel()
+    lo, hi = rowptr[cols], rowptr[cols + 1]
+    while True:
+        act = lo < hi
+        if not bool(act.any()):
+            return lo
+        mid = torch.where(act, (lo + hi) // 2, lo).clamp_(max=nnz - 1)
+        right = act & (colind[mid].long() < rows)
+        lo = torch.where(right, mid + 1, lo)
+        hi = torch.where(act & ~right, mid, hi)
+
+
+def nedelec_structure(mesh, host=False):
+    """Copies of the Nedelec pattern and of the edge list, (rowptr, colind,
+    edges2nodes), so the checks can run after the handle is released; with
+    ``host``, kept in host memory (moved there one array at a time)."""
     rowptr, colind = mesh.pattern("ned")
+    if host:
+        rowptr = rowptr.cpu()
+        colind = colind.cpu()
+    e2n = mesh.topology(("edges2nodes",))["edges2nodes"]
+    return rowptr, colind, e2n.cpu() if host else e2n
+
+
+def check_identities(mesh, tn, K, M, u=None, volume=1.0, structure=None):
+    """Bitwise symmetry, K G = 0 and the constant-field identity (b = 1, on a
+    domain of the given volume) on the whole output, in row chunks of about
+    2^27 nonzeros (elementwise torch ops: no library gemv). With ``u``, also
+    returns u^T K u, u^T M u and the sums of the magnitudes of their terms.
+    ``structure`` (from nedelec_structure) stands in for ``mesh``."""
+    import torch
+    dev = tn.device
+    rowptr, colind, e2n = structure if structure is not None else nedelec_structure(mesh)
+    rowptr, colind, e2n = rowptr.to(dev), colind.to(dev), e2n.to(dev).long()
     N = rowptr.numel() - 1
-    rows_t = torch.repeat_interleave(torch.arange(N, device=tn.device), torch.diff(rowptr))
-    ci = colind.long()
-    del colind
-    keys = rows_t * N + ci
-    pos = torch.searchsorted(keys, ci * N + rows_t)
-    assert torch.equal(keys[pos], ci * N + rows_t)
-    del keys
-    assert torch.equal(K[pos], K) and torch.equal(M[pos], M)
-    del pos
-    t = mesh.topology()
-    e2n = t["edges2nodes"].long()
-    del t
+    nnz = colind.numel()
+    rp_h = rowptr.cpu().numpy()
     rng = np.random.default_rng(5)
-    phi = torch.tensor(rng.normal(size=tn.shape[0]), device=tn.device)
-    v = phi[e2n[:, 0]] - phi[e2n[:, 1]]
-    y = torch.zeros(N, dtype=torch.float64, device=tn.device)
-    y.index_add_(0, rows_t, K * v[ci])
+    phi = torch.tensor(rng.normal(size=tn.shape[0]), device=dev)
+    v = phi[e2n[:, 0]] - phi[e2n[:, 1]]  # discrete gradient of phi
+    del phi
+    c = torch.tensor(rng.normal(size=tn.shape[1]), device=dev)
+    uc = ((tn[e2n[:, 0]] - tn[e2n[:, 1]]) * c).sum(dim=1)  # dofs of the constant field c
+    del e2n
+    y = torch.zeros(N, dtype=torch.float64, device=dev)
+    acc = torch.zeros(7, dtype=torch.float64, device=dev)
+    for r0, r1 in row_chunks(rp_h):
+        p0, p1 = int(rp_h[r0]), int(rp_h[r1])
+        rows = torch.repeat_interleave(torch.arange(r0, r1, device=dev), torch.diff(rowptr[r0:r1 + 1]))
+        ci = colind[p0:p1].long()
+        pos = transposed_positions(rowptr, colind, rows, ci)
+        assert bool((pos < nnz).all()) and torch.equal(colind[pos].long(), rows)
+        Kc, Mc = K[p0:p1], M[p0:p1]
+        assert torch.equal(K[pos], Kc) and torch.equal(M[pos], Mc)
+        del pos
+        y.index_add_(0, rows, Kc * v[ci])
+        w = uc[rows] * uc[ci]
+        terms = [(w * Mc).sum(), (w * Kc).sum(), (w * Kc).abs().sum()]
+        if u is not None:
+            w = u[rows] * u[ci]
+            terms += [(w * Kc).sum(), (w * Mc).sum(), (w * Kc).abs().sum(), (w * Mc).abs().sum()]
+        acc[:len(terms)] += torch.stack(terms)
+        del rows, ci, w
     rel = float(y.abs().max() / (K.abs().max() * v.abs().max()))
     say(f"    K G phi: max rel {rel:.2e}")
     assert rel <= 1e-12
-    del y, v, phi
-    c = torch.tensor(rng.normal(size=3), device=tn.device)
-    u = ((tn[e2n[:, 0]] - tn[e2n[:, 1]]) * c).sum(dim=1)
-    w = u[rows_t] * u[ci]
-    uMu = float((w * M).sum())
-    uKu = float((w * K).sum())
-    uKu_abs = float((w * K).abs().sum())
-    expect = float((c * c).sum())  # sum of the element volumes of the unit cube, b = 1
+    del y, v
+    uMu, uKu, uKu_abs = (float(x) for x in acc[:3])
+    expect = float((c * c).sum()) * volume  # |c|^2 times the sum of the element volumes, b = 1
     say(f"    constant field: uMu rel err {abs(uMu - expect) / expect:.2e}, |uKu|/sum|wK| {abs(uKu) / uKu_abs:.2e}")
     assert abs(uMu - expect) <= 1e-12 * expect
     assert abs(uKu) <= 1e-12 * uKu_abs
+    if u is not None:
+        return float(acc[3]), float(acc[4]), (float(acc[5]), float(acc[6]))
+    return None
 
 
 def strictly_increasing_rows(rows):

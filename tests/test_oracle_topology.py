@@ -58,6 +58,28 @@ def test_numbering_matches_brute_force(maker):
             assert topo.elems2faces.tolist() == el2f
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 8, 17])
+def test_l_shape_torch_layout_equals_numpy(m):
+    """The torch layout of the L-shape mesh (used for the large timing levels)
+    is the numpy one: same node coordinates, same element lists."""
+    import torch
+    nodes, elems = mg.l_shape(m)
+    tn, te = mg.l_shape_torch(m, "cpu")
+    assert te.dtype == torch.int32 and tn.dtype == torch.float64
+    assert np.array_equal(tn.numpy(), nodes) and np.array_equal(te.numpy(), elems)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_kuhn_box_torch_layout_equals_numpy(n):
+    """The torch layout of the Kuhn cube mesh (used for the large timing
+    levels) is the numpy one: same node coordinates, same element lists."""
+    import torch
+    nodes, elems = mg.kuhn_box(n)
+    tn, te = mg.kuhn_box_torch(n, "cpu")
+    assert te.dtype == torch.int32 and tn.dtype == torch.float64
+    assert np.array_equal(tn.numpy(), nodes) and np.array_equal(te.numpy(), elems)
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 9])
 def test_euler_and_kuhn_closed_forms(n):
     nodes, elems = mg.kuhn_box(n)
