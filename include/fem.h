@@ -328,10 +328,14 @@ fem_status fem_field_error(fem_mesh mesh, fem_kind kind, const double* nodes, co
  *          relative residual ||rhs - A' x|| / ||rhs|| of the returned x, formed
  *          at the end (it can stay above rtol by the rounding of A' x)
  * Deterministic: every dot product is summed in one fixed order. Allocates its
- * workspace (6 n_rows + 8229 doubles) for the call and synchronises `stream`.
+ * workspace (6 n_rows + 8229 doubles, and with B the nnz values ca A + cb B,
+ * formed once so that an iteration reads one value array) for the call and
+ * synchronises `stream`.
  * FEM_EINVAL for bad arguments or a non-positive diagonal entry; FEM_EHIP if
  * the iteration breaks down (p . A' p <= 0). Reaching max_iter is not an
- * error: check rel_resid.                                                   */
+ * error: check rel_resid. With the environment variable FEM_CG_LOG=N set, a
+ * line on stderr reports the iterations and the recursive relative residual
+ * at the first convergence test after every N iterations.                  */
 fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* colind,
                         const double* A, const double* B, double ca, double cb, const double* rhs,
                         double* x, double rtol, int64_t max_iter, void* stream, int64_t* iters,

@@ -59,6 +59,26 @@ def unit_square(nx: int, ny: Optional[int] = None, lx: float = 1.0, ly: float = 
     return nodes, elems
 
 
+def unit_square_torch(n: int, device):
+    """The mesh of ``unit_square(n)`` (n cells per side), laid out with torch on
+    ``device`` (the same node coordinates, from the same ``numpy.linspace``
+    values, and the same element lists): float64 nodes [V, 2] and int32 elems
+    [T, 3] tensors."""
+    import torch
+    xs = torch.tensor(np.linspace(0.0, 1.0, n + 1), dtype=torch.float64, device=device)
+    g = torch.arange(n + 1, device=device)
+    j, i = torch.meshgrid(g, g, indexing="ij")  # i fastest
+    nodes = torch.stack([xs[i.reshape(-1)], xs[j.reshape(-1)]], dim=1)
+    del i, j
+    c = torch.arange(n, device=device, dtype=torch.int32)
+    j, i = torch.meshgrid(c, c, indexing="ij")
+    v00 = (i + (n + 1) * j).reshape(-1)
+    del i, j
+    v11 = v00 + (n + 2)
+    elems = torch.stack([v00, v00 + 1, v11, v00, v11, v00 + (n + 1)], dim=1).reshape(-1, 3)
+    return nodes, elems
+
+
 def kuhn_box(nx: int, ny: Optional[int] = None, nz: Optional[int] = None,
              lx: float = 1.0, ly: float = 1.0, lz: float = 1.0):
     """Kuhn (6 tets per cube) mesh of a box: returns (nodes [V,3] f64, elems [T,4] i32)."""

@@ -11,6 +11,8 @@
 // a group are adjacent in the value and column arrays.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <utility>
 
 #include "fem_internal.h"
@@ -204,6 +206,15 @@ __device__ __forceinline__ double cg_row(const CgArgs& C, int64_t i, int j, cons
     return s;
 }
 
+// The system's values ca A + cb B, formed once per solve so that an iteration
+// reads one value array instead of two (grid-stride: nnz may exceed what one
+// work-item per entry can address).
+__global__ __launch_bounds__(CG_BLOCK) void k_cg_combine(const double* A, const double* B, double ca, double cb,
+                                                         int64_t nnz, double* AB) {
+    for (int64_t e = (int64_t)blockIdx.x * CG_BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * CG_BLOCK)
+        AB[e] = ca * A[e] + cb * B[e];
+}
+
 __global__ __launch_bounds__(CG_BLOCK) void k_cg_diag(const CgArgs C) {
     const int64_t i = (int64_t)blockIdx.x * CG_BLOCK + threadIdx.x;
     if (i >= C.n) return;
@@ -363,6 +374,21 @@ struct CgLaunch {
 
 }  // namespace fem
 
+namespace fem {
+
+// FEM_CG_LOG=N: one line on stderr at the first convergence test after every N
+// iterations (iterations done, recursive relative residual), so that a long
+// solve reports its progress; unset or not a positive number: silent.
+static int64_t cg_log_every() {
+    const char* s = std::getenv("FEM_CG_LOG");
+    if (!s) return 0;
+    char* end = nullptr;
+    const long long v = std::strtoll(s, &end, 10);
+    return (end != s && v > 0) ? (int64_t)v : 0;
+}
+
+}  // namespace fem
+
 extern "C" {
 
 fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* colind, const double* A,
@@ -383,6 +409,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     // the caller queues next.
     struct Res {
         char* ws = nullptr;
+        double* ab = nullptr;  // ca A + cb B when B is given
         hipStream_t s = nullptr;
         hipEvent_t ev = nullptr;
         hipGraph_t graph = nullptr;
@@ -394,6 +421,7 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
             if (ev) (void)hipEventDestroy(ev);
             if (s) (void)hipStreamDestroy(s);
             if (ws) (void)hipFree(ws);
+            if (ab) (void)hipFree(ab);
         }
     } R;
     FEM_HIP(hipMalloc(reinterpret_cast<void**>(&R.ws), bytes));
@@ -427,6 +455,16 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     FEM_HIP(hipMemcpyAsync(&nnz, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FEM_HIP(hipStreamSynchronize(s));
     C.nnz = nnz;
+    if (B) {
+        FEM_HIP(hipMalloc(reinterpret_cast<void**>(&R.ab), (size_t)std::max<int64_t>(nnz, 1) * sizeof(double)));
+        const unsigned gc = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8 * CG_GRID, (nnz + CG_BLOCK - 1) / CG_BLOCK));
+        hipLaunchKernelGGL(k_cg_combine, dim3(gc), dim3(CG_BLOCK), 0, s, A, B, ca, cb, nnz, R.ab);
+        FEM_HIP(hipGetLastError());
+        C.A = R.ab;
+        C.B = nullptr;
+        C.ca = 1.0;
+        C.cb = 0.0;
+    }
     CgLaunch L;
     L.C = C;
     L.G = nnz <= 8 * n ? 4 : nnz <= 16 * n ? 8 : 16;
@@ -447,6 +485,8 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
     int64_t it = 0;
     const double target = rtol * rtol * bb;
     bool converged = bb == 0.0 || rr <= target;
+    const int64_t log_every = cg_log_every();
+    int64_t next_log = log_every;
     while (!converged && it < max_iter) {
         const int64_t steps = std::min<int64_t>(CG_CHECK, max_iter - it);
         if (steps == CG_CHECK) {
@@ -477,6 +517,11 @@ fem_status fem_cg_solve(int64_t n_rows, const int64_t* rowptr, const int32_t* co
         if (flag & ERR_BOUNDS) return fail(FEM_ERANGE, "fem_cg_solve (checked build): a column index outside [0, n_rows)");
         if (flag & 2) return fail(FEM_EHIP, "fem_cg_solve: breakdown (p . A p <= 0: the matrix is not positive definite)");
         converged = rr <= target || !std::isfinite(rr);
+        if (log_every > 0 && it >= next_log) {
+            std::fprintf(stderr, "fem_cg_solve: %lld iterations, relative residual %.3e\n", (long long)it,
+                         std::sqrt(rr / bb));
+            next_log = (it / log_every + 1) * log_every;
+        }
     }
     // true residual of the result
     L.residual(true, p0);

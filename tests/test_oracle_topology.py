@@ -69,6 +69,17 @@ def test_l_shape_torch_layout_equals_numpy(m):
     assert np.array_equal(tn.numpy(), nodes) and np.array_equal(te.numpy(), elems)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16])
+def test_unit_square_torch_layout_equals_numpy(n):
+    """The torch layout of the unit-square mesh (used for the large eddy-current
+    meshes) is the numpy one: same node coordinates, same element lists."""
+    import torch
+    nodes, elems = mg.unit_square(n)
+    tn, te = mg.unit_square_torch(n, "cpu")
+    assert te.dtype == torch.int32 and tn.dtype == torch.float64
+    assert np.array_equal(tn.numpy(), nodes) and np.array_equal(te.numpy(), elems)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
 def test_kuhn_box_torch_layout_equals_numpy(n):
     """The torch layout of the Kuhn cube mesh (used for the large timing
