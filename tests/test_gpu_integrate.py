@@ -175,7 +175,7 @@ def test_field_error(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_cg_solve(dim):
+def test_cg_solve(dim, monkeypatch, capfd):
     import scipy.sparse.linalg as spla
     import torch
     import paper_1409_4618_amd as fem
@@ -202,6 +202,20 @@ def test_cg_solve(dim):
     say(f"    {iters} iterations, residual {res:.2e}, rel err vs direct {err:.2e}")
     assert res <= 1e-10 and err <= 1e-8
     assert torch.equal(x, x2) and iters == iters2
+    # the solve forms ca A + cb B once: the same as passing K + 2M formed here
+    # (2M is exact, so both round K + 2M once), bitwise
+    x3, iters3, _ = fem.cg_solve(rowptr, colind, K + 2.0 * M, trhs, rtol=1e-12)
+    assert torch.equal(x, x3) and iters == iters3
+    # FEM_CG_LOG=N: a progress line at the first convergence test after every
+    # N iterations, and the same result
+    capfd.readouterr()
+    monkeypatch.setenv("FEM_CG_LOG", "64")
+    x4, iters4, _ = fem.cg_solve(rowptr, colind, K, trhs, B=M, ca=1.0, cb=2.0, rtol=1e-12)
+    lines = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("fem_cg_solve:")]
+    its = [int(ln.split()[1]) for ln in lines]
+    assert torch.equal(x, x4) and iters4 == iters
+    assert len(its) == iters // 64 or len(its) == (iters - 1) // 64
+    assert all(b - a >= 64 for a, b in zip(its, its[1:])) and all(i % 16 == 0 for i in its)
 
 
 def _paper_errors():

@@ -25,6 +25,12 @@ def run_case(name, nodes, elems, kind, a=None, b=None):
     K, M = fem.assemble(mesh, kind, tn, ta, tb)
     rowptr, colind = mesh.pattern(kind)
     topo_g = {k: v.cpu().numpy() for k, v in mesh.topology().items()}
+    # a named subset is the same copy of those arrays; an unknown name is refused
+    sub = mesh.topology(("signs_e", "edges2nodes"))
+    assert list(sub) == ["signs_e", "edges2nodes"]
+    assert all(np.array_equal(v.cpu().numpy(), topo_g[k]) for k, v in sub.items())
+    with pytest.raises(ValueError):
+        mesh.topology(("faces2nodes",) if mesh.dim == 2 else ("edges",))
     K2, M2 = fem.assemble(mesh, kind, tn, ta, tb)
     mesh.status()
     out = dict(mesh=mesh, K=K.cpu().numpy(), M=M.cpu().numpy(), K2=K2.cpu().numpy(),
