@@ -292,7 +292,16 @@ struct FnArgs {
     int fn;
     int n_terms;
     int n_comp;
-    double p[FEM_POLY_MAX_TERMS * 5];  // polynomial terms: coefficient, component, exponents
+    // polynomial terms: coefficient, component and exponents, the integers
+    // stored as such so that a kernel reads and loops on them in scalar
+    // registers (they are the same for every lane); 32 bytes a term, one
+    // scalar load each
+    struct alignas(32) Term {
+        double coef;
+        int comp;
+        int expo[3];
+        int pad[2];
+    } term[FEM_POLY_MAX_TERMS];
 };
 fem_status gauss_legendre01(int m, QuadRule* q);
 // the handle's scratch for fixed-order element sums (2 ceil(T / 256) doubles)

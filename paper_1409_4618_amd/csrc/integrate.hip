@@ -99,7 +99,10 @@ fem_status make_fn_args(fem_function fn, int dim, const double* params, int n_pa
                         return fail(FEM_EINVAL, "polynomial: exponents must be integers 0..30");
                 }
                 if ((int)c + 1 > nc) nc = (int)c + 1;
-                for (int j = 0; j < w; ++j) F->p[t * w + j] = p[j];
+                F->term[t].coef = p[0];
+                F->term[t].comp = (int)c;
+                for (int d = 0; d < 3; ++d) F->term[t].expo[d] = d < dim ? (int)p[2 + d] : 0;
+                F->term[t].pad[0] = F->term[t].pad[1] = 0;
             }
             F->n_comp = nc;
             return FEM_OK;
@@ -127,7 +130,7 @@ fem_status make_fn_args(fem_function fn, int dim, const double* params, int n_pa
 
 // ---------------------------------------------------------------------------
 // squared L2 norm (Section 3.1): per element sum_q w_q |J| |f(F_K(xhat_q))|^2
-template <int DIM>
+template <int DIM, int FAM>
 __global__ __launch_bounds__(INT_BLOCK) void k_norm_L2(const int32_t* __restrict__ elems,
                                                         const double* __restrict__ nodes, int64_t T,
                                                         const QuadRule q, const FnArgs F,
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(INT_BLOCK) void k_norm_L2(const int32_t* __restrict
         for_points<DIM>(q, [&](const double* xh, double w) {
             double x[DIM], fv[3];
             phys_point<DIM>(g, xh, x);
-            eval_fn<DIM>(F, x, fv);
+            eval_fn<DIM, FAM>(F, x, fv);
             double s = 0.0;
             for (int c = 0; c < F.n_comp; ++c) s += fv[c] * fv[c];
             acc += w * s;
@@ -495,12 +498,21 @@ fem_status fem_norm_L2(fem_mesh m, const double* nodes, fem_function fn, const d
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     m->last_stream = s;
     const unsigned grid = int_grid(m->T);
-    if (m->dim == 2)
-        hipLaunchKernelGGL(k_norm_L2<2>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, m->T, q, F, per_elem,
+    // one kernel per dimension and function family (each holds only its
+    // family's evaluation, so the polynomial one keeps few registers)
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, m->T, q, F, per_elem,
                            m->int_partials, m->err_word);
-    else
-        hipLaunchKernelGGL(k_norm_L2<3>, dim3(grid), dim3(INT_BLOCK), 0, s, m->elems, nodes, m->T, q, F, per_elem,
-                           m->int_partials, m->err_word);
+    };
+    const int fam = fn_family(F.fn);
+    if (m->dim == 2) {
+        if (fam == FN_POLY) launch(k_norm_L2<2, FN_POLY>);
+        else if (fam == FN_BUBBLE) launch(k_norm_L2<2, FN_BUBBLE>);
+        else launch(k_norm_L2<2, FN_EDDY>);
+    } else {
+        if (fam == FN_POLY) launch(k_norm_L2<3, FN_POLY>);
+        else launch(k_norm_L2<3, FN_BUBBLE>);  // the eddy functions are two-dimensional
+    }
     FEM_HIP(hipGetLastError());
     return launch_sum_partials(m->int_partials, grid, total, s);
 }

@@ -85,20 +85,32 @@ __device__ __forceinline__ void bubble_eval(int fn, const double* x, double* out
     if (fn == FEM_FN_BUBBLE_F) out[0] = f;
 }
 
-// f at the physical point x (dim coordinates) into out[0 .. n_comp-1].
-template <int DIM>
+// Function families of the catalogue: a kernel compiled for one family holds
+// only that family's evaluation (and its registers); FN_ANY switches at run
+// time.
+enum { FN_ANY = 0, FN_POLY = 1, FN_EDDY = 2, FN_BUBBLE = 3 };
+inline int fn_family(int fn) {
+    return fn == FEM_FN_POLYNOMIAL ? FN_POLY : fn >= FEM_FN_BUBBLE_U ? FN_BUBBLE : FN_EDDY;
+}
+
+// f at the physical point x (dim coordinates) into out[0 .. n_comp-1]; FAM the
+// family of F.fn, or FN_ANY.
+template <int DIM, int FAM = FN_ANY>
 __device__ __forceinline__ void eval_fn(const FnArgs& F, const double* x, double* out) {
-    if (F.fn >= FEM_FN_BUBBLE_U) {
+    if (FAM == FN_BUBBLE || (FAM == FN_ANY && F.fn >= FEM_FN_BUBBLE_U)) {
         bubble_eval<DIM>(F.fn, x, out);
-    } else if (F.fn == FEM_FN_POLYNOMIAL) {
-        constexpr int W = 2 + DIM;
+    } else if (FAM == FN_POLY || (FAM == FN_ANY && F.fn == FEM_FN_POLYNOMIAL)) {
         for (int c = 0; c < F.n_comp; ++c) out[c] = 0.0;
         for (int t = 0; t < F.n_terms; ++t) {
-            const double* p = F.p + t * W;
-            double v = p[0];
+            const FnArgs::Term term = F.term[t];
+            double v = term.coef;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) v *= ipow(x[d], (int)p[2 + d]);
-            out[(int)p[1]] += v;
+            for (int d = 0; d < DIM; ++d) v *= ipow(x[d], term.expo[d]);
+            // the component by uniform branches, not a dynamic register index
+            const int c = term.comp;
+            if (c == 0) out[0] += v;
+            else if (DIM == 2 || c == 1) out[1] += v;
+            else out[2] += v;
         }
     } else {
         eddy_eval(F.fn, x[0], x[1], out);
