@@ -304,7 +304,8 @@ def small_mesh_latency(steps, warmup):
             "us_batch_kernel_graph": us_batch, "nnz": s["nnz"],
             "note": "us_graph: fem_assemble captured in a HIP graph (torch.cuda.CUDAGraph), one replay per "
                     "assembly; us_graph_x16_per_assembly: 16 assemblies captured in one graph; "
-                    "us_batch_kernel_graph: the one-mesh persistent batch kernel's graph"}
+                    "us_batch_kernel_graph: a one-mesh batch's graph (its default configuration: one grid launch "
+                    "for the mesh's element kind)"}
 
 
 def batched_rate(steps, warmup, ref_mtets, scale=1.0):

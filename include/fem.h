@@ -418,9 +418,10 @@ fem_status fem_status_query(fem_mesh mesh);
 void fem_mesh_destroy(fem_mesh mesh);
 
 /* ---------------------------------------------------------------------------
- * Batched assembly: many meshes of uneven sizes (mixed dims and kinds) in ONE
- * persistent kernel launch. Not in the paper (a launch-amortisation layer over
- * the same per-element computation).
+ * Batched assembly: many meshes of uneven sizes (mixed dims and kinds) in one
+ * launch (a persistent kernel over every kind), or with element-major tiles in
+ * one launch per element kind present (schedules 3-4 below). Not in the paper
+ * (a launch-amortisation layer over the same per-element computation).
  *   meshes  host array [n] of handles, each with fem_pattern(kinds[i]) built
  *   kinds   host array [n]
  * The batch borrows the meshes (they must outlive it).                     */
@@ -437,15 +438,21 @@ fem_status fem_batch_bind(fem_batch batch, const double* const* nodes,
 
 /* Autotuner: times every candidate (tiling with its workgroup size, schedule)
  * with the bound buffers on `stream`: element-major tiles of 256 and of 128
- * lanes, row tiles of 64/128/256 rows, each with the three schedules. Keeps
+ * lanes with schedules 0-4, row tiles of 64/128/256 rows with schedules 0-2. Keeps
  * the fastest, and records it in the JSON cache file
  * `cache_path` (NULL = no file). If the file already holds an entry for this
  * device and batch signature, that entry is used without timing. Synchronises. */
 fem_status fem_batch_tune(fem_batch batch, const char* cache_path, void* stream);
 
 /* Which configuration the batch uses (host outputs, may be NULL):
- * tiling, schedule (0 static, 1 dynamic queue, 2 LPT-sorted dynamic queue),
- * workgroup size, number of work items, persistent grid size. Tiling
+ * tiling, schedule, workgroup size, number of work items, grid size (the
+ * workgroups launched: the persistent grid, or with schedules 3-4 one per
+ * work item). Schedules: 0 static stride, 1 dynamic queue, 2 LPT-sorted
+ * dynamic queue (a persistent kernel over every kind); with element-major
+ * tiles also 3 and 4: the items grouped by element kind, one plain-grid
+ * launch per kind (one workgroup per item, the kind's own kernel and its
+ * occupancy), in mesh order (3) or by decreasing cost (4; the default when
+ * element-major tiles fit). Tiling
  * (`rows_per_tile`):
  *   0            element-major tiles, one element per lane, in workgroups of
  *                `threads` lanes (128 or 256: the elements per tile and the

@@ -697,8 +697,9 @@ class Batch:
         check(lib().fem_batch_tune(self._h, p, _stream_ptr()), "fem_batch_tune")
 
     def set_config(self, rows_per_tile: int, schedule: int, threads: int = 256):
-        """Tiling (0 = element-major, or 64/128/256 rows), schedule (0..2) and,
-        for element-major tiles, the workgroup size (128 or 256)."""
+        """Tiling (0 = element-major, or 64/128/256 rows), schedule (0..2; with
+        element-major tiles also 3..4, one launch per element kind) and, for
+        element-major tiles, the workgroup size (128 or 256)."""
         check(lib().fem_batch_set_config(self._h, rows_per_tile, schedule, threads), "fem_batch_set_config")
 
     def config(self):

@@ -313,6 +313,15 @@ struct fem_batch_s {
     bool ema_ok = false;    // every mesh has usable element-major tiles (256 lanes)
     int nt = 256;           // element-major tiles: workgroup size, 128 or 256
     int ema128 = -1;        // 128-lane tiles: -1 not built yet, 0 unusable, 1 usable
+    // element-major tiles, schedules 3-4: the work items grouped by element
+    // kind, one plain-grid launch per kind present (its own kernel and LDS
+    // size, one workgroup per item)
+    struct Seg {
+        int kc;
+        int64_t off, n;
+        int lds_bytes;
+    };
+    std::vector<Seg> segs;
     bool work_valid = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -360,6 +369,7 @@ static fem_status build_work(fem_batch B) {
     drop_graph(B);
     std::vector<int2> work;
     std::vector<double> cost;
+    std::vector<int> kcs;  // element kind of each item
     B->pmax = 0;
     B->lds_bytes = 0;
     for (size_t i = 0; i < B->meshes.size(); ++i) {
@@ -374,19 +384,34 @@ static fem_status build_work(fem_batch B) {
         else
             B->pmax = std::max(B->pmax, ds.pat.tile_pmax[rows_index(R)]);
         const double per_row = ds.pat.n_rows ? (double)ds.pat.nnz / (double)ds.pat.n_rows : 0.0;
+        const int kc = kind_code(m->dim, B->kinds[i]);
         for (int64_t t = 0; t < nt; ++t) {
             work.push_back(make_int2((int)i, (int)t));
             const int64_t rows = std::min<int64_t>(R, ds.pat.n_rows - t * R);
             cost.push_back(per_row * (double)rows * ds.nloc);
+            kcs.push_back(kc);
         }
     }
-    if (B->schedule == 2) {
+    // Schedules 3-4 (element-major tiles): grouped by kind (stable), one
+    // segment per kind. The decreasing-cost order of schedules 2 and 4 applies
+    // within a segment (or to the whole list).
+    const bool split = ema && B->schedule >= 3;
+    const bool by_cost = B->schedule == 2 || B->schedule == 4;
+    {
         std::vector<size_t> idx(work.size());
         for (size_t q = 0; q < idx.size(); ++q) idx[q] = q;
-        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            if (split && kcs[x] != kcs[y]) return kcs[x] < kcs[y];
+            return by_cost && cost[x] > cost[y];
+        });
         std::vector<int2> w2(work.size());
-        for (size_t q = 0; q < idx.size(); ++q) w2[q] = work[idx[q]];
+        std::vector<int> k2(work.size());
+        for (size_t q = 0; q < idx.size(); ++q) {
+            w2[q] = work[idx[q]];
+            k2[q] = kcs[idx[q]];
+        }
         work.swap(w2);
+        kcs.swap(k2);
     }
     B->n_work = (int64_t)work.size();
     if (B->n_work > B->work_cap) {
@@ -399,9 +424,24 @@ static fem_status build_work(fem_batch B) {
         FEM_HIP(hipMemcpy(B->work_dev, work.data(), B->n_work * sizeof(int2), hipMemcpyHostToDevice));
     // persistent grid: as many workgroups as can be resident
     int per_cu = 1;
+    B->segs.clear();
     if (ema) {
         if (B->lds_bytes > lds_limit_bytes())
             return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
+        if (split) {
+            for (int64_t q = 0; q < B->n_work;) {
+                int64_t q1 = q;
+                int lds = 0;
+                while (q1 < B->n_work && kcs[q1] == kcs[q]) {
+                    const int i = work[q1].x;
+                    const Pattern::Ema& E = dofset(B->meshes[i], B->kinds[i]).pat.ema[ema_index(B->nt)];
+                    lds = std::max(lds, ema_lds_bytes(kcs[q], E.R, E.pmax, E.max_slots));
+                    ++q1;
+                }
+                B->segs.push_back({kcs[q], q, q1 - q, lds});
+                q = q1;
+            }
+        }
         per_cu = batch_ema_blocks_per_cu(B->lds_bytes, B->nt);
     } else {
         const int bytes = B->pmax * 16;
@@ -410,6 +450,9 @@ static fem_status build_work(fem_batch B) {
         per_cu = batch_blocks_per_cu(B->R, bytes);
     }
     B->grid = (int)std::min<int64_t>((int64_t)cu_count() * per_cu, std::max<int64_t>(1, B->n_work));
+    if (split) {  // workgroups launched: one per item
+        B->grid = (int)std::min<int64_t>(B->n_work, 0x7FFFFFFF);
+    }
     // rebuild the device table with the tiling of this configuration
     for (size_t i = 0; i < B->host_table.size(); ++i) {
         MeshDev& md = B->host_table[i];
@@ -503,7 +546,7 @@ fem_status fem_batch_create(const fem_mesh* meshes, const fem_kind* kinds, int n
         return st;
     }
     B->R = B->ema_ok ? 0 : 128;
-    B->schedule = 1;
+    B->schedule = B->ema_ok ? 4 : 1;
     *out = B;
     return FEM_OK;
 }
@@ -527,8 +570,9 @@ fem_status fem_batch_bind(fem_batch B, const double* const* nodes, const double*
 
 fem_status fem_batch_set_config(fem_batch B, int R, int schedule, int threads) {
     if (!B) return fail(FEM_EINVAL, "fem_batch_set_config: batch is NULL");
-    if ((R != 0 && R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > 2)
-        return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 0/64/128/256, schedule 0..2");
+    if ((R != 0 && R != 64 && R != 128 && R != 256) || schedule < 0 || schedule > (R == 0 ? 4 : 2))
+        return fail(FEM_EINVAL, "fem_batch_set_config: rows_per_tile must be 0/64/128/256, schedule 0..4 for "
+                                "element-major tiles and 0..2 for row tiles");
     if (R == 0 ? (threads != 128 && threads != 256) : (threads != 0 && threads != 256))
         return fail(FEM_EINVAL, "fem_batch_set_config: threads must be 128 or 256 for element-major tiles, "
                                 "0 or 256 for row tiles");
@@ -556,8 +600,15 @@ fem_status fem_batch_assemble(fem_batch B, void* stream) {
     if (!B->work_valid)
         if (fem_status st = build_work(B)) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (B->R == 0 && !B->segs.empty()) {
+        for (const auto& g : B->segs)
+            if (fem_status st = launch_batch_ema(B->table_dev, B->work_dev + g.off, g.n, B->schedule, 0,
+                                                 g.lds_bytes, B->nt, g.kc, nullptr, s))
+                return st;
+        return FEM_OK;
+    }
     if (B->R == 0)
-        return launch_batch_ema(B->table_dev, B->work_dev, B->n_work, B->schedule, B->grid, B->lds_bytes, B->nt,
+        return launch_batch_ema(B->table_dev, B->work_dev, B->n_work, B->schedule, B->grid, B->lds_bytes, B->nt, -1,
                                 B->counters, s);
     return launch_batch(B->table_dev, B->work_dev, B->n_work, B->R, B->schedule, B->grid, B->pmax,
                         B->counters, s);
@@ -589,11 +640,12 @@ fem_status fem_batch_tune(fem_batch B, const char* cache_path, void* stream) {
     double best = 1e30;
     int bestR = B->ema_ok ? 0 : 128, bestS = 1, bestT = 256;
     // tilings: element-major tiles of 256 and of 128 lanes (the elements per
-    // tile and the wavefronts per workgroup), then row tiles of 64/128/256 rows
+    // tile and the wavefronts per workgroup; schedules 0-4), then row tiles of
+    // 64/128/256 rows (schedules 0-2)
     const int Rs[5] = {0, 0, 64, 128, 256};
     const int Ts[5] = {256, 128, 256, 256, 256};
     for (int ri = B->ema_ok ? 0 : 2; ri < 5; ++ri) {
-        for (int sched = 0; sched < 3; ++sched) {
+        for (int sched = 0; sched < (Rs[ri] == 0 ? 5 : 3); ++sched) {
             B->R = Rs[ri];
             B->nt = Ts[ri];
             B->schedule = sched;

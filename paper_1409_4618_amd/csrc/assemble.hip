@@ -832,18 +832,15 @@ fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s) {
     }
 }
 
-// Batched persistent kernel over element-major tiles: as k_batch, with the
+// Batched persistent kernels over element-major tiles: as k_batch, with the
 // work items (mesh, element-major tile) and the tile body of the forward path.
 // Each mesh keeps its own rows per tile and LDS layout; the dynamic LDS is the
-// largest over the meshes.
-template <int NT>
-// Five wavefronts per SIMD: the kernel holds every kind's tile body, and the
-// register count of the widest one (3D Nedelec) otherwise lands just above
-// the five-wavefront limit.
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_ema(const MeshDev* __restrict__ table,
-                                                  const int2* __restrict__ work, int64_t n_work,
-                                                  int schedule, unsigned* counters) {
-    extern __shared__ __align__(16) char smem_raw[];
+// largest over the meshes. The work loop: a static stride over the items, or
+// items taken from a device counter that resets itself when the last
+// workgroup leaves (no memset, so graph replays are valid).
+template <int NT, class Body>
+__device__ __forceinline__ void batch_work_loop(const int2* __restrict__ work, int64_t n_work, int schedule,
+                                                unsigned* counters, Body&& body) {
     __shared__ int64_t s_w;
     int64_t w = blockIdx.x;
     for (;;) {
@@ -854,14 +851,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_
             __syncthreads();
         }
         if (w >= n_work) break;
-        const int2 item = work[w];
-        const MeshDev md = table[item.x];
-        const int64_t tile = item.y;
-        switch (md.kind_code) {
-            case 0: tile_ema<0, NT>(md, tile, smem_raw); break;
-            case 1: tile_ema<1, NT>(md, tile, smem_raw); break;
-            default: tile_ema<2, NT>(md, tile, smem_raw); break;
-        }
+        body(work[w]);
         __syncthreads();
         if (schedule == 0) w += gridDim.x;
     }
@@ -874,6 +864,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_
     }
 }
 
+// Every kind in one kernel (a wave-uniform branch per tile). Five wavefronts
+// per SIMD: the kernel holds every kind's tile body, and the register count of
+// the widest one (3D Nedelec) otherwise lands just above the five-wavefront
+// limit.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_ema(const MeshDev* __restrict__ table,
+                                                  const int2* __restrict__ work, int64_t n_work,
+                                                  int schedule, unsigned* counters) {
+    extern __shared__ __align__(16) char smem_raw[];
+    batch_work_loop<NT>(work, n_work, schedule, counters, [&](int2 item) {
+        const MeshDev md = table[item.x];
+        switch (md.kind_code) {
+            case 0: tile_ema<0, NT>(md, item.y, smem_raw); break;
+            case 1: tile_ema<1, NT>(md, item.y, smem_raw); break;
+            default: tile_ema<2, NT>(md, item.y, smem_raw); break;
+        }
+    });
+}
+
 template <int NT>
 static fem_status launch_batch_ema_t(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
                                      int grid, int lds_bytes, unsigned* counters, hipStream_t s) {
@@ -884,14 +893,46 @@ static fem_status launch_batch_ema_t(const MeshDev* table, const int2* work, int
     return FEM_OK;
 }
 
+// The items of one element kind as a plain grid, one workgroup per item,
+// scheduled by the hardware dispatcher in item order: no work loop, so the
+// kernel holds one kind's tile body with the registers (and occupancy) of the
+// single-mesh kernel of that kind. One such launch per kind present.
+template <int KC, int NT>
+__global__ __launch_bounds__(NT) void k_batch_ema_grid(const MeshDev* __restrict__ table,
+                                                       const int2* __restrict__ work) {
+    extern __shared__ __align__(16) char smem_raw[];
+    const int2 item = work[blockIdx.x];
+    tile_ema<KC, NT>(table[item.x], item.y, smem_raw);
+}
+
+template <int KC, int NT>
+static fem_status launch_batch_ema_grid_t(const MeshDev* table, const int2* work, int64_t n_work, int lds_bytes,
+                                          hipStream_t s) {
+    FEM_HIP(set_lds(k_batch_ema_grid<KC, NT>, lds_bytes));
+    hipLaunchKernelGGL((k_batch_ema_grid<KC, NT>), dim3((unsigned)n_work), dim3(NT), lds_bytes, s, table, work);
+    FEM_HIP(hipGetLastError());
+    return FEM_OK;
+}
+
 fem_status launch_batch_ema(const MeshDev* table, const int2* work, int64_t n_work, int schedule,
-                            int grid, int lds_bytes, int nt, unsigned* counters, hipStream_t s) {
+                            int grid, int lds_bytes, int nt, int kc, unsigned* counters, hipStream_t s) {
     if (n_work == 0) return FEM_OK;
     if (lds_bytes > lds_limit_bytes())
         return fail(FEM_EOVERFLOW, "fem_batch: a tile needs more LDS than the device has");
-    if (nt == 128)
-        return launch_batch_ema_t<128>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
-    return launch_batch_ema_t<256>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
+    if (kc < 0) {
+        if (nt == 128)
+            return launch_batch_ema_t<128>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
+        return launch_batch_ema_t<256>(table, work, n_work, schedule, grid, lds_bytes, counters, s);
+    }
+    if (n_work >= (int64_t(1) << 31)) return fail(FEM_EOVERFLOW, "fem_batch: more than 2^31 - 1 tiles of one kind");
+    if (nt == 128) {
+        if (kc == 0) return launch_batch_ema_grid_t<0, 128>(table, work, n_work, lds_bytes, s);
+        if (kc == 1) return launch_batch_ema_grid_t<1, 128>(table, work, n_work, lds_bytes, s);
+        return launch_batch_ema_grid_t<2, 128>(table, work, n_work, lds_bytes, s);
+    }
+    if (kc == 0) return launch_batch_ema_grid_t<0, 256>(table, work, n_work, lds_bytes, s);
+    if (kc == 1) return launch_batch_ema_grid_t<1, 256>(table, work, n_work, lds_bytes, s);
+    return launch_batch_ema_grid_t<2, 256>(table, work, n_work, lds_bytes, s);
 }
 
 int batch_ema_blocks_per_cu(int lds_bytes, int nt) {

@@ -318,8 +318,11 @@ int default_rows_per_tile(int kind_code);
 fem_status launch_forward_ema(const MeshDev& md, int nt, hipStream_t s);
 // batched element-major tiles (workgroups of 256 lanes)
 // nt: workgroup size of the element-major tiles (128 or 256)
+// kc < 0: the persistent kernel over every kind (grid workgroups, schedule
+// 0..2); kc = 0..2: a plain grid over the items of that kind (one workgroup
+// per item)
 fem_status launch_batch_ema(const MeshDev* table_dev, const int2* work_dev, int64_t n_work,
-                            int schedule, int grid, int lds_bytes, int nt, unsigned* counters,
+                            int schedule, int grid, int lds_bytes, int nt, int kc, unsigned* counters,
                             hipStream_t s);
 int batch_ema_blocks_per_cu(int lds_bytes, int nt);
 

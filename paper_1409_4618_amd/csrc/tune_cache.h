@@ -4,9 +4,9 @@
 // One JSON object per line,
 //   {"device": "...", "signature": "...", "rows_per_tile": R, "schedule": S, "threads": N, "ms": t}
 // A lookup takes the last line whose device and signature match and whose
-// rows per tile (0, 64, 128, 256), schedule (0-2) and threads (128 or 256 for
-// element-major tiles, 256 for row tiles; 256 when the field is absent) are
-// valid; malformed, truncated or foreign lines are skipped. A store appends
+// rows per tile (0, 64, 128, 256), schedule (0-4 for element-major tiles,
+// 0-2 for row tiles) and threads (128 or 256 for element-major tiles, 256 for
+// row tiles; 256 when the field is absent) are valid; malformed, truncated or foreign lines are skipped. A store appends
 // one line.
 #pragma once
 
@@ -57,7 +57,7 @@ inline bool cache_lookup(const char* path, const std::string& dev, const std::st
         if (line.find("\"threads\": ") != std::string::npos && !cache_field(line, "\"threads\": ", &nt))
             continue;
         const bool nt_ok = r == 0 ? (nt == 128 || nt == 256) : nt == 256;
-        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= 2 && nt_ok) {
+        if ((r == 0 || r == 64 || r == 128 || r == 256) && sc >= 0 && sc <= (r == 0 ? 4 : 2) && nt_ok) {
             *R = r;
             *sched = sc;
             *threads = nt;

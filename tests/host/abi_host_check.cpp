@@ -48,6 +48,10 @@ static void check_cache(const std::string& dir) {
     junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 64, \"schedule\": 1, \"threads\": 128}\n";
     junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 0, \"schedule\": 0, \"threads\": 512}\n";
     junk += "{\"device\": \"dev\", \"signature\": \"sig3\", \"rows_per_tile\": 0, \"schedule\": 0, \"threads\": }\n";
+    // per-kind launches (schedules 3-4) are valid with element-major tiles only
+    junk += "{\"device\": \"dev\", \"signature\": \"sig4\", \"rows_per_tile\": 0, \"schedule\": 4, \"threads\": 256}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig4\", \"rows_per_tile\": 64, \"schedule\": 3, \"threads\": 256}\n";
+    junk += "{\"device\": \"dev\", \"signature\": \"sig4\", \"rows_per_tile\": 0, \"schedule\": 5, \"threads\": 256}\n";
     junk += std::string(200000, 'z') + "\n";                  // a long line
     junk += std::string("\0\x01\xff", 3) + "\n";              // binary bytes
     junk += "{\"device\": \"dev\", \"signature\": \"sig\", \"rows_per_tile\": 0, \"schedule\": 2, \"ms\": 0.5}";  // no newline
@@ -56,6 +60,7 @@ static void check_cache(const std::string& dir) {
     CHECK(R == 0 && S == 2 && N == 256);  // the last valid matching line wins; no threads field: 256
     CHECK(fem::cache_lookup(p.c_str(), "dev", "sig2", &R, &S, &N) && R == 256 && S == 2);
     CHECK(fem::cache_lookup(p.c_str(), "dev", "sig3", &R, &S, &N) && R == 0 && S == 1 && N == 128);
+    CHECK(fem::cache_lookup(p.c_str(), "dev", "sig4", &R, &S, &N) && R == 0 && S == 4 && N == 256);
     CHECK(!fem::cache_lookup(p.c_str(), "dev", "nosuch", &R, &S, &N));
     // store, then read back
     const std::string q = dir + "/store.jsonl";

@@ -1,6 +1,8 @@
-"""Batched persistent launch: bitwise equal to single-mesh launches for every
-tile size and schedule, HIP-graph replays equal to direct launches, and the
-autotuner's choice recorded in / read back from its cache file."""
+"""Batched launch: bitwise equal to single-mesh launches for every tile size
+and schedule (the persistent kernel over every kind with schedules 0-2, one
+launch per element kind with schedules 3-4), HIP-graph replays equal to
+direct launches, and the autotuner's choice recorded in / read back from its
+cache file."""
 import json
 import os
 
@@ -48,7 +50,7 @@ def test_single_meshes_match_oracle(batch_setup):
 
 
 @pytest.mark.parametrize("rows,threads", [(0, 256), (0, 128), (64, 256), (128, 256), (256, 256)])
-@pytest.mark.parametrize("schedule", [0, 1, 2])
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3, 4])
 def test_batch_equals_single_launches(batch_setup, rows, threads, schedule):
     import torch
     import paper_1409_4618_amd as fem
@@ -59,6 +61,11 @@ def test_batch_equals_single_launches(batch_setup, rows, threads, schedule):
         K.fill_(float("nan"))
         M.fill_(float("nan"))
     B.bind(nodes, a, b, Ks, Ms)
+    if rows != 0 and schedule > 2:
+        # the per-kind launches exist for element-major tiles only
+        with pytest.raises(fem.FemError):
+            B.set_config(rows, schedule, threads)
+        return
     B.set_config(rows, schedule, threads)
     B.assemble()
     B.assemble()  # the device work counter resets itself between launches
@@ -76,15 +83,15 @@ def test_batch_equals_single_launches(batch_setup, rows, threads, schedule):
         assert B.config()["rows_per_tile"] == 64
 
 
-@pytest.mark.parametrize("rows,threads", [(0, 256), (0, 128), (128, 256)])
-def test_graph_replay_equals_direct(batch_setup, rows, threads):
+@pytest.mark.parametrize("rows,threads,schedule", [(0, 256, 1), (0, 256, 4), (0, 128, 3), (128, 256, 1)])
+def test_graph_replay_equals_direct(batch_setup, rows, threads, schedule):
     import torch
     import paper_1409_4618_amd as fem
     probs, meshes, kinds, nodes, a, b, Ks, Ms, refs = batch_setup
-    say(f"[gpu] batch graph replays, rows={rows} threads={threads}")
+    say(f"[gpu] batch graph replays, rows={rows} threads={threads} schedule={schedule}")
     B = fem.Batch(meshes, kinds)
     B.bind(nodes, a, b, Ks, Ms)
-    B.set_config(rows, 1, threads)
+    B.set_config(rows, schedule, threads)
     for rep in range(3):
         for K, M in zip(Ks, Ms):
             K.zero_()
