@@ -6,7 +6,8 @@ library the process loaded and saves every result to ``out_dir/results.npz``;
 
 Covered: topology and patterns; the forward (element-major tiles, and the row
 kernels when FEM_FWD_PATH=rows) for 2D and 3D, both kinds, relabelled meshes;
-the batch (element-major tiles of 256 and 128 lanes, row tiles); the adjoint
+the batch (element-major tiles of 256 and 128 lanes, row tiles, the per-kind
+launches); the adjoint
 (separate and shared weights, the quadratic form, vertex derivatives) and the
 quadratic-form value; integration, load vector, H(curl) error and CG of the
 eddy example; the P1 system, its boundary elimination and error; the
@@ -92,17 +93,17 @@ def run(out_dir):
     Ms = [torch.empty_like(K) for K in Ks]
     B = fem.Batch(ms, kinds)
     B.bind(nodes, aa, bb, Ks, Ms)
-    for rows, threads in ((0, 256), (0, 128), (64, 256), (256, 256)):
+    for rows, threads, sched in ((0, 256, 1), (0, 128, 1), (64, 256, 1), (256, 256, 1), (0, 256, 4)):
         for K in Ks + Ms:
             K.fill_(float("nan"))
-        B.set_config(rows, 1, threads)
+        B.set_config(rows, sched, threads)
         B.assemble()
         torch.cuda.synchronize()
         for m in ms:
             m.status()
         for i, (K, M) in enumerate(zip(Ks, Ms)):
-            keep(f"batch{rows}_{threads}_{i}_K", K)
-            keep(f"batch{rows}_{threads}_{i}_M", M)
+            keep(f"batch{rows}_{threads}_{sched}_{i}_K", K)
+            keep(f"batch{rows}_{threads}_{sched}_{i}_M", M)
 
     # Section 3.1 / 4.2: integration, load, error and CG on the eddy example
     from paper_1409_4618_amd.eddy import eddy_current
