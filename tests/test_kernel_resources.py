@@ -6,7 +6,10 @@ Occupancy is what hides the gather latency of these memory-bound kernels, so
 the budgets are part of the design: a VGPR count above a wavefront boundary
 costs a wavefront per SIMD (gfx950: 512 VGPRs per lane per SIMD, allocated in
 blocks of 8), and a spill (private segment) adds memory traffic. The batched
-kernel holds every kind's tile body and sits exactly at its boundary.
+kernel over every kind holds every kind's tile body and sits exactly at its
+boundary; the batch's per-kind grid kernels take their kind's registers (the
+3D Nedelec one a few more than the single-mesh kernel: the mesh descriptor
+comes from the table).
 """
 import glob
 import os
@@ -26,6 +29,9 @@ BUDGETS = [
     ("k_forward_emaILi1ELi256", 8),   # 3D Raviart-Thomas forward
     ("k_forward_emaILi0ELi256", 8),   # 2D forward
     ("k_batch_emaILi256", 5),         # batched forward, all kinds
+    ("k_batch_ema_gridILi2ELi256", 5),  # batched forward, one launch per kind: 3D Nedelec
+    ("k_batch_ema_gridILi1ELi256", 8),  # 3D Raviart-Thomas
+    ("k_batch_ema_gridILi0ELi256", 8),  # 2D
     ("k_backwardILi2ELi2", 4),        # 3D Nedelec adjoint, quadratic form
     ("k_backwardILi2ELi1", 3),        # 3D Nedelec adjoint, materialised weights
 ]
